@@ -1,0 +1,185 @@
+/*
+ * mgwr.h -- C ABI of the MI355X (gfx950) multigrid waveform relaxation
+ * (MGWR) solver for the time-fractional heat equation
+ *     D_t^alpha u - Laplace(u) = f  on (0, L)^dims x (0, T],
+ *     u = 0 on the boundary, u(., 0) = g,
+ * discretised with the L1 scheme in time and central differences in space
+ * (Gaspar & Rodrigo, arXiv:1608.05400, Section 2 and Section 6), and solved
+ * by Algorithm 1 (Section 3): red-black waveform relaxation that solves one
+ * lower-triangular Toeplitz system along all M time levels per spatial point,
+ * coarsening in space only, full weighting and linear/bilinear interpolation.
+ *
+ * Array conventions (every array argument is a DEVICE pointer, FP64,
+ * contiguous, owned by the caller; the library never keeps a pointer after
+ * the call returns):
+ *   dims = 1: f, u, r are [M][N]; element (m, n-1) is the value at node
+ *             x_n = n h (n = 1..N, h = L/(N+1)) and time t_{m+1} = (m+1) T/M;
+ *             g (the initial condition, "u0") is [N].
+ *   dims = 2: f, u, r are [M][N][N]; element (m, l-1, n-1) is the value at
+ *             (x_n, y_l, t_{m+1}), x fastest; g is [N][N].
+ *   t_0 is not stored: it is given by g.  g == NULL means g = 0.
+ *
+ * Work is issued on the handle's stream (mgwr_set_stream; default: the null
+ * stream) and is stream-ordered with the caller's work on that stream.
+ * mgwr_solve synchronises the stream before it returns (it reads residual
+ * norms); the other calls are asynchronous unless stated.
+ *
+ * Return codes: MGWR_OK (0) on success; a positive code is a completed call
+ * with a warning (u holds the last iterate); a negative code is an error, in
+ * which case nothing was written to the output arrays unless stated and
+ * mgwr_last_error() describes it.  A handle is not thread-safe; distinct
+ * handles are independent.
+ */
+#ifndef MGWR_H
+#define MGWR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgwr_ctx *mgwr_t;
+typedef struct mgwr_batch_ctx *mgwr_batch_t;
+
+enum mgwr_status {
+    MGWR_OK = 0,
+    MGWR_NOT_CONVERGED = 1, /* maxit cycles done before the tolerance was met          */
+    MGWR_STAGNATED = 2,     /* residual stopped decreasing above the tolerance         */
+    MGWR_EINVAL = -1,       /* invalid argument (sizes, alpha, T, dims, NULL pointers)  */
+    MGWR_ENOMEM = -2,       /* device allocation failed                                 */
+    MGWR_EDEVICE = -3,      /* HIP runtime error                                        */
+    MGWR_ENONFINITE = -4,   /* NaN or Inf in the residual (input or divergence)         */
+    MGWR_EDIVERGED = -5     /* residual grew beyond 1e6 times its initial value         */
+};
+
+/* Arithmetic of the V-cycle. */
+enum mgwr_precision {
+    MGWR_FP64 = 0,          /* Algorithm 1 applied to u in FP64 ("plain")                 */
+    MGWR_MIXED_FP32 = 1,    /* refinement: FP64 residual, V-cycle on the error in FP32    */
+    MGWR_MIXED_BF16X3 = 2,  /* refinement: FP64 residual, V-cycle on the error in FP32
+                               storage with Toeplitz products as three BF16 MFMA passes
+                               (hi*hi + hi*lo + lo*hi) accumulated in FP32               */
+    MGWR_FP64_REFINED = 3   /* refinement with an FP64 V-cycle on the error            */
+};
+
+enum mgwr_norm { MGWR_NORM_MAX = 0, MGWR_NORM_L2 = 1 };
+
+/* Smoother line solve (Section 5.2): both solve (T_M + sigma I) x = b along
+ * every time line of one colour exactly (up to rounding). */
+enum mgwr_smoother {
+    MGWR_SMOOTH_INVERSE = 0, /* one causal Toeplitz product with the precomputed first
+                                column of (T_M + sigma I)^{-1}                        */
+    MGWR_SMOOTH_DC = 1       /* divide-and-conquer blocked forward substitution: base
+                                blocks by the inverse of the leading block, history
+                                updates by full Toeplitz-block products            */
+};
+
+typedef struct {
+    int nu1, nu2;       /* pre-/post-smoothing steps of Algorithm 1 (default 1, 1)          */
+    int gamma;          /* coarse cycles per level: 1 = V, 2 = W (default 1)                 */
+    int maxit;          /* maximum cycles in mgwr_solve (default 100)                        */
+    int norm;           /* enum mgwr_norm (default MGWR_NORM_MAX)                            */
+    int warm_start;     /* mgwr_solve: 1 = u already holds the initial iterate (default 0:
+                           u^0 = g at every time level, Section 3)                         */
+    int precision;      /* enum mgwr_precision (default MGWR_FP64)                           */
+    int first_colour;   /* colour relaxed first: 0 = even n (2D: n + l even), as ordered in
+                           the text of Section 3; 1 = odd n first (default 0)              */
+    int smoother;       /* enum mgwr_smoother (default MGWR_SMOOTH_INVERSE)                  */
+    int dc_block;       /* base block of MGWR_SMOOTH_DC, a power of two >= 64 (0 = auto)      */
+    double L;           /* domain length (default 1)                                         */
+    double stall;       /* mgwr_solve stops with MGWR_STAGNATED when a cycle reduces the
+                           residual by less than this factor (default 0.5; 0 disables)      */
+} mgwr_options;
+
+typedef struct {
+    int iters;          /* cycles done                                                        */
+    int status;         /* the return code of mgwr_solve                                      */
+    double r0;          /* norm of the initial residual                                       */
+    double rk;          /* norm of the final residual                                         */
+    double relres;      /* rk / r0                                                            */
+    double mean_factor; /* (rk / r0)^(1/iters)  (Section 7, mean convergence factor)          */
+    double hist[128];   /* residual norms after 0..min(iters,127) cycles                      */
+} mgwr_info;
+
+/* Fill *o with the defaults listed above.  Host only; never fails. */
+int mgwr_default_options(mgwr_options *o);
+
+/* L1 weights of the time discretisation (Section 2, L1 scheme; Section 5,
+ * first column of T_M): *c = tau^-alpha / Gamma(2 - alpha) and
+ * r[i-1] = c (d_i - d_{i-1}), i = 1..M, d_k = k^(1-alpha) - (k-1)^(1-alpha),
+ * d_0 = 0, d_1 = 1.  Host only (no device use).  r: host array of M doubles.
+ * Returns MGWR_EINVAL on bad sizes or alpha outside (0, 1]. */
+int mgwr_l1_weights(int M, double alpha, double T, double *c, double *r);
+
+/* Create a solver for N interior points per dimension (N = 2^k - 1, k >= 1,
+ * so that coarsening reaches one point, Section 1 and Section 3), M >= 1 time
+ * steps, order 0 < alpha <= 1, final time T > 0, dims in {1, 2}.  Computes
+ * the L1 weights and, for every level, the first column of the inverse of
+ * T_M + sigma_l I (Section 5.2), and allocates the device hierarchy on the
+ * current HIP device.  opts may be NULL (defaults).  Synchronous. */
+int mgwr_create(int N, int M, double alpha, double T, int dims, mgwr_t *out);
+int mgwr_create_ex(int N, int M, double alpha, double T, int dims, const mgwr_options *opts,
+                   mgwr_t *out);
+int mgwr_destroy(mgwr_t h);
+
+/* Change options (allocates the buffers the new precision needs). */
+int mgwr_set_options(mgwr_t h, const mgwr_options *opts);
+int mgwr_get_options(mgwr_t h, mgwr_options *opts);
+
+/* hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
+int mgwr_set_stream(mgwr_t h, void *hip_stream);
+
+/* `sweeps` red-black waveform-relaxation steps (Section 3, eq. red-black;
+ * Section 6, eq. red-black_2d) on the finest level, in place on u, in FP64:
+ * for each colour in turn, every point p of that colour gets the solution x
+ * of (T_M + sigma I) x = f_p + c d g_p + (sum of neighbours of p)/h^2. */
+int mgwr_smooth(mgwr_t h, const double *f, const double *g, double *u, int sweeps);
+
+/* Residual r = f + c d_m g - T_M u - A_h u of the discrete problem (Section 2,
+ * eq. discrete_model_IVP_1; Section 6), in FP64.  If norms != NULL (host,
+ * 2 doubles) it receives {max |r|, ||r||_2} and the call synchronises. */
+int mgwr_residual(mgwr_t h, const double *f, const double *g, const double *u, double *r,
+                  double *norms);
+
+/* One cycle of Algorithm 1 (V or W per options.gamma) on u in place, FP64. */
+int mgwr_vcycle(mgwr_t h, const double *f, const double *g, double *u);
+
+/* Iterate until ||r_k|| <= tol ||r_0|| (norm per options; Section 7 uses a
+ * reduction by 1e-10), maxit, or stagnation.  u receives the last iterate.
+ * info may be NULL.  Synchronises the stream. */
+int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol,
+               mgwr_info *info);
+
+/* C = X B, B and C device [M][ldb]/[M][ldc] FP64 with P columns, where X is
+ * the lower-triangular Toeplitz matrix T_M (which = -1) or the inverse of
+ * T_M + sigma_l I on level `which` >= 0 (0 = coarsest), applied in the
+ * arithmetic `precision` (enum mgwr_precision; FP64_REFINED is FP64).
+ * Exposes the Toeplitz product kernels for testing. */
+int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int ldb, int P,
+                        double *C, int ldc);
+
+/* Host copy of the first column (M doubles) of T_M (which = -1) or of the
+ * inverse of T_M + sigma_l I on level `which`. */
+int mgwr_get_column(mgwr_t h, int which, double *out);
+
+/* Number of levels (finest = levels - 1). */
+int mgwr_levels(mgwr_t h);
+
+/* ---- batches of independent 1D or 2D problems (uneven N, M, alpha) ----
+ * count problems; N[i], M[i], alpha[i], T[i] as for mgwr_create; all share
+ * dims and opts.  f, g, u are host arrays of count device pointers (g may
+ * be NULL or contain NULLs).  infos: host array of count mgwr_info (may be
+ * NULL).  Returns the worst status over the problems. */
+int mgwr_batch_create(int count, const int *N, const int *M, const double *alpha,
+                      const double *T, int dims, const mgwr_options *opts, mgwr_batch_t *out);
+int mgwr_batch_solve(mgwr_batch_t b, const double *const *f, const double *const *g,
+                     double *const *u, double tol, mgwr_info *infos);
+int mgwr_batch_set_stream(mgwr_batch_t b, void *hip_stream);
+int mgwr_batch_destroy(mgwr_batch_t b);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *mgwr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGWR_H */

@@ -1,0 +1,310 @@
+"""ctypes binding of ``libmgwr.so`` (declared in ``include/mgwr.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Arrays are torch tensors on the GPU (float64, contiguous); torch provides the
+device memory and the stream (``torch.cuda.current_stream()``).  There is no
+CPU fallback: if the library cannot be loaded, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgwr.so")
+
+MGWR_OK, MGWR_NOT_CONVERGED, MGWR_STAGNATED = 0, 1, 2
+MGWR_EINVAL, MGWR_ENOMEM, MGWR_EDEVICE, MGWR_ENONFINITE, MGWR_EDIVERGED = -1, -2, -3, -4, -5
+FP64, MIXED_FP32, MIXED_BF16X3, FP64_REFINED = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3, "fp64r": FP64_REFINED}
+NORM_MAX, NORM_L2 = 0, 1
+STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "stagnated", -1: "einval", -2: "enomem",
+                -3: "edevice", -4: "enonfinite", -5: "ediverged"}
+
+EXPORTED = [
+    "mgwr_default_options", "mgwr_l1_weights", "mgwr_create", "mgwr_create_ex", "mgwr_destroy",
+    "mgwr_set_options", "mgwr_get_options", "mgwr_set_stream", "mgwr_smooth", "mgwr_residual",
+    "mgwr_vcycle", "mgwr_solve", "mgwr_toeplitz_apply", "mgwr_get_column", "mgwr_levels",
+    "mgwr_batch_create", "mgwr_batch_solve", "mgwr_batch_set_stream", "mgwr_batch_destroy",
+    "mgwr_last_error",
+]
+
+
+class MgwrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("gamma", ctypes.c_int),
+                ("maxit", ctypes.c_int), ("norm", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("precision", ctypes.c_int), ("first_colour", ctypes.c_int),
+                ("smoother", ctypes.c_int), ("dc_block", ctypes.c_int),
+                ("L", ctypes.c_double), ("stall", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("r0", ctypes.c_double),
+                ("rk", ctypes.c_double), ("relres", ctypes.c_double),
+                ("mean_factor", ctypes.c_double), ("hist", ctypes.c_double * 128)]
+
+    def as_dict(self):
+        n = min(self.iters, 127) + 1
+        return {"iters": self.iters, "status": STATUS_NAMES.get(self.status, self.status),
+                "r0": self.r0, "rk": self.rk, "relres": self.relres,
+                "mean_factor": self.mean_factor, "hist": list(self.hist[:n])}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; build it first only if no build exists."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        from . import build as _build
+        _build.build()
+    lib = ctypes.CDLL(path)
+    P, I, D, VP = ctypes.POINTER, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    h = ctypes.c_void_p
+    lib.mgwr_default_options.argtypes = [P(Options)]
+    lib.mgwr_l1_weights.argtypes = [I, D, D, P(D), P(D)]
+    lib.mgwr_create.argtypes = [I, I, D, D, I, P(h)]
+    lib.mgwr_create_ex.argtypes = [I, I, D, D, I, P(Options), P(h)]
+    lib.mgwr_destroy.argtypes = [h]
+    lib.mgwr_set_options.argtypes = [h, P(Options)]
+    lib.mgwr_get_options.argtypes = [h, P(Options)]
+    lib.mgwr_set_stream.argtypes = [h, VP]
+    lib.mgwr_smooth.argtypes = [h, VP, VP, VP, I]
+    lib.mgwr_residual.argtypes = [h, VP, VP, VP, VP, P(D)]
+    lib.mgwr_vcycle.argtypes = [h, VP, VP, VP]
+    lib.mgwr_solve.argtypes = [h, VP, VP, VP, D, P(Info)]
+    lib.mgwr_toeplitz_apply.argtypes = [h, I, I, VP, I, I, VP, I]
+    lib.mgwr_get_column.argtypes = [h, I, P(D)]
+    lib.mgwr_levels.argtypes = [h]
+    lib.mgwr_batch_create.argtypes = [I, P(I), P(I), P(D), P(D), I, P(Options), P(h)]
+    lib.mgwr_batch_solve.argtypes = [h, P(VP), P(VP), P(VP), D, P(Info)]
+    lib.mgwr_batch_set_stream.argtypes = [h, VP]
+    lib.mgwr_batch_destroy.argtypes = [h]
+    lib.mgwr_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().mgwr_last_error().decode()
+
+
+def _check(rc, allow_positive=True):
+    if rc < 0 or (rc > 0 and not allow_positive):
+        raise MgwrError(rc, last_error())
+    return rc
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().mgwr_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if k == "norm" and isinstance(v, str):
+            v = {"max": NORM_MAX, "l2": NORM_L2}[v]
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def l1_weights(M: int, alpha: float, T: float = 1.0):
+    """Host-side L1 weights (c, r[0..M-1]) computed by the library."""
+    import numpy as np
+    r = np.zeros(M)
+    c = ctypes.c_double()
+    _check(load().mgwr_l1_weights(M, alpha, T, ctypes.byref(c),
+                                  r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), False)
+    return c.value, r
+
+
+def _ptr(t, name, shape=None, allow_none=False):
+    import torch
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Solver:
+    """Handle of one problem: N interior points per dimension (2^k - 1), M time
+    steps, fractional order alpha, final time T, dims in {1, 2}."""
+
+    def __init__(self, N: int, M: int, alpha: float, T: float = 1.0, dims: int = 1, **opts):
+        self.N, self.M, self.alpha, self.T, self.dims = N, M, alpha, T, dims
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        o = default_options(**opts)
+        _check(self._lib.mgwr_create_ex(N, M, alpha, T, dims, ctypes.byref(o), ctypes.byref(self._h)),
+               False)
+
+    @property
+    def grid_shape(self):
+        return (self.M, self.N) if self.dims == 1 else (self.M, self.N, self.N)
+
+    @property
+    def ic_shape(self):
+        return self.grid_shape[1:]
+
+    def close(self):
+        if self._h:
+            self._lib.mgwr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def options(self) -> Options:
+        o = Options()
+        _check(self._lib.mgwr_get_options(self._h, ctypes.byref(o)))
+        return o
+
+    def set_options(self, **kw):
+        o = self.options()
+        for k, v in kw.items():
+            if k == "precision" and isinstance(v, str):
+                v = PRECISIONS[v]
+            if k == "norm" and isinstance(v, str):
+                v = {"max": NORM_MAX, "l2": NORM_L2}[v]
+            setattr(o, k, v)
+        _check(self._lib.mgwr_set_options(self._h, ctypes.byref(o)), False)
+
+    def levels(self) -> int:
+        return _check(self._lib.mgwr_levels(self._h))
+
+    def _bind_stream(self):
+        _check(self._lib.mgwr_set_stream(self._h, _stream()))
+
+    def smooth(self, f, u, g=None, sweeps=1):
+        self._bind_stream()
+        _check(self._lib.mgwr_smooth(self._h, _ptr(f, "f", self.grid_shape),
+                                     _ptr(g, "g", self.ic_shape, True),
+                                     _ptr(u, "u", self.grid_shape), sweeps), False)
+        return u
+
+    def residual(self, f, u, g=None, r=None, norms=False):
+        import torch
+        if r is None:
+            r = torch.empty_like(u)
+        self._bind_stream()
+        nrm = (ctypes.c_double * 2)()
+        _check(self._lib.mgwr_residual(self._h, _ptr(f, "f", self.grid_shape),
+                                       _ptr(g, "g", self.ic_shape, True),
+                                       _ptr(u, "u", self.grid_shape), _ptr(r, "r", self.grid_shape),
+                                       nrm if norms else None), False)
+        return (r, (nrm[0], nrm[1])) if norms else r
+
+    def vcycle(self, f, u, g=None):
+        self._bind_stream()
+        _check(self._lib.mgwr_vcycle(self._h, _ptr(f, "f", self.grid_shape),
+                                     _ptr(g, "g", self.ic_shape, True),
+                                     _ptr(u, "u", self.grid_shape)), False)
+        return u
+
+    def solve(self, f, u, g=None, tol=1e-10, raise_on_error=True):
+        self._bind_stream()
+        info = Info()
+        rc = self._lib.mgwr_solve(self._h, _ptr(f, "f", self.grid_shape),
+                                  _ptr(g, "g", self.ic_shape, True), _ptr(u, "u", self.grid_shape),
+                                  tol, ctypes.byref(info))
+        if rc < 0 and raise_on_error:
+            raise MgwrError(rc, last_error())
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
+
+    def toeplitz_apply(self, B, which=-1, precision=FP64, C=None):
+        import torch
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        if B.dim() != 2 or B.shape[0] != self.M:
+            raise ValueError("B must be [M, P]")
+        if C is None:
+            C = torch.empty_like(B)
+        self._bind_stream()
+        P = B.shape[1]
+        _check(self._lib.mgwr_toeplitz_apply(self._h, which, precision, _ptr(B, "B"), P, P,
+                                             _ptr(C, "C"), P), False)
+        return C
+
+    def column(self, which=-1):
+        import numpy as np
+        out = np.zeros(self.M)
+        _check(self._lib.mgwr_get_column(self._h, which,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), False)
+        return out
+
+
+class Batch:
+    """Many independent problems of uneven (N, M, alpha) sharing dims/options."""
+
+    def __init__(self, Ns: Sequence[int], Ms: Sequence[int], alphas: Sequence[float],
+                 Ts: Optional[Sequence[float]] = None, dims: int = 1, **opts):
+        self._lib = load()
+        n = len(Ns)
+        Ts = Ts if Ts is not None else [1.0] * n
+        self.Ns, self.Ms, self.dims = list(Ns), list(Ms), dims
+        self._b = ctypes.c_void_p()
+        o = default_options(**opts)
+        _check(self._lib.mgwr_batch_create(
+            n, (ctypes.c_int * n)(*Ns), (ctypes.c_int * n)(*Ms), (ctypes.c_double * n)(*alphas),
+            (ctypes.c_double * n)(*Ts), dims, ctypes.byref(o), ctypes.byref(self._b)), False)
+
+    def close(self):
+        if self._b:
+            self._lib.mgwr_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, fs, us, gs=None, tol=1e-10):
+        n = len(fs)
+        fp = (ctypes.c_void_p * n)(*[_ptr(f, "f").value for f in fs])
+        up = (ctypes.c_void_p * n)(*[_ptr(u, "u").value for u in us])
+        gp = None
+        if gs is not None:
+            gp = (ctypes.c_void_p * n)(*[(_ptr(g, "g").value if g is not None else None) for g in gs])
+        infos = (Info * n)()
+        _check(self._lib.mgwr_batch_set_stream(self._b, _stream()))
+        rc = self._lib.mgwr_batch_solve(self._b, fp, gp, up, tol, infos)
+        if rc < 0:
+            raise MgwrError(rc, last_error())
+        return rc, [i.as_dict() for i in infos]

@@ -1,0 +1,119 @@
+// Internal interfaces of the MGWR library: device data layouts and the
+// kernel launchers the host runtime (mgwr_capi.cpp) drives.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mgwr {
+
+// Arithmetic of a causal Toeplitz product (history GEMM).
+enum GemmMode { GM_F64 = 0, GM_F32 = 1, GM_BF16X3 = 2 };
+
+// BF16 MFMA fragment table of one Toeplitz coefficient vector t[0..n-1].
+// Fragment q (q = -kQOff .. nq - kQOff - 1) holds, for lane l and element e,
+// t[16 q + (l % 16) - (8 (l / 16) + e)] (zero outside [0, n)): the A operand
+// of v_mfma_f32_16x16x32_bf16 for a 16x32 tile whose row/column origins
+// differ by 16 q.  hi = bf16(t), lo = bf16(t - hi); 1 KB per fragment each.
+constexpr int kQOff = 16;
+
+struct ToepCoef {
+    int n = 0;                 // number of coefficients
+    double *d64 = nullptr;     // [n]
+    float *d32 = nullptr;      // [n]
+    uint16_t *fhi = nullptr;   // [nq][64][8]
+    uint16_t *flo = nullptr;
+    int nq = 0;
+};
+
+// Epilogues of the Toeplitz product acc[i][p] = sum_k t[off + i - k] B[k][p].
+enum EpiKind {
+    EPI_STORE = 0,    // out[i][p] = acc
+    EPI_SCATTER = 1,  // out[i][colour_point(p)] = acc      (smoother: new colour values)
+    EPI_RESID = 2,    // out[i][p] = F + cd*g - acc - A_h U  (residual)
+    EPI_RESID_DD = 3, // same with U = hi + lo, stencil in double-double (FP64 only)
+    EPI_SUB = 4       // out[i][p] -= acc                    (D&C history update)
+};
+
+struct EpiArgs {
+    void *out = nullptr;       // storage type S of the mode (double for F64, float otherwise)
+    long ldo = 0;
+    int dims = 1, n = 1, colour = 0;   // grid of the level (points per dim) and colour
+    const void *F = nullptr;   // [M][ld] rhs of the level (type S)
+    const void *U = nullptr;   // [M][ld] iterate of the level (type S)
+    const double *ulo = nullptr;       // low part of U (EPI_RESID_DD)
+    const double *cd = nullptr;        // c d_{m+1}, m = 0..M-1 (g term), may be null
+    const double *g = nullptr;         // [P] initial condition, may be null
+    long ld = 0;               // leading dimension of F, U (= points of the level)
+    double ih2 = 0.0;          // 1 / h^2
+};
+
+struct GemmArgs {
+    int mode = GM_F64;
+    int M = 0;         // output rows (time levels)
+    int P = 0;         // columns
+    int K = 0;         // rows of B
+    int off = 0;       // coefficient index s = off + i - k
+    const ToepCoef *coef = nullptr;
+    const void *B = nullptr;   // F64: double [K][ldb]; F32: float [K][ldb];
+    const void *Bhi = nullptr; // BF16X3: uint16 k8-packed [K/8][ldb][8]
+    const void *Blo = nullptr;
+    long ldb = 0;
+    int epi = EPI_STORE;
+    EpiArgs ea;
+};
+
+// Flat point index of the j-th point of a colour (0: n even / n + l even).
+__host__ __device__ inline int colour_point(int dims, int n, int colour, int j)
+{
+    if (dims == 1) return colour == 0 ? 2 * j + 1 : 2 * j;
+    int a = (colour == 0) ? (n + 1) / 2 : n / 2;   // points of the colour in an odd row
+    int q = j / n, r = j - q * n;
+    if (r < a) {   // row l = 2q + 1 (odd)
+        int x = (colour == 0) ? 2 * r : 2 * r + 1;
+        return (2 * q) * n + x;
+    }
+    r -= a;        // row l = 2q + 2 (even)
+    int x = (colour == 0) ? 2 * r + 1 : 2 * r;
+    return (2 * q + 1) * n + x;
+}
+__host__ __device__ inline int colour_count(int dims, int n, int colour)
+{
+    if (dims == 1) return colour == 0 ? n / 2 : (n + 1) / 2;
+    long t = (long)n * n;
+    return colour == 0 ? (int)((t + 1) / 2) : (int)(t / 2);
+}
+
+// ---- launchers (all asynchronous on `s`) ----
+hipError_t launch_toep_gemm(const GemmArgs &a, hipStream_t s);
+
+// panel[k][j] = F[k][pt] + cd[k] g[pt] + (sum of neighbours of pt in U)[k] * ih2,
+// pt = colour_point(j); S = double (f64) or float; packed: write bf16 hi/lo
+// k8-packed [Mpad/8][ldp][8] instead of a plain [M][ldp] panel.
+hipError_t launch_rhs_panel(int f64, int packed, int dims, int n, int colour, int M, int Mpad,
+                            const void *F, const void *U, const double *cd, const double *g,
+                            double ih2, void *panel, void *panel_lo, long ldp, hipStream_t s);
+// Split a float array [M][P] into bf16 hi/lo k8-packed [Mpad/8][ldp][8].
+hipError_t launch_split_bf16(int M, int Mpad, int P, const float *X, uint16_t *hi, uint16_t *lo,
+                             long ldp, hipStream_t s);
+// Scatter a plain panel X[M][ldx] into the colour points of U (type S).
+hipError_t launch_scatter(int f64, int dims, int n, int colour, int M, const void *X, long ldx,
+                          void *U, hipStream_t s);
+hipError_t launch_restrict(int f64, int dims, int nf, int M, const void *rf, void *rc, hipStream_t s);
+hipError_t launch_prolong_add(int f64, int dims, int nc, int M, const void *ec, void *uf,
+                              hipStream_t s);
+// u[k][p] = g ? g[p] : 0 (S = double or float), count = M * P
+hipError_t launch_fill(int f64, long M, long P, const double *g, void *u, hipStream_t s);
+// Block partials of {max |x|, sum x^2} for x double[n]; if out32 != null also
+// writes float(x) there.  partials: [nblk][2]; returns nblk via *nblk.
+hipError_t launch_norm_partials(long n, const double *x, float *out32, double *partials,
+                                int *nblk, hipStream_t s);
+hipError_t launch_norm_final(int nblk, const double *partials, double *out2, hipStream_t s);
+// (hi, lo) += e; e double or float; lo may be null (plain FP64 add).
+hipError_t launch_dd_update(long n, int e_f64, const void *e, double *hi, double *lo,
+                            hipStream_t s);
+// Fill one coefficient table (fp32 copy and bf16 fragment table) from d64.
+hipError_t launch_build_coef(ToepCoef &c, hipStream_t s);
+int norm_partial_blocks(long n);
+
+}  // namespace mgwr
