@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X MGWR solver: space-time unknowns per second to a
+1e-10 relative residual, mixed precision against FP64, on one GPU.
+
+Workload (default "1d"): the 1D time-fractional heat equation on (0,1) x (0,1]
+with N = 4095 interior points and M = 16384 time steps, alpha in {0.3, 0.7},
+forcing = manufactured term of u = t^2 sin(pi x) plus a seeded 20-mode random
+field (paper_1608_05400_amd.workloads.config2).  One step solves both alpha
+problems from u = 0 with a V(1,1) cycle until the FP64 residual is reduced by
+--tol in the max norm.  Inputs are resident in HBM before the timed region.
+
+Modes: "bf16x3" (split-BF16 inner cycle, FP64 double-double refinement; the
+reported value), "fp64" (Algorithm 1 in FP64 on u), "fp32" (FP32 inner
+cycle), "fp64r" (FP64 inner cycle with double-double refinement).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "space-time unknowns/sec to 1e-10 rel residual, mixed vs FP64 MGWR, 1 GPU"
+PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}   # MI355X dense: FP64, FP32, BF16 MFMA
+MODE_DTYPE = {0: "f64", 1: "f32", 2: "bf16"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def make_workloads(name):
+    from paper_1608_05400_amd import workloads as W
+    if name == "1d":
+        return [W.config2(0.3), W.config2(0.7)], "1d_N4095_M16384_alpha0.3+0.7"
+    if name == "2d":
+        return [W.manufactured_2d(511, 2048, 0.4)], "2d_N511_M2048_alpha0.4"
+    if name == "2dns":
+        return [W.nonsmooth_2d(1023, 1024, 0.3)], "2d_nonsmooth_N1023_M1024_alpha0.3"
+    if name == "small":
+        return [W.manufactured_1d()], "1d_N63_M64_alpha0.5"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def sampled_error(w, u_dev, npts=4096, seed=0):
+    """Max relative error of u against the exact discrete solution at sampled
+    space-time points, from the oracle's modal solve (the forcing is a finite
+    sum of sine modes)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    v = oracle.modal_solve(w.dims, w.N, w.M, w.alpha, w.kx, w.s, ky=w.ky)
+    m = rng.integers(1, w.M + 1, size=npts)
+    m[:64] = w.M
+    n = rng.integers(1, w.N + 1, size=npts)
+    l = rng.integers(1, w.N + 1, size=npts) if w.dims == 2 else np.ones(npts, dtype=np.int64)
+    ref = oracle.modal_eval(w.dims, w.N, w.M, w.kx, v, np.stack([m, n, l], 1), ky=w.ky)
+    import torch
+    if w.dims == 1:
+        idx = (m - 1) * w.N + (n - 1)
+    else:
+        idx = (m - 1) * w.N * w.N + (l - 1) * w.N + (n - 1)
+    got = u_dev.reshape(-1)[torch.from_numpy(idx).to(u_dev.device)].cpu().numpy()
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def run_mode(mode, wls, fs, steps, warmup, tol, check, profile):
+    import torch
+    from paper_1608_05400_amd import binding as B
+    solvers = [B.Solver(w.N, w.M, w.alpha, T=w.T, dims=w.dims, precision=mode, maxit=40) for w in wls]
+    us = [torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda") for s in solvers]
+    infos = []
+    for it in range(warmup):
+        for s, f, u in zip(solvers, fs, us):
+            s.solve(f, u, tol=tol)
+        log(f"{mode}: warmup {it + 1}/{warmup} done")
+    if profile:
+        for s in solvers:
+            s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        infos = []
+        for s, f, u in zip(solvers, fs, us):
+            infos.append(s.solve(f, u, tol=tol))
+        log(f"{mode}: step {k + 1}/{steps} done, iters {[i['iters'] for i in infos]}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    records = []
+    if profile:
+        for s in solvers:
+            records += s.profile_records()
+            s.profile(False)
+    unknowns = sum(w.unknowns for w in wls)
+    res = {
+        "mode": mode,
+        "value": unknowns * steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "iters": [i["iters"] for i in infos],
+        "status": [i["status"] for i in infos],
+        "relres": [i["relres"] for i in infos],
+        "mean_factor": [round(i["mean_factor"], 5) for i in infos],
+    }
+    if check:
+        res["err_vs_oracle"] = [sampled_error(w, u) for w, u in zip(wls, us)]
+    for s in solvers:
+        s.close()
+    del us
+    torch.cuda.empty_cache()
+    return res, records
+
+
+def roofline_of(records, steps):
+    """Dominant Toeplitz-product kernel (largest total time) and its achieved
+    algorithmic FLOP rate from the per-launch HIP events."""
+    if not records:
+        return None
+    from paper_1608_05400_amd import binding as B
+    by = {}
+    for r in records:
+        d = by.setdefault(r["kernel"], {"ms": 0.0, "flops": 0.0, "n": 0})
+        d["ms"] += r["ms"]
+        d["flops"] += r["flops"]
+        d["n"] += 1
+    kid = max(by, key=lambda k: by[k]["ms"])
+    d = by[kid]
+    mode = kid >> 4
+    achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[mode]
+    out = {
+        "bound": "mfma",
+        "kernel": B.kernel_name(kid),
+        "dtype": MODE_DTYPE[mode],
+        "achieved": round(achieved, 2),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": None,
+        "launches_per_step": d["n"] // max(1, steps),
+        "avg_launch_ms": round(d["ms"] / d["n"], 4),
+        "avg_launch_gflop": round(d["flops"] / d["n"] / 1e9, 3),
+        "share_of_product_time": round(d["ms"] / sum(v["ms"] for v in by.values()), 3),
+    }
+    if mode == 2:
+        out["issued_frac"] = round(3 * achieved / peak, 4)   # three BF16 passes per product
+    return out
+
+
+def cpu_baseline(w, seconds):
+    """The oracle's direct time-stepping solve on a bounded sample: the first
+    Ms time levels of the full problem; its cost is dominated by the O(N M^2)
+    history sum, so the full-problem time is scaled by (M / Ms)^2."""
+    import oracle
+    f = w.forcing()
+    oracle.direct_solve(w.dims, w.N, w.M, w.alpha, f, Mstop=64)   # load, page in
+    ms0 = min(w.M, 512)
+    t = time.perf_counter()
+    oracle.direct_solve(w.dims, w.N, w.M, w.alpha, f, Mstop=ms0)
+    t0 = time.perf_counter() - t
+    Ms = int(min(w.M, max(ms0, ms0 * math.sqrt(seconds / max(t0, 1e-3)))))
+    t = time.perf_counter()
+    oracle.direct_solve(w.dims, w.N, w.M, w.alpha, f, Mstop=Ms)
+    ts = time.perf_counter() - t
+    t_full = ts * (w.M / Ms) ** 2
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    return {"value": w.unknowns / t_full, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": (f"direct time-stepping solve of {w.name}: first {Ms} of {w.M} time levels "
+                       f"took {ts:.2f} s; full-solve time scaled by (M/Ms)^2 = {t_full:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="1d", choices=["1d", "2d", "2dns", "small"])
+    ap.add_argument("--modes", default="bf16x3,fp64,fp32,fp64r")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    from paper_1608_05400_amd import binding as B
+    B.load()
+    wls, wname = make_workloads(args.workload)
+    fs = [w.forcing_torch("cuda").contiguous() for w in wls]
+    torch.cuda.synchronize()
+    log(f"workload {wname}: {sum(w.unknowns for w in wls)} unknowns per step")
+
+    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
+    results = {}
+    rooflines = {}
+    for i, mode in enumerate(modes):
+        steps = args.steps if i < 2 else max(1, min(args.steps, 1))
+        res, recs = run_mode(mode, wls, fs, steps, args.warmup if i < 2 else 0, args.tol,
+                             not args.no_check, profile=True)
+        results[mode] = res
+        rooflines[mode] = roofline_of(recs, steps)
+        log(f"{mode}: {res['value']:.4g} unknowns/s, {res['ms_per_step']:.1f} ms/step, "
+            f"iters {res['iters']}, relres {res['relres']}, err {res.get('err_vs_oracle')}")
+
+    primary = modes[0]
+    p = results[primary]
+    line = {
+        "metric": METRIC,
+        "value": p["value"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": p["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+bf16x3" if primary == "bf16x3" else ("f64+f32" if primary == "fp32" else "f64"),
+        "data": "synthetic",
+        "config": {"workload": wname, "mode": primary, "cycle": "V(1,1)", "tol": args.tol,
+                   "norm": "max"},
+        "roofline": rooflines.get(primary),
+        "modes": results,
+        "rooflines": rooflines,
+    }
+    if "fp64" in results and primary != "fp64":
+        line["speedup_vs_fp64"] = p["value"] / results["fp64"]["value"]
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
+        log(f"cpu baseline: {line['cpu_baseline']['value']:.4g} unknowns/s")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,28 @@ int mgwr_batch_solve(mgwr_batch_t b, const double *const *f, const double *const
 int mgwr_batch_set_stream(mgwr_batch_t b, void *hip_stream);
 int mgwr_batch_destroy(mgwr_batch_t b);
 
+/* ---- per-launch timing of the Toeplitz products (history GEMMs) ----
+ * With profiling on, every Toeplitz-product launch of the handle is bracketed
+ * by HIP events recorded on the handle's stream.  kernel identifies the
+ * kernel instantiation: (mode << 4) | (epilogue << 1) | narrow, with mode 0 =
+ * FP64, 1 = FP32, 2 = split-BF16; epilogue 0 = store, 1 = colour scatter
+ * (smoother), 2 = residual, 3 = residual with double-double iterate, 4 =
+ * subtract; narrow = 1 for the few-column variant.  flops counts the
+ * multiply-adds of the product that are not structurally zero, times 2. */
+typedef struct {
+    int kernel, level, M, P, K;
+    double flops;  /* algorithmic flops of the launch                        */
+    double ms;     /* elapsed time between the two events                    */
+} mgwr_kernel_record;
+
+/* on != 0 clears the records and starts recording; on == 0 stops. */
+int mgwr_profile_enable(mgwr_t h, int on);
+/* Number of records (synchronises the handle's stream). */
+int mgwr_profile_count(mgwr_t h);
+int mgwr_profile_get(mgwr_t h, int i, mgwr_kernel_record *rec);
+/* Name of the kernel function of a kernel id (as profilers print it). */
+const char *mgwr_kernel_name(int kernel);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *mgwr_last_error(void);
 

@@ -27,6 +27,7 @@ EXPORTED = [
     "mgwr_set_options", "mgwr_get_options", "mgwr_set_stream", "mgwr_smooth", "mgwr_residual",
     "mgwr_vcycle", "mgwr_solve", "mgwr_toeplitz_apply", "mgwr_get_column", "mgwr_levels",
     "mgwr_batch_create", "mgwr_batch_solve", "mgwr_batch_set_stream", "mgwr_batch_destroy",
+    "mgwr_profile_enable", "mgwr_profile_count", "mgwr_profile_get", "mgwr_kernel_name",
     "mgwr_last_error",
 ]
 
@@ -43,6 +44,12 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("first_colour", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("dc_block", ctypes.c_int),
                 ("L", ctypes.c_double), ("stall", ctypes.c_double)]
+
+
+class KernelRecord(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int), ("level", ctypes.c_int), ("M", ctypes.c_int),
+                ("P", ctypes.c_int), ("K", ctypes.c_int), ("flops", ctypes.c_double),
+                ("ms", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -90,6 +97,11 @@ def load(path: str = LIB_PATH):
     lib.mgwr_batch_solve.argtypes = [h, P(VP), P(VP), P(VP), D, P(Info)]
     lib.mgwr_batch_set_stream.argtypes = [h, VP]
     lib.mgwr_batch_destroy.argtypes = [h]
+    lib.mgwr_profile_enable.argtypes = [h, I]
+    lib.mgwr_profile_count.argtypes = [h]
+    lib.mgwr_profile_get.argtypes = [h, I, P(KernelRecord)]
+    lib.mgwr_kernel_name.argtypes = [I]
+    lib.mgwr_kernel_name.restype = ctypes.c_char_p
     lib.mgwr_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
@@ -127,6 +139,10 @@ def l1_weights(M: int, alpha: float, T: float = 1.0):
     _check(load().mgwr_l1_weights(M, alpha, T, ctypes.byref(c),
                                   r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), False)
     return c.value, r
+
+
+def kernel_name(kernel: int) -> str:
+    return load().mgwr_kernel_name(kernel).decode()
 
 
 def _ptr(t, name, shape=None, allow_none=False):
@@ -260,6 +276,20 @@ class Solver:
         _check(self._lib.mgwr_toeplitz_apply(self._h, which, precision, _ptr(B, "B"), P, P,
                                              _ptr(C, "C"), P), False)
         return C
+
+    def profile(self, on=True):
+        """Start (clearing old records) or stop per-launch timing of the products."""
+        _check(self._lib.mgwr_profile_enable(self._h, 1 if on else 0), False)
+
+    def profile_records(self):
+        n = _check(self._lib.mgwr_profile_count(self._h))
+        out = []
+        rec = KernelRecord()
+        for i in range(n):
+            _check(self._lib.mgwr_profile_get(self._h, i, ctypes.byref(rec)), False)
+            out.append({"kernel": rec.kernel, "name": kernel_name(rec.kernel), "level": rec.level,
+                        "M": rec.M, "P": rec.P, "K": rec.K, "flops": rec.flops, "ms": rec.ms})
+        return out
 
     def column(self, which=-1):
         import numpy as np

@@ -142,9 +142,11 @@ struct Level {
     long P = 0;
     int Pc[2] = {0, 0};
     double h = 0, ih2 = 0, sigma = 0;
-    ToepCoef inv;
+    ToepCoef inv;     // first column of (T_M + sigma I)^{-1}
+    ToepCoef inv_h;   // the same without its first entry (history part)
+    double lam0 = 0;  // first entry of that column
     double *u64 = nullptr, *f64 = nullptr;  // FP64 hierarchy (levels below the finest)
-    void *e = nullptr, *fe = nullptr;       // inner hierarchy of the refinement (all levels)
+    double *e = nullptr, *fe = nullptr;     // inner hierarchy of the refinement (all levels)
 };
 
 }  // namespace
@@ -157,17 +159,24 @@ struct mgwr_ctx {
     int device = 0;
     double c = 0;
     std::vector<double> r_host, d_host;
-    ToepCoef tm;
+    ToepCoef tm;      // first column of T_M
+    ToepCoef tm_h;    // the same without r_1 (history part)
     double *cd = nullptr;
     std::vector<Level> lv;
     int Mpad = 0;
     long maxPc = 0;
     // workspace
     double *res64 = nullptr, *panel64 = nullptr, *ulo = nullptr, *rs64 = nullptr;
-    float *rs32 = nullptr, *panel32 = nullptr, *fe32_fine = nullptr;
+    float *panel32 = nullptr, *op32 = nullptr;
     uint16_t *pk_hi = nullptr, *pk_lo = nullptr;
     long pk_ld = 0;
     double *partials = nullptr, *norms_dev = nullptr, *norms_host = nullptr;
+    // per-launch timing of the Toeplitz products
+    bool prof = false;
+    struct Pending { hipEvent_t a, b; mgwr_kernel_record rec; };
+    std::vector<Pending> pending;
+    std::vector<mgwr_kernel_record> records;
+    std::vector<hipEvent_t> event_pool;
     int inner_prec = -1;             // precision the inner buffers exist for
     std::vector<void *> inner_alloc; // buffers owned by the inner hierarchy
     std::vector<void *> alloc;       // everything else
@@ -206,6 +215,71 @@ int upload_coef(mgwr_ctx *h, ToepCoef &c, const std::vector<double> &v)
     return MGWR_OK;
 }
 
+// Multiply-adds of a Toeplitz product that are not structurally zero.
+double product_flops(const GemmArgs &a)
+{
+    double macs = 0;
+    for (int i = 0; i < a.M; ++i) {
+        long lo = std::max(0, a.off + i - a.coef->n + 1), hi = std::min(a.K - 1, i + a.off);
+        if (hi >= lo) macs += (double)(hi - lo + 1);
+    }
+    return 2.0 * macs * a.P;
+}
+
+int kernel_id(const GemmArgs &a)
+{
+    int narrow = (a.mode != GM_BF16X3 && a.P <= 32) ? 1 : 0;
+    return (a.mode << 4) | (a.epi << 1) | narrow;
+}
+
+hipEvent_t take_event(mgwr_ctx *h)
+{
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int resolve_profile(mgwr_ctx *h)
+{
+    if (h->pending.empty()) return MGWR_OK;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (auto &p : h->pending) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+        p.rec.ms = ms;
+        h->records.push_back(p.rec);
+        h->event_pool.push_back(p.a);
+        h->event_pool.push_back(p.b);
+    }
+    h->pending.clear();
+    return MGWR_OK;
+}
+
+int run_gemm(mgwr_ctx *h, const GemmArgs &a, int level)
+{
+    if (!h->prof) {
+        HIPCHK(launch_toep_gemm(a, h->stream));
+        return MGWR_OK;
+    }
+    mgwr_ctx::Pending p;
+    p.a = take_event(h);
+    p.b = take_event(h);
+    if (!p.a || !p.b) return fail(MGWR_EDEVICE, "hipEventCreate failed");
+    p.rec.kernel = kernel_id(a); p.rec.level = level; p.rec.M = a.M; p.rec.P = a.P; p.rec.K = a.K;
+    p.rec.flops = product_flops(a); p.rec.ms = 0;
+    HIPCHK(hipEventRecord(p.a, h->stream));
+    HIPCHK(launch_toep_gemm(a, h->stream));
+    HIPCHK(hipEventRecord(p.b, h->stream));
+    h->pending.push_back(p);
+    if (h->pending.size() >= 4096) CHK(resolve_profile(h));
+    return MGWR_OK;
+}
+
 bool is_pow2m1(int N)
 {
     return N >= 1 && ((N + 1) & N) == 0;
@@ -230,68 +304,64 @@ int check_opts(const mgwr_options *o)
     return MGWR_OK;
 }
 
-bool inner_f64(int prec) { return prec == MGWR_FP64 || prec == MGWR_FP64_REFINED; }
-
-// Allocate the buffers the refinement with precision `prec` needs.
+// Allocate the buffers the refinement with precision `prec` needs.  The
+// inner hierarchy is FP64 in every precision; FP32 / split-BF16 appear only
+// as product operands.
 int alloc_inner(mgwr_t h, int prec)
 {
     if (h->inner_prec == prec) return MGWR_OK;
     free_list(h->inner_alloc);
     for (auto &L : h->lv) { L.e = nullptr; L.fe = nullptr; }
-    h->rs64 = nullptr; h->rs32 = nullptr; h->panel32 = nullptr; h->fe32_fine = nullptr;
+    h->rs64 = nullptr; h->panel32 = nullptr; h->op32 = nullptr;
     h->pk_hi = h->pk_lo = nullptr;
     h->inner_prec = -1;
     const long M = h->M;
     const int nl = (int)h->lv.size();
     const long Pf = h->lv.back().P;
-    if (prec == MGWR_FP64) {
-        h->inner_prec = prec;
-        return MGWR_OK;
-    }
-    if (prec == MGWR_FP64_REFINED) {
+    if (prec != MGWR_FP64) {
         for (int l = 0; l < nl; ++l) {
-            CHK(dmalloc(h, h->inner_alloc, &h->lv[l].e, sizeof(double) * M * h->lv[l].P));
+            CHK(dmalloc(h, h->inner_alloc, (void **)&h->lv[l].e, sizeof(double) * M * h->lv[l].P));
             if (l < nl - 1)
-                CHK(dmalloc(h, h->inner_alloc, &h->lv[l].fe, sizeof(double) * M * h->lv[l].P));
+                CHK(dmalloc(h, h->inner_alloc, (void **)&h->lv[l].fe, sizeof(double) * M * h->lv[l].P));
         }
-        h->lv.back().fe = h->res64;
+        h->lv.back().fe = h->res64;   // the outer residual is the finest right-hand side
         CHK(dmalloc(h, h->inner_alloc, (void **)&h->rs64, sizeof(double) * M * Pf));
-    } else {
-        for (int l = 0; l < nl; ++l) {
-            CHK(dmalloc(h, h->inner_alloc, &h->lv[l].e, sizeof(float) * M * h->lv[l].P));
-            CHK(dmalloc(h, h->inner_alloc, &h->lv[l].fe, sizeof(float) * M * h->lv[l].P));
-        }
-        h->fe32_fine = (float *)h->lv.back().fe;
-        CHK(dmalloc(h, h->inner_alloc, (void **)&h->rs32, sizeof(float) * M * Pf));
+    }
+    if (prec == MGWR_MIXED_FP32 || prec == MGWR_MIXED_BF16X3) {
         CHK(dmalloc(h, h->inner_alloc, (void **)&h->panel32, sizeof(float) * M * h->maxPc));
-        if (prec == MGWR_MIXED_BF16X3) {
-            h->pk_ld = (Pf + 127) / 128 * 128;
-            size_t bytes = sizeof(uint16_t) * (size_t)h->Mpad * h->pk_ld;
-            CHK(dmalloc(h, h->inner_alloc, (void **)&h->pk_hi, bytes));
-            CHK(dmalloc(h, h->inner_alloc, (void **)&h->pk_lo, bytes));
-        }
+        CHK(dmalloc(h, h->inner_alloc, (void **)&h->op32, sizeof(float) * M * Pf));
+    }
+    if (prec == MGWR_MIXED_BF16X3) {
+        h->pk_ld = (Pf + 127) / 128 * 128;
+        size_t bytes = sizeof(uint16_t) * (size_t)h->Mpad * h->pk_ld;
+        CHK(dmalloc(h, h->inner_alloc, (void **)&h->pk_hi, bytes));
+        CHK(dmalloc(h, h->inner_alloc, (void **)&h->pk_lo, bytes));
     }
     h->inner_prec = prec;
     return MGWR_OK;
 }
 
 // ---------------------------------------------------------------------------
-// One cycle over a hierarchy whose per-level iterate/rhs are given.
+// One cycle over a hierarchy whose per-level iterate/rhs are given (FP64).
 struct Hier {
-    int f64;                    // storage double (else float)
-    int prec;                   // precision of the products (enum mgwr_precision)
-    std::vector<void *> u, f;   // per level
-    const double *g;            // initial condition on the finest level (plain FP64 only)
-    void *rscratch;             // residual scratch [M][P_fine] of the storage type
+    int prec;                     // precision of the products (enum mgwr_precision)
+    std::vector<double *> u, f;   // per level
+    const double *g;              // initial condition on the finest level (plain FP64 only)
+    double *rscratch;             // residual scratch [M][P_fine]
 };
 
 int level_mode(const Hier &H, long cols)
 {
-    if (H.f64) return GM_F64;
+    if (H.prec == MGWR_FP64 || H.prec == MGWR_FP64_REFINED) return GM_F64;
     if (H.prec == MGWR_MIXED_BF16X3 && cols >= kBf16MinCols) return GM_BF16X3;
     return GM_F32;
 }
 
+// One half-sweep: every point of `colour` on level `lev` gets the solution of
+// (T_M + sigma I) x = b along its time line, as one Toeplitz product with the
+// precomputed inverse column.  In FP64 the product is the whole solve; in
+// FP32 / split-BF16 the product covers the strictly lower (history) part and
+// the epilogue adds lambda_0 b with b rebuilt in FP64.
 int half_sweep(mgwr_t h, const Hier &H, int lev, int colour)
 {
     Level &L = h->lv[lev];
@@ -301,21 +371,25 @@ int half_sweep(mgwr_t h, const Hier &H, int lev, int colour)
     const double *g = fine ? H.g : nullptr;
     GemmArgs a;
     a.mode = level_mode(H, Pc);
-    a.M = h->M; a.P = Pc; a.K = h->M; a.off = 0; a.coef = &L.inv;
-    a.epi = EPI_SCATTER;
+    a.M = h->M; a.P = Pc; a.K = h->M; a.off = 0;
     a.ea.out = H.u[lev]; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n; a.ea.colour = colour;
-    if (a.mode == GM_BF16X3) {
-        long ldp = (Pc + 127) / 128 * 128;
-        HIPCHK(launch_rhs_panel(0, 1, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], nullptr,
-                                nullptr, L.ih2, h->pk_hi, h->pk_lo, ldp, h->stream));
-        a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+    a.ea.F = H.f[lev]; a.ea.ld = L.P; a.ea.ih2 = L.ih2; a.ea.cd = h->cd; a.ea.g = g;
+    if (a.mode == GM_F64) {
+        HIPCHK(launch_rhs_panel(0, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
+                                h->panel64, nullptr, Pc, h->stream));
+        a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
+    } else if (a.mode == GM_F32) {
+        HIPCHK(launch_rhs_panel(1, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
+                                h->panel32, nullptr, Pc, h->stream));
+        a.coef = &L.inv_h; a.epi = EPI_SMOOTH; a.ea.diag = L.lam0; a.B = h->panel32; a.ldb = Pc;
     } else {
-        void *panel = H.f64 ? (void *)h->panel64 : (void *)h->panel32;
-        HIPCHK(launch_rhs_panel(H.f64, 0, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd,
-                                g, L.ih2, panel, nullptr, Pc, h->stream));
-        a.B = panel; a.ldb = Pc;
+        long ldp = (Pc + 127) / 128 * 128;
+        HIPCHK(launch_rhs_panel(2, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
+                                h->pk_hi, h->pk_lo, ldp, h->stream));
+        a.coef = &L.inv_h; a.epi = EPI_SMOOTH; a.ea.diag = L.lam0;
+        a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
     }
-    HIPCHK(launch_toep_gemm(a, h->stream));
+    CHK(run_gemm(h, a, lev));
     return MGWR_OK;
 }
 
@@ -327,27 +401,29 @@ int sweep(mgwr_t h, const Hier &H, int lev)
     return MGWR_OK;
 }
 
-// out = f + c d g - T_M u - A_h u on level lev (storage type of H).
-int level_residual(mgwr_t h, const Hier &H, int lev, void *out)
+// out = f + c d g - T_M u - A_h u on level lev.
+int level_residual(mgwr_t h, const Hier &H, int lev, double *out)
 {
     Level &L = h->lv[lev];
     const bool fine = (lev == (int)h->lv.size() - 1);
     GemmArgs a;
     a.mode = level_mode(H, L.P);
-    a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm;
+    a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0;
     a.epi = EPI_RESID;
     a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
     a.ea.F = H.f[lev]; a.ea.U = H.u[lev]; a.ea.ld = L.P; a.ea.ih2 = L.ih2;
     a.ea.cd = h->cd; a.ea.g = fine ? H.g : nullptr;
-    if (a.mode == GM_BF16X3) {
-        long ldp = (L.P + 127) / 128 * 128;
-        HIPCHK(launch_split_bf16(h->M, h->Mpad, (int)L.P, (const float *)H.u[lev], h->pk_hi, h->pk_lo, ldp,
-                                 h->stream));
-        a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+    if (a.mode == GM_F64) {
+        a.coef = &h->tm; a.B = H.u[lev]; a.ldb = L.P;
+    } else if (a.mode == GM_F32) {
+        HIPCHK(launch_operand(1, h->M, h->Mpad, (int)L.P, H.u[lev], h->op32, nullptr, L.P, h->stream));
+        a.coef = &h->tm_h; a.ea.diag = h->c; a.B = h->op32; a.ldb = L.P;
     } else {
-        a.B = H.u[lev]; a.ldb = L.P;
+        long ldp = (L.P + 127) / 128 * 128;
+        HIPCHK(launch_operand(2, h->M, h->Mpad, (int)L.P, H.u[lev], h->pk_hi, h->pk_lo, ldp, h->stream));
+        a.coef = &h->tm_h; a.ea.diag = h->c; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
     }
-    HIPCHK(launch_toep_gemm(a, h->stream));
+    CHK(run_gemm(h, a, lev));
     return MGWR_OK;
 }
 
@@ -358,10 +434,10 @@ int cycle(mgwr_t h, const Hier &H, int lev)
     for (int i = 0; i < o.nu1; ++i) CHK(sweep(h, H, lev));
     Level &L = h->lv[lev];
     CHK(level_residual(h, H, lev, H.rscratch));
-    HIPCHK(launch_restrict(H.f64, h->dims, L.n, h->M, H.rscratch, H.f[lev - 1], h->stream));
-    HIPCHK(launch_fill(H.f64, h->M, h->lv[lev - 1].P, nullptr, H.u[lev - 1], h->stream));
+    HIPCHK(launch_restrict(h->dims, L.n, h->M, H.rscratch, H.f[lev - 1], h->stream));
+    HIPCHK(launch_fill(h->M, h->lv[lev - 1].P, nullptr, H.u[lev - 1], h->stream));
     for (int k = 0; k < o.gamma; ++k) CHK(cycle(h, H, lev - 1));
-    HIPCHK(launch_prolong_add(H.f64, h->dims, h->lv[lev - 1].n, h->M, H.u[lev - 1], H.u[lev], h->stream));
+    HIPCHK(launch_prolong_add(h->dims, h->lv[lev - 1].n, h->M, H.u[lev - 1], H.u[lev], h->stream));
     for (int i = 0; i < o.nu2; ++i) CHK(sweep(h, H, lev));
     return MGWR_OK;
 }
@@ -369,27 +445,24 @@ int cycle(mgwr_t h, const Hier &H, int lev)
 Hier plain_hier(mgwr_t h, const double *f, const double *g, double *u)
 {
     Hier H;
-    H.f64 = 1; H.prec = MGWR_FP64; H.g = g; H.rscratch = h->res64;
+    H.prec = MGWR_FP64; H.g = g; H.rscratch = h->res64;
     for (auto &L : h->lv) { H.u.push_back(L.u64); H.f.push_back(L.f64); }
-    H.u.back() = u; H.f.back() = (void *)f;
+    H.u.back() = u; H.f.back() = (double *)f;
     return H;
 }
 
 Hier inner_hier(mgwr_t h)
 {
     Hier H;
-    H.f64 = inner_f64(h->opt.precision) ? 1 : 0;
-    H.prec = h->opt.precision; H.g = nullptr;
-    H.rscratch = H.f64 ? (void *)h->rs64 : (void *)h->rs32;
+    H.prec = h->opt.precision; H.g = nullptr; H.rscratch = h->rs64;
     for (auto &L : h->lv) { H.u.push_back(L.e); H.f.push_back(L.fe); }
     return H;
 }
 
-// FP64 residual of the finest level into res64 (double-double iterate when lo
-// != nullptr) and its norms (host, synchronising).  If out32 != nullptr the
-// residual is also written there as float.
+// FP64 residual of the finest level into res (double-double iterate when lo
+// != nullptr) and its norms (host, synchronising).
 int fine_residual_norms(mgwr_t h, const double *f, const double *g, const double *u, const double *lo,
-                        double *res, float *out32, double norms[2])
+                        double *res, double norms[2])
 {
     Level &L = h->lv.back();
     GemmArgs a;
@@ -399,10 +472,10 @@ int fine_residual_norms(mgwr_t h, const double *f, const double *g, const double
     a.ea.out = res; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
     a.ea.F = f; a.ea.U = u; a.ea.ulo = lo; a.ea.ld = L.P; a.ea.ih2 = L.ih2; a.ea.cd = h->cd; a.ea.g = g;
     a.B = u; a.ldb = L.P;
-    HIPCHK(launch_toep_gemm(a, h->stream));
+    CHK(run_gemm(h, a, (int)h->lv.size() - 1));
     if (norms) {
         int nblk = 0;
-        HIPCHK(launch_norm_partials((long)h->M * L.P, res, out32, h->partials, &nblk, h->stream));
+        HIPCHK(launch_norm_partials((long)h->M * L.P, res, h->partials, &nblk, h->stream));
         HIPCHK(launch_norm_final(nblk, h->partials, h->norms_dev, h->stream));
         HIPCHK(hipMemcpyAsync(h->norms_host, h->norms_dev, 2 * sizeof(double), hipMemcpyDeviceToHost,
                               h->stream));
@@ -468,6 +541,8 @@ int mgwr_destroy(mgwr_t h)
     free_list(h->inner_alloc);
     free_list(h->alloc);
     if (h->norms_host) hipHostFree(h->norms_host);
+    for (auto &p : h->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+    for (auto e : h->event_pool) hipEventDestroy(e);
     delete h;
     return MGWR_OK;
 }
@@ -522,7 +597,15 @@ int mgwr_create_ex(int N, int M, double alpha, double T, int dims, const mgwr_op
             th.emplace_back([&, l]() { inverse_column(h->r_host, h->lv[l].sigma, lam[l]); });
         for (auto &t : th) t.join();
         CHK(upload_coef(h, h->tm, h->r_host));
-        for (size_t l = 0; l < h->lv.size(); ++l) CHK(upload_coef(h, h->lv[l].inv, lam[l]));
+        std::vector<double> hist = h->r_host;
+        hist[0] = 0.0;
+        CHK(upload_coef(h, h->tm_h, hist));
+        for (size_t l = 0; l < h->lv.size(); ++l) {
+            CHK(upload_coef(h, h->lv[l].inv, lam[l]));
+            h->lv[l].lam0 = lam[l][0];
+            lam[l][0] = 0.0;
+            CHK(upload_coef(h, h->lv[l].inv_h, lam[l]));
+        }
         std::vector<double> cdv(M);
         for (int m = 0; m < M; ++m) cdv[m] = h->c * h->d_host[m + 1];
         CHK(dmalloc(h, h->alloc, (void **)&h->cd, sizeof(double) * M));
@@ -613,7 +696,7 @@ int mgwr_residual(mgwr_t h, const double *f, const double *g, const double *u, d
     CHK(check_ptr(r, "r"));
     CHK(set_device(h));
     double nrm[2];
-    CHK(fine_residual_norms(h, f, g, u, nullptr, r, nullptr, norms ? nrm : nullptr));
+    CHK(fine_residual_norms(h, f, g, u, nullptr, r, norms ? nrm : nullptr));
     if (norms) { norms[0] = nrm[0]; norms[1] = nrm[1]; }
     return MGWR_OK;
 }
@@ -641,7 +724,7 @@ int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol
     CHK(alloc_inner(h, prec));
     const long Pf = h->lv.back().P;
     const long n = (long)h->M * Pf;
-    if (!o.warm_start) HIPCHK(launch_fill(1, h->M, Pf, g, u, h->stream));
+    if (!o.warm_start) HIPCHK(launch_fill(h->M, Pf, g, u, h->stream));
     if (refine) HIPCHK(hipMemsetAsync(h->ulo, 0, sizeof(double) * n, h->stream));
     Hier Hp = plain_hier(h, f, g, u);
     Hier Hi;
@@ -651,11 +734,10 @@ int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol
     memset(&inf, 0, sizeof inf);
     int status = MGWR_NOT_CONVERGED;
     double r0 = 0, prev = 0, rn = 0;
-    int it = 0;
+    int it = 0, slow = 0;
     for (;; ++it) {
         double nrm[2];
-        CHK(fine_residual_norms(h, f, g, u, refine ? h->ulo : nullptr, h->res64,
-                                (refine && !inner_f64(prec)) ? h->fe32_fine : nullptr, nrm));
+        CHK(fine_residual_norms(h, f, g, u, refine ? h->ulo : nullptr, h->res64, nrm));
         rn = nrm[o.norm];
         if (!std::isfinite(nrm[1]) || !std::isfinite(rn)) {
             status = MGWR_ENONFINITE;
@@ -670,16 +752,25 @@ int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol
             fail(MGWR_EDIVERGED, "residual grew from %g to %g", r0, rn);
             break;
         }
-        if (it > 0 && o.stall > 0 && rn > o.stall * prev) { status = MGWR_STAGNATED; break; }
+        // Stagnation: a cycle that does not reduce the residual by the factor
+        // `stall`.  Near the rounding floor (below 1e-6 r0) one such cycle
+        // ends the solve; above it three in a row do (a refinement step may
+        // raise the residual once while it removes the smooth error).
+        if (it > 0 && o.stall > 0 && rn > o.stall * prev) {
+            ++slow;
+            if (rn < 1e-6 * r0 || slow >= 3) { status = MGWR_STAGNATED; break; }
+        } else {
+            slow = 0;
+        }
         if (it >= o.maxit) { status = MGWR_NOT_CONVERGED; break; }
         prev = rn;
         if (!refine) {
             CHK(cycle(h, Hp, (int)h->lv.size() - 1));
         } else {
             Level &L = h->lv.back();
-            HIPCHK(launch_fill(Hi.f64, h->M, L.P, nullptr, L.e, h->stream));
+            HIPCHK(launch_fill(h->M, L.P, nullptr, L.e, h->stream));
             CHK(cycle(h, Hi, (int)h->lv.size() - 1));
-            HIPCHK(launch_dd_update(n, Hi.f64, L.e, u, h->ulo, h->stream));
+            HIPCHK(launch_dd_update(n, L.e, u, h->ulo, h->stream));
         }
     }
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -706,28 +797,25 @@ int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int
     const ToepCoef *coef = which < 0 ? &h->tm : &h->lv[which].inv;
     GemmArgs a;
     a.M = h->M; a.P = P; a.K = h->M; a.off = 0; a.coef = coef; a.epi = EPI_STORE;
-    if (inner_f64(precision)) {
-        a.mode = GM_F64; a.B = B; a.ldb = ldb; a.ea.out = C; a.ea.ldo = ldc;
-        HIPCHK(launch_toep_gemm(a, h->stream));
+    a.ea.out = C; a.ea.ldo = ldc;
+    if (precision == MGWR_FP64 || precision == MGWR_FP64_REFINED) {
+        a.mode = GM_F64; a.B = B; a.ldb = ldb;
+        CHK(run_gemm(h, a, which));
         return MGWR_OK;
     }
-    // FP32 / BF16x3: go through float copies (test path; allocates)
+    // FP32 / split-BF16 operands are built from a contiguous FP64 copy (test
+    // path; allocates temporaries)
     std::vector<void *> tmp;
-    auto cleanup = [&]() { hipStreamSynchronize(h->stream); free_list(tmp); };
-    float *b32 = nullptr, *c32 = nullptr;
     long n = (long)h->M * P;
     int rc = [&]() -> int {
-        CHK(dmalloc(h, tmp, (void **)&b32, sizeof(float) * n));
-        CHK(dmalloc(h, tmp, (void **)&c32, sizeof(float) * n));
-        // B -> contiguous FP64 copy -> float (the norm kernel's cast output)
         double *bd = nullptr;
         CHK(dmalloc(h, tmp, (void **)&bd, sizeof(double) * n));
         HIPCHK(hipMemcpy2DAsync(bd, sizeof(double) * P, B, sizeof(double) * ldb, sizeof(double) * P, h->M,
                                 hipMemcpyDeviceToDevice, h->stream));
-        int nblk;
-        HIPCHK(launch_norm_partials(n, bd, b32, h->partials, &nblk, h->stream));
-        a.ea.out = c32; a.ea.ldo = P;
         if (precision == MGWR_MIXED_FP32) {
+            float *b32 = nullptr;
+            CHK(dmalloc(h, tmp, (void **)&b32, sizeof(float) * n));
+            HIPCHK(launch_operand(1, h->M, h->Mpad, P, bd, b32, nullptr, P, h->stream));
             a.mode = GM_F32; a.B = b32; a.ldb = P;
         } else {
             long ldp = (P + 127) / 128 * 128;
@@ -735,19 +823,52 @@ int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int
             size_t bytes = sizeof(uint16_t) * (size_t)h->Mpad * ldp;
             CHK(dmalloc(h, tmp, (void **)&hi, bytes));
             CHK(dmalloc(h, tmp, (void **)&lo, bytes));
-            HIPCHK(launch_split_bf16(h->M, h->Mpad, P, b32, hi, lo, ldp, h->stream));
+            HIPCHK(launch_operand(2, h->M, h->Mpad, P, bd, hi, lo, ldp, h->stream));
             a.mode = GM_BF16X3; a.Bhi = hi; a.Blo = lo; a.ldb = ldp;
         }
-        HIPCHK(launch_toep_gemm(a, h->stream));
-        // c32 -> C (double): reuse dd_update on a zeroed C
-        HIPCHK(hipMemsetAsync(bd, 0, sizeof(double) * n, h->stream));
-        HIPCHK(launch_dd_update(n, 0, c32, bd, nullptr, h->stream));
-        HIPCHK(hipMemcpy2DAsync(C, sizeof(double) * ldc, bd, sizeof(double) * P, sizeof(double) * P, h->M,
-                                hipMemcpyDeviceToDevice, h->stream));
+        CHK(run_gemm(h, a, which));
         return MGWR_OK;
     }();
-    cleanup();
+    hipStreamSynchronize(h->stream);
+    free_list(tmp);
     return rc;
+}
+
+int mgwr_profile_enable(mgwr_t h, int on)
+{
+    if (!h) return fail(MGWR_EINVAL, "NULL handle");
+    CHK(set_device(h));
+    CHK(resolve_profile(h));
+    if (on) h->records.clear();
+    h->prof = on != 0;
+    return MGWR_OK;
+}
+
+int mgwr_profile_count(mgwr_t h)
+{
+    if (!h) return fail(MGWR_EINVAL, "NULL handle");
+    CHK(set_device(h));
+    CHK(resolve_profile(h));
+    return (int)h->records.size();
+}
+
+int mgwr_profile_get(mgwr_t h, int i, mgwr_kernel_record *rec)
+{
+    if (!h || !rec) return fail(MGWR_EINVAL, "NULL argument");
+    CHK(resolve_profile(h));
+    if (i < 0 || i >= (int)h->records.size()) return fail(MGWR_EINVAL, "record %d out of range", i);
+    *rec = h->records[i];
+    return MGWR_OK;
+}
+
+const char *mgwr_kernel_name(int kernel)
+{
+    static thread_local std::string name;
+    int mode = kernel >> 4, epi = (kernel >> 1) & 7, narrow = kernel & 1;
+    if (mode == GM_BF16X3) name = "k_toep_bf16x3<" + std::to_string(epi) + ">";
+    else name = std::string(narrow ? "k_toep_narrow<" : "k_toep_wide<") + std::to_string(mode) + ", " +
+                std::to_string(epi) + ">";
+    return name.c_str();
 }
 
 // ---------------------------------------------------------------------------

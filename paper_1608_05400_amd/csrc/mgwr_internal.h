@@ -1,5 +1,10 @@
 // Internal interfaces of the MGWR library: device data layouts and the
 // kernel launchers the host runtime (mgwr_capi.cpp) drives.
+//
+// All grid functions (iterates, right-hand sides, residuals) are FP64 in HBM,
+// time-major [M][P].  Only the operands of the Toeplitz products may be held
+// in lower precision (FP32 panels, or split-BF16 hi/lo panels in the k8-packed
+// layout [Mpad/8][ld][8]).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
@@ -29,23 +34,26 @@ struct ToepCoef {
 // Epilogues of the Toeplitz product acc[i][p] = sum_k t[off + i - k] B[k][p].
 enum EpiKind {
     EPI_STORE = 0,    // out[i][p] = acc
-    EPI_SCATTER = 1,  // out[i][colour_point(p)] = acc      (smoother: new colour values)
-    EPI_RESID = 2,    // out[i][p] = F + cd*g - acc - A_h U  (residual)
-    EPI_RESID_DD = 3, // same with U = hi + lo, stencil in double-double (FP64 only)
-    EPI_SUB = 4       // out[i][p] -= acc                    (D&C history update)
+    EPI_SCATTER = 1,  // U[i][colour_point(p)] = acc                     (smoother, full product)
+    EPI_SMOOTH = 2,   // U[i][pt] = diag * b + acc, b = F + cd g + nbr(U)/h^2 recomputed in FP64,
+                      // pt = colour_point(p)                              (smoother, history product)
+    EPI_RESID = 3,    // out[i][p] = F + cd g - diag * U - acc - A_h U      (residual)
+    EPI_RESID_DD = 4, // same with U = hi + lo, stencil in double-double
+    EPI_SUB = 5       // out[i][p] -= acc                                   (D&C history update)
 };
 
 struct EpiArgs {
-    void *out = nullptr;       // storage type S of the mode (double for F64, float otherwise)
+    double *out = nullptr;     // output (EPI_STORE/RESID/SUB) or the iterate U (SCATTER/SMOOTH)
     long ldo = 0;
     int dims = 1, n = 1, colour = 0;   // grid of the level (points per dim) and colour
-    const void *F = nullptr;   // [M][ld] rhs of the level (type S)
-    const void *U = nullptr;   // [M][ld] iterate of the level (type S)
+    const double *F = nullptr;         // [M][ld] right-hand side of the level
+    const double *U = nullptr;         // [M][ld] iterate of the level (RESID)
     const double *ulo = nullptr;       // low part of U (EPI_RESID_DD)
     const double *cd = nullptr;        // c d_{m+1}, m = 0..M-1 (g term), may be null
     const double *g = nullptr;         // [P] initial condition, may be null
-    long ld = 0;               // leading dimension of F, U (= points of the level)
-    double ih2 = 0.0;          // 1 / h^2
+    long ld = 0;                       // leading dimension of F, U (= points of the level)
+    double ih2 = 0.0;                  // 1 / h^2
+    double diag = 0.0;                 // t[0] when the product holds only the history part
 };
 
 struct GemmArgs {
@@ -55,8 +63,8 @@ struct GemmArgs {
     int K = 0;         // rows of B
     int off = 0;       // coefficient index s = off + i - k
     const ToepCoef *coef = nullptr;
-    const void *B = nullptr;   // F64: double [K][ldb]; F32: float [K][ldb];
-    const void *Bhi = nullptr; // BF16X3: uint16 k8-packed [K/8][ldb][8]
+    const void *B = nullptr;   // F64: double [K][ldb]; F32: float [K][ldb]
+    const void *Bhi = nullptr; // BF16X3: uint16 k8-packed [Kpad/8][ldb][8]
     const void *Blo = nullptr;
     long ldb = 0;
     int epi = EPI_STORE;
@@ -87,31 +95,28 @@ __host__ __device__ inline int colour_count(int dims, int n, int colour)
 // ---- launchers (all asynchronous on `s`) ----
 hipError_t launch_toep_gemm(const GemmArgs &a, hipStream_t s);
 
-// panel[k][j] = F[k][pt] + cd[k] g[pt] + (sum of neighbours of pt in U)[k] * ih2,
-// pt = colour_point(j); S = double (f64) or float; packed: write bf16 hi/lo
-// k8-packed [Mpad/8][ldp][8] instead of a plain [M][ldp] panel.
-hipError_t launch_rhs_panel(int f64, int packed, int dims, int n, int colour, int M, int Mpad,
-                            const void *F, const void *U, const double *cd, const double *g,
-                            double ih2, void *panel, void *panel_lo, long ldp, hipStream_t s);
-// Split a float array [M][P] into bf16 hi/lo k8-packed [Mpad/8][ldp][8].
-hipError_t launch_split_bf16(int M, int Mpad, int P, const float *X, uint16_t *hi, uint16_t *lo,
-                             long ldp, hipStream_t s);
-// Scatter a plain panel X[M][ldx] into the colour points of U (type S).
-hipError_t launch_scatter(int f64, int dims, int n, int colour, int M, const void *X, long ldx,
-                          void *U, hipStream_t s);
-hipError_t launch_restrict(int f64, int dims, int nf, int M, const void *rf, void *rc, hipStream_t s);
-hipError_t launch_prolong_add(int f64, int dims, int nc, int M, const void *ec, void *uf,
-                              hipStream_t s);
-// u[k][p] = g ? g[p] : 0 (S = double or float), count = M * P
-hipError_t launch_fill(int f64, long M, long P, const double *g, void *u, hipStream_t s);
-// Block partials of {max |x|, sum x^2} for x double[n]; if out32 != null also
-// writes float(x) there.  partials: [nblk][2]; returns nblk via *nblk.
-hipError_t launch_norm_partials(long n, const double *x, float *out32, double *partials,
-                                int *nblk, hipStream_t s);
+// Right-hand side of a colour half-sweep, b = F + cd g + (neighbour sum of U)/h^2
+// at the points of the colour, as the B operand of the smoother's product:
+// fmt 0: FP64 panel [M][ldp]; 1: FP32 panel [M][ldp]; 2: split-BF16 k8-packed
+// [Mpad/8][ldp][8] (hi into panel, lo into panel_lo; zero for k >= M, j >= Pc).
+hipError_t launch_rhs_panel(int fmt, int dims, int n, int colour, int M, int Mpad, const double *F,
+                            const double *U, const double *cd, const double *g, double ih2,
+                            void *panel, void *panel_lo, long ldp, hipStream_t s);
+// X [M][P] FP64 -> FP32 copy [M][P] (fmt 1) or split-BF16 k8-packed (fmt 2).
+hipError_t launch_operand(int fmt, int M, int Mpad, int P, const double *X, void *out,
+                          void *out_lo, long ldp, hipStream_t s);
+hipError_t launch_restrict(int dims, int nf, int M, const double *rf, double *rc, hipStream_t s);
+hipError_t launch_prolong_add(int dims, int nc, int M, const double *ec, double *uf, hipStream_t s);
+// u[k][p] = g ? g[p] : 0
+hipError_t launch_fill(long M, long P, const double *g, double *u, hipStream_t s);
+// Block partials of {max |x|, sum x^2}; partials: [nblk][2]; returns nblk.
+hipError_t launch_norm_partials(long n, const double *x, double *partials, int *nblk,
+                                hipStream_t s);
 hipError_t launch_norm_final(int nblk, const double *partials, double *out2, hipStream_t s);
-// (hi, lo) += e; e double or float; lo may be null (plain FP64 add).
-hipError_t launch_dd_update(long n, int e_f64, const void *e, double *hi, double *lo,
-                            hipStream_t s);
+// (hi, lo) += e (double-double); lo == nullptr: hi += e.
+hipError_t launch_dd_update(long n, const double *e, double *hi, double *lo, hipStream_t s);
+// FP32 -> FP64 copy.
+hipError_t launch_widen(long n, const float *x, double *y, hipStream_t s);
 // Fill one coefficient table (fp32 copy and bf16 fragment table) from d64.
 hipError_t launch_build_coef(ToepCoef &c, hipStream_t s);
 int norm_partial_blocks(long n);

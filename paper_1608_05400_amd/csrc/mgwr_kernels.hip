@@ -89,35 +89,40 @@ __device__ inline void stencil_dd(const double *H, const double *Lo, int dims, i
 
 // ---------------------------------------------------------------------------
 // Epilogue of the Toeplitz products, element (i, p) with product value acc.
-template <typename S, int EPI>
+// All grid functions are FP64.
+template <int EPI>
 __device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
 {
     if constexpr (EPI == EPI_STORE) {
-        ((S *)e.out)[(long)i * e.ldo + p] = (S)acc;
+        e.out[(long)i * e.ldo + p] = acc;
     } else if constexpr (EPI == EPI_SUB) {
-        S *o = (S *)e.out + (long)i * e.ldo + p;
-        *o = (S)((double)*o - acc);
+        double *o = e.out + (long)i * e.ldo + p;
+        *o = *o - acc;
     } else if constexpr (EPI == EPI_SCATTER) {
-        ((S *)e.out)[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = (S)acc;
+        e.out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = acc;
+    } else if constexpr (EPI == EPI_SMOOTH) {
+        // x = t0 b + (history product); b rebuilt from F and the other colour
+        // of U, which this half-sweep does not write.
+        const int pt = colour_point(e.dims, e.n, e.colour, p);
+        const double *Ui = e.out + (long)i * e.ld;
+        double b = e.F[(long)i * e.ld + pt] + nbr_sum(Ui, e.dims, e.n, pt) * e.ih2;
+        if (e.g) b += e.cd[i] * e.g[pt];
+        e.out[(long)i * e.ldo + pt] = e.diag * b + acc;
     } else if constexpr (EPI == EPI_RESID) {
-        const S *U = (const S *)e.U + (long)i * e.ld;
-        double rhs = (double)((const S *)e.F)[(long)i * e.ld + p];
+        const double *U = e.U + (long)i * e.ld;
+        double rhs = e.F[(long)i * e.ld + p];
         if (e.g) rhs += e.cd[i] * e.g[p];
-        double st = (e.dims == 1 ? 2.0 : 4.0) * (double)U[p] - nbr_sum(U, e.dims, e.n, p);
-        if constexpr (sizeof(S) == 4) {
-            float r = (float)rhs - (float)acc - (float)st * (float)e.ih2;
-            ((S *)e.out)[(long)i * e.ldo + p] = (S)r;
-        } else {
-            ((S *)e.out)[(long)i * e.ldo + p] = (S)(rhs - acc - st * e.ih2);
-        }
+        double u = U[p];
+        double st = (e.dims == 1 ? 2.0 : 4.0) * u - nbr_sum(U, e.dims, e.n, p);
+        e.out[(long)i * e.ldo + p] = rhs - e.diag * u - acc - st * e.ih2;
     } else if constexpr (EPI == EPI_RESID_DD) {
-        const double *H = (const double *)e.U + (long)i * e.ld;
+        const double *H = e.U + (long)i * e.ld;
         const double *Lo = e.ulo + (long)i * e.ld;
-        double rhs = ((const double *)e.F)[(long)i * e.ld + p];
+        double rhs = e.F[(long)i * e.ld + p];
         if (e.g) rhs += e.cd[i] * e.g[p];
         double shi, slo;
         stencil_dd(H, Lo, e.dims, e.n, p, shi, slo);
-        ((double *)e.out)[(long)i * e.ldo + p] = ((rhs - acc) - shi * e.ih2) - slo * e.ih2;
+        e.out[(long)i * e.ldo + p] = ((rhs - acc) - shi * e.ih2) - slo * e.ih2;
     }
 }
 
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(256) void k_toep_wide(KP kp)
             for (int v = 0; v < 4; ++v) {
                 int i = i0 + wm * 64 + 16 * x + T::crow(lane, v);
                 int p = p0 + wn * 32 + 16 * y + (lane & 15);
-                if (i < kp.M && p < kp.P) epi_apply<S, EPI>(kp.ea, i, p, (double)acc[x][y][v]);
+                if (i < kp.M && p < kp.P) epi_apply<EPI>(kp.ea, i, p, (double)acc[x][y][v]);
             }
 }
 
@@ -299,7 +304,7 @@ __global__ __launch_bounds__(256) void k_toep_narrow(KP kp)
         int row = e / NBN, col = e % NBN;
         double sum = (double)red[0][e] + (double)red[1][e] + (double)red[2][e] + (double)red[3][e];
         int i = i0 + row, p = p0 + col;
-        if (i < kp.M && p < kp.P) epi_apply<S, EPI>(kp.ea, i, p, sum);
+        if (i < kp.M && p < kp.P) epi_apply<EPI>(kp.ea, i, p, sum);
     }
 }
 
@@ -398,7 +403,7 @@ __global__ __launch_bounds__(256) void k_toep_bf16x3(KP kp)
             for (int v = 0; v < 4; ++v) {
                 int i = i0 + wm * 64 + 16 * x + 4 * (lane >> 4) + v;
                 int p = p0 + wn * 64 + 16 * y + (lane & 15);
-                if (i < kp.M && p < kp.P) epi_apply<float, EPI>(kp.ea, i, p, (double)acc[x][y][v]);
+                if (i < kp.M && p < kp.P) epi_apply<EPI>(kp.ea, i, p, (double)acc[x][y][v]);
             }
 }
 
@@ -428,6 +433,7 @@ static hipError_t launch_mode(const GemmArgs &a, KP &kp, hipStream_t s)
     switch (a.epi) {
     case EPI_STORE: return launch_mode_epi<MODE, EPI_STORE>(a, kp, s);
     case EPI_SCATTER: return launch_mode_epi<MODE, EPI_SCATTER>(a, kp, s);
+    case EPI_SMOOTH: return launch_mode_epi<MODE, EPI_SMOOTH>(a, kp, s);
     case EPI_RESID: return launch_mode_epi<MODE, EPI_RESID>(a, kp, s);
     case EPI_SUB: return launch_mode_epi<MODE, EPI_SUB>(a, kp, s);
     case EPI_RESID_DD:
@@ -457,10 +463,11 @@ hipError_t launch_toep_gemm(const GemmArgs &a, hipStream_t s)
 // ---------------------------------------------------------------------------
 // Colour right-hand side of the smoother (Section 3, eq. red-black; Section 6,
 // eq. red-black_2d): b = f + c d g + (neighbour sum) / h^2 at the points of
-// one colour, gathered into a dense panel.
+// one colour, gathered into a dense panel (the B operand of the product).
 template <typename S>
-__global__ void k_rhs_panel(int dims, int n, int colour, int M, int Pc, const S *F, const S *U,
-                            const double *cd, const double *g, double ih2, S *panel, long ldp)
+__global__ void k_rhs_panel(int dims, int n, int colour, int M, int Pc, const double *F,
+                            const double *U, const double *cd, const double *g, double ih2, S *panel,
+                            long ldp)
 {
     long P = (dims == 1) ? n : (long)n * n;
     long total = (long)M * Pc;
@@ -468,90 +475,92 @@ __global__ void k_rhs_panel(int dims, int n, int colour, int M, int Pc, const S 
          e += (long)gridDim.x * blockDim.x) {
         int k = (int)(e / Pc), j = (int)(e - (long)k * Pc);
         int pt = colour_point(dims, n, colour, j);
-        const S *Uk = U + (long)k * P;
-        double b = (double)F[(long)k * P + pt] + nbr_sum(Uk, dims, n, pt) * ih2;
+        const double *Uk = U + (long)k * P;
+        double b = F[(long)k * P + pt] + nbr_sum(Uk, dims, n, pt) * ih2;
         if (g) b += cd[k] * g[pt];
         panel[(long)k * ldp + j] = (S)b;
     }
 }
 
-// Same, written as split BF16 hi/lo in the k8-packed layout [Mpad/8][ldp][8]
-// (zero outside k < M, j < Pc).  One thread builds the 8 time rows of a column.
+__device__ inline void store_split8(const float *b, uint16_t *hi, uint16_t *lo, long e)
+{
+    uint16_t h8[8], l8[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        uint16_t hb = f2bf(b[q]);
+        h8[q] = hb;
+        l8[q] = f2bf(b[q] - bf2f(hb));
+    }
+    uint4 vh, vl;
+    vh.x = h8[0] | ((uint32_t)h8[1] << 16); vh.y = h8[2] | ((uint32_t)h8[3] << 16);
+    vh.z = h8[4] | ((uint32_t)h8[5] << 16); vh.w = h8[6] | ((uint32_t)h8[7] << 16);
+    vl.x = l8[0] | ((uint32_t)l8[1] << 16); vl.y = l8[2] | ((uint32_t)l8[3] << 16);
+    vl.z = l8[4] | ((uint32_t)l8[5] << 16); vl.w = l8[6] | ((uint32_t)l8[7] << 16);
+    ((uint4 *)hi)[e] = vh;
+    ((uint4 *)lo)[e] = vl;
+}
+
+// Same right-hand side as split BF16 hi/lo in the k8-packed layout
+// [Mpad/8][ldp][8] (zero outside k < M, j < Pc).  One thread builds the 8
+// time rows of one column.
 __global__ void k_rhs_panel_packed(int dims, int n, int colour, int M, int Mpad, int Pc,
-                                   const float *F, const float *U, double ih2, uint16_t *hi,
-                                   uint16_t *lo, long ldp)
+                                   const double *F, const double *U, const double *cd,
+                                   const double *g, double ih2, uint16_t *hi, uint16_t *lo, long ldp)
 {
     long P = (dims == 1) ? n : (long)n * n;
     long total = (long)(Mpad / 8) * ldp;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
         int kg = (int)(e / ldp), j = (int)(e - (long)kg * ldp);
-        uint16_t h8[8], l8[8];
+        float b8[8];
         int pt = (j < Pc) ? colour_point(dims, n, colour, j) : 0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             int k = kg * 8 + q;
-            float b = 0.0f;
+            double b = 0.0;
             if (k < M && j < Pc) {
-                const float *Uk = U + (long)k * P;
-                b = F[(long)k * P + pt] + (float)(nbr_sum(Uk, dims, n, pt) * ih2);
+                const double *Uk = U + (long)k * P;
+                b = F[(long)k * P + pt] + nbr_sum(Uk, dims, n, pt) * ih2;
+                if (g) b += cd[k] * g[pt];
             }
-            uint16_t hb = f2bf(b);
-            h8[q] = hb;
-            l8[q] = f2bf(b - bf2f(hb));
+            b8[q] = (float)b;
         }
-        uint4 vh, vl;
-        vh.x = h8[0] | ((uint32_t)h8[1] << 16); vh.y = h8[2] | ((uint32_t)h8[3] << 16);
-        vh.z = h8[4] | ((uint32_t)h8[5] << 16); vh.w = h8[6] | ((uint32_t)h8[7] << 16);
-        vl.x = l8[0] | ((uint32_t)l8[1] << 16); vl.y = l8[2] | ((uint32_t)l8[3] << 16);
-        vl.z = l8[4] | ((uint32_t)l8[5] << 16); vl.w = l8[6] | ((uint32_t)l8[7] << 16);
-        ((uint4 *)hi)[e] = vh;
-        ((uint4 *)lo)[e] = vl;
+        store_split8(b8, hi, lo, e);
     }
 }
 
-__global__ void k_split_bf16(int M, int Mpad, int P, const float *X, uint16_t *hi, uint16_t *lo,
+__global__ void k_split_bf16(int M, int Mpad, int P, const double *X, uint16_t *hi, uint16_t *lo,
                              long ldp)
 {
     long total = (long)(Mpad / 8) * ldp;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
         int kg = (int)(e / ldp), j = (int)(e - (long)kg * ldp);
-        uint16_t h8[8], l8[8];
+        float b8[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             int k = kg * 8 + q;
-            float b = (k < M && j < P) ? X[(long)k * P + j] : 0.0f;
-            uint16_t hb = f2bf(b);
-            h8[q] = hb;
-            l8[q] = f2bf(b - bf2f(hb));
+            b8[q] = (k < M && j < P) ? (float)X[(long)k * P + j] : 0.0f;
         }
-        uint4 vh, vl;
-        vh.x = h8[0] | ((uint32_t)h8[1] << 16); vh.y = h8[2] | ((uint32_t)h8[3] << 16);
-        vh.z = h8[4] | ((uint32_t)h8[5] << 16); vh.w = h8[6] | ((uint32_t)h8[7] << 16);
-        vl.x = l8[0] | ((uint32_t)l8[1] << 16); vl.y = l8[2] | ((uint32_t)l8[3] << 16);
-        vl.z = l8[4] | ((uint32_t)l8[5] << 16); vl.w = l8[6] | ((uint32_t)l8[7] << 16);
-        ((uint4 *)hi)[e] = vh;
-        ((uint4 *)lo)[e] = vl;
+        store_split8(b8, hi, lo, e);
     }
 }
 
-template <typename S>
-__global__ void k_scatter(int dims, int n, int colour, int M, int Pc, const S *X, long ldx, S *U)
+__global__ void k_narrow_f32(long n, const double *x, float *y)
 {
-    long P = (dims == 1) ? n : (long)n * n;
-    long total = (long)M * Pc;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        int k = (int)(e / Pc), j = (int)(e - (long)k * Pc);
-        U[(long)k * P + colour_point(dims, n, colour, j)] = X[(long)k * ldx + j];
-    }
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+
+__global__ void k_widen(long n, const float *x, double *y)
+{
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
 }
 
 // Full weighting (Section 3; Section 6): coarse node J on fine node 2J,
 // weights [1 2 1]/4 (1D) and their tensor product /16 (2D).
-template <typename S>
-__global__ void k_restrict(int dims, int nf, int M, const S *rf, S *rc)
+__global__ void k_restrict(int dims, int nf, int M, const double *rf, double *rc)
 {
     int nc = (nf - 1) / 2;
     long Pc = (dims == 1) ? nc : (long)nc * nc;
@@ -561,33 +570,30 @@ __global__ void k_restrict(int dims, int nf, int M, const S *rf, S *rc)
          e += (long)gridDim.x * blockDim.x) {
         int k = (int)(e / Pc);
         long q = e - (long)k * Pc;
-        const S *r = rf + (long)k * Pf;
+        const double *r = rf + (long)k * Pf;
         double v;
         if (dims == 1) {
             int x = 2 * (int)q + 1;
-            v = 0.25 * ((double)r[x - 1] + 2.0 * (double)r[x] + (double)r[x + 1]);
+            v = 0.25 * (r[x - 1] + 2.0 * r[x] + r[x + 1]);
         } else {
             int I = (int)(q % nc), J = (int)(q / nc);
             int x = 2 * I + 1, y = 2 * J + 1;
-            const S *r0 = r + (long)(y - 1) * nf, *r1 = r + (long)y * nf, *r2 = r + (long)(y + 1) * nf;
-            v = ((double)r0[x - 1] + 2.0 * (double)r0[x] + (double)r0[x + 1]
-                 + 2.0 * ((double)r1[x - 1] + 2.0 * (double)r1[x] + (double)r1[x + 1])
-                 + (double)r2[x - 1] + 2.0 * (double)r2[x] + (double)r2[x + 1]) * (1.0 / 16.0);
+            const double *r0 = r + (long)(y - 1) * nf, *r1 = r + (long)y * nf, *r2 = r + (long)(y + 1) * nf;
+            v = (r0[x - 1] + 2.0 * r0[x] + r0[x + 1] + 2.0 * (r1[x - 1] + 2.0 * r1[x] + r1[x + 1])
+                 + r2[x - 1] + 2.0 * r2[x] + r2[x + 1]) * (1.0 / 16.0);
         }
-        rc[e] = (S)v;
+        rc[e] = v;
     }
 }
 
 // Linear / bilinear interpolation of the coarse correction, added to the fine
 // iterate (Section 3; Section 6); coarse values on the boundary are zero.
-template <typename S>
-__device__ inline double coarse_at(const S *e, int nc, int X)  // X: 1-based coarse index
+__device__ inline double coarse_at(const double *e, int nc, int X)  // X: 1-based coarse index
 {
-    return (X >= 1 && X <= nc) ? (double)e[X - 1] : 0.0;
+    return (X >= 1 && X <= nc) ? e[X - 1] : 0.0;
 }
 
-template <typename S>
-__global__ void k_prolong_add(int dims, int nc, int M, const S *ec, S *uf)
+__global__ void k_prolong_add(int dims, int nc, int M, const double *ec, double *uf)
 {
     int nf = 2 * nc + 1;
     long Pc = (dims == 1) ? nc : (long)nc * nc;
@@ -597,7 +603,7 @@ __global__ void k_prolong_add(int dims, int nc, int M, const S *ec, S *uf)
          e += (long)gridDim.x * blockDim.x) {
         int k = (int)(e / Pf);
         long p = e - (long)k * Pf;
-        const S *c = ec + (long)k * Pc;
+        const double *c = ec + (long)k * Pc;
         double v;
         if (dims == 1) {
             int nn = (int)p + 1;   // paper numbering
@@ -606,21 +612,20 @@ __global__ void k_prolong_add(int dims, int nc, int M, const S *ec, S *uf)
             int nn = (int)(p % nf) + 1, ll = (int)(p / nf) + 1;
             int xa = nn / 2, xb = (nn + 1) / 2, ya = ll / 2, yb = (ll + 1) / 2;
             auto at = [&](int X, int Y) -> double {
-                return (X >= 1 && X <= nc && Y >= 1 && Y <= nc) ? (double)c[(long)(Y - 1) * nc + (X - 1)] : 0.0;
+                return (X >= 1 && X <= nc && Y >= 1 && Y <= nc) ? c[(long)(Y - 1) * nc + (X - 1)] : 0.0;
             };
             v = 0.25 * (at(xa, ya) + at(xb, ya) + at(xa, yb) + at(xb, yb));
         }
-        uf[e] = (S)((double)uf[e] + v);
+        uf[e] += v;
     }
 }
 
-template <typename S>
-__global__ void k_fill(long M, long P, const double *g, S *u)
+__global__ void k_fill(long M, long P, const double *g, double *u)
 {
     long total = M * P;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
          e += (long)gridDim.x * blockDim.x) {
-        u[e] = g ? (S)g[e % P] : (S)0;
+        u[e] = g ? g[e % P] : 0.0;
     }
 }
 
@@ -634,8 +639,7 @@ int norm_partial_blocks(long n)
     return (int)b;
 }
 
-__global__ __launch_bounds__(kNormThreads) void k_norm_partials(long n, const double *x, float *out32,
-                                                                double *partials)
+__global__ __launch_bounds__(kNormThreads) void k_norm_partials(long n, const double *x, double *partials)
 {
     __shared__ double smax[kNormThreads], ssum[kNormThreads];
     long per = (n + gridDim.x - 1) / gridDim.x;
@@ -646,7 +650,6 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_partials(long n, const do
         double a = fabs(v);
         mx = (a > mx || a != a) ? a : mx;   // keeps a NaN once seen
         sq += v * v;
-        if (out32) out32[e] = (float)v;
     }
     smax[threadIdx.x] = mx;
     ssum[threadIdx.x] = sq;
@@ -695,12 +698,11 @@ __global__ __launch_bounds__(kNormThreads) void k_norm_final(int nblk, const dou
 
 // (hi, lo) <- (hi, lo) + e as a renormalised double-double (TwoSum, then
 // fast renormalisation); with lo == nullptr a plain FP64 add.
-template <typename E>
-__global__ void k_dd_update(long n, const E *e, double *hi, double *lo)
+__global__ void k_dd_update(long n, const double *e, double *hi, double *lo)
 {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
          i += (long)gridDim.x * blockDim.x) {
-        double d = (double)e[i];
+        double d = e[i];
         if (!lo) {
             hi[i] += d;
             continue;
@@ -742,88 +744,72 @@ static inline dim3 grid_for(long total, int threads = 256)
     return dim3((unsigned)b);
 }
 
-hipError_t launch_rhs_panel(int f64, int packed, int dims, int n, int colour, int M, int Mpad,
-                            const void *F, const void *U, const double *cd, const double *g,
-                            double ih2, void *panel, void *panel_lo, long ldp, hipStream_t s)
+hipError_t launch_rhs_panel(int fmt, int dims, int n, int colour, int M, int Mpad, const double *F,
+                            const double *U, const double *cd, const double *g, double ih2,
+                            void *panel, void *panel_lo, long ldp, hipStream_t s)
 {
     int Pc = colour_count(dims, n, colour);
-    if (packed) {
+    if (fmt == 2) {
         long total = (long)(Mpad / 8) * ldp;
         hipLaunchKernelGGL(k_rhs_panel_packed, grid_for(total), dim3(256), 0, s, dims, n, colour, M, Mpad,
-                           Pc, (const float *)F, (const float *)U, ih2, (uint16_t *)panel,
-                           (uint16_t *)panel_lo, ldp);
-    } else if (f64) {
+                           Pc, F, U, cd, g, ih2, (uint16_t *)panel, (uint16_t *)panel_lo, ldp);
+    } else if (fmt == 0) {
         hipLaunchKernelGGL(k_rhs_panel<double>, grid_for((long)M * Pc), dim3(256), 0, s, dims, n, colour,
-                           M, Pc, (const double *)F, (const double *)U, cd, g, ih2, (double *)panel, ldp);
+                           M, Pc, F, U, cd, g, ih2, (double *)panel, ldp);
     } else {
         hipLaunchKernelGGL(k_rhs_panel<float>, grid_for((long)M * Pc), dim3(256), 0, s, dims, n, colour,
-                           M, Pc, (const float *)F, (const float *)U, cd, g, ih2, (float *)panel, ldp);
+                           M, Pc, F, U, cd, g, ih2, (float *)panel, ldp);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_split_bf16(int M, int Mpad, int P, const float *X, uint16_t *hi, uint16_t *lo,
-                             long ldp, hipStream_t s)
+hipError_t launch_operand(int fmt, int M, int Mpad, int P, const double *X, void *out, void *out_lo,
+                          long ldp, hipStream_t s)
 {
-    long total = (long)(Mpad / 8) * ldp;
-    hipLaunchKernelGGL(k_split_bf16, grid_for(total), dim3(256), 0, s, M, Mpad, P, X, hi, lo, ldp);
+    if (fmt == 2) {
+        long total = (long)(Mpad / 8) * ldp;
+        hipLaunchKernelGGL(k_split_bf16, grid_for(total), dim3(256), 0, s, M, Mpad, P, X, (uint16_t *)out,
+                           (uint16_t *)out_lo, ldp);
+    } else {
+        long n = (long)M * P;
+        hipLaunchKernelGGL(k_narrow_f32, grid_for(n), dim3(256), 0, s, n, X, (float *)out);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(int f64, int dims, int n, int colour, int M, const void *X, long ldx,
-                          void *U, hipStream_t s)
+hipError_t launch_widen(long n, const float *x, double *y, hipStream_t s)
 {
-    int Pc = colour_count(dims, n, colour);
-    if (f64)
-        hipLaunchKernelGGL(k_scatter<double>, grid_for((long)M * Pc), dim3(256), 0, s, dims, n, colour, M,
-                           Pc, (const double *)X, ldx, (double *)U);
-    else
-        hipLaunchKernelGGL(k_scatter<float>, grid_for((long)M * Pc), dim3(256), 0, s, dims, n, colour, M,
-                           Pc, (const float *)X, ldx, (float *)U);
+    hipLaunchKernelGGL(k_widen, grid_for(n), dim3(256), 0, s, n, x, y);
     return hipGetLastError();
 }
 
-hipError_t launch_restrict(int f64, int dims, int nf, int M, const void *rf, void *rc, hipStream_t s)
+hipError_t launch_restrict(int dims, int nf, int M, const double *rf, double *rc, hipStream_t s)
 {
     int nc = (nf - 1) / 2;
     long total = (long)M * ((dims == 1) ? nc : (long)nc * nc);
-    if (f64)
-        hipLaunchKernelGGL(k_restrict<double>, grid_for(total), dim3(256), 0, s, dims, nf, M,
-                           (const double *)rf, (double *)rc);
-    else
-        hipLaunchKernelGGL(k_restrict<float>, grid_for(total), dim3(256), 0, s, dims, nf, M,
-                           (const float *)rf, (float *)rc);
+    hipLaunchKernelGGL(k_restrict, grid_for(total), dim3(256), 0, s, dims, nf, M, rf, rc);
     return hipGetLastError();
 }
 
-hipError_t launch_prolong_add(int f64, int dims, int nc, int M, const void *ec, void *uf, hipStream_t s)
+hipError_t launch_prolong_add(int dims, int nc, int M, const double *ec, double *uf, hipStream_t s)
 {
     int nf = 2 * nc + 1;
     long total = (long)M * ((dims == 1) ? nf : (long)nf * nf);
-    if (f64)
-        hipLaunchKernelGGL(k_prolong_add<double>, grid_for(total), dim3(256), 0, s, dims, nc, M,
-                           (const double *)ec, (double *)uf);
-    else
-        hipLaunchKernelGGL(k_prolong_add<float>, grid_for(total), dim3(256), 0, s, dims, nc, M,
-                           (const float *)ec, (float *)uf);
+    hipLaunchKernelGGL(k_prolong_add, grid_for(total), dim3(256), 0, s, dims, nc, M, ec, uf);
     return hipGetLastError();
 }
 
-hipError_t launch_fill(int f64, long M, long P, const double *g, void *u, hipStream_t s)
+hipError_t launch_fill(long M, long P, const double *g, double *u, hipStream_t s)
 {
-    if (f64)
-        hipLaunchKernelGGL(k_fill<double>, grid_for(M * P), dim3(256), 0, s, M, P, g, (double *)u);
-    else
-        hipLaunchKernelGGL(k_fill<float>, grid_for(M * P), dim3(256), 0, s, M, P, g, (float *)u);
+    hipLaunchKernelGGL(k_fill, grid_for(M * P), dim3(256), 0, s, M, P, g, u);
     return hipGetLastError();
 }
 
-hipError_t launch_norm_partials(long n, const double *x, float *out32, double *partials, int *nblk,
-                                hipStream_t s)
+hipError_t launch_norm_partials(long n, const double *x, double *partials, int *nblk, hipStream_t s)
 {
     int b = norm_partial_blocks(n);
     *nblk = b;
-    hipLaunchKernelGGL(k_norm_partials, dim3(b), dim3(kNormThreads), 0, s, n, x, out32, partials);
+    hipLaunchKernelGGL(k_norm_partials, dim3(b), dim3(kNormThreads), 0, s, n, x, partials);
     return hipGetLastError();
 }
 
@@ -833,12 +819,9 @@ hipError_t launch_norm_final(int nblk, const double *partials, double *out2, hip
     return hipGetLastError();
 }
 
-hipError_t launch_dd_update(long n, int e_f64, const void *e, double *hi, double *lo, hipStream_t s)
+hipError_t launch_dd_update(long n, const double *e, double *hi, double *lo, hipStream_t s)
 {
-    if (e_f64)
-        hipLaunchKernelGGL(k_dd_update<double>, grid_for(n), dim3(256), 0, s, n, (const double *)e, hi, lo);
-    else
-        hipLaunchKernelGGL(k_dd_update<float>, grid_for(n), dim3(256), 0, s, n, (const float *)e, hi, lo);
+    hipLaunchKernelGGL(k_dd_update, grid_for(n), dim3(256), 0, s, n, e, hi, lo);
     return hipGetLastError();
 }
 

@@ -282,3 +282,81 @@ def test_runs_are_bitwise_deterministic(B):
             s.solve(dev(f), U, g=dev(g), tol=1e-12)
             outs.append(host(U))
     assert np.array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------------------
+# full workload sizes, in the launch configuration the benchmark times:
+# sampled outputs against the exact discrete solution from the oracle's modal
+# solve (every workload forcing is a finite sum of sine modes)
+
+def _sampled_modal_error(w, U, npts=3000, seed=5):
+    rng = np.random.default_rng(seed)
+    v = oracle.modal_solve(w.dims, w.N, w.M, w.alpha, w.kx, w.s, ky=w.ky)
+    m = rng.integers(1, w.M + 1, size=npts)
+    m[:50] = w.M
+    m[50:100] = 1
+    n = rng.integers(1, w.N + 1, size=npts)
+    l = rng.integers(1, w.N + 1, size=npts) if w.dims == 2 else np.ones(npts, dtype=np.int64)
+    ref = oracle.modal_eval(w.dims, w.N, w.M, w.kx, v, np.stack([m, n, l], 1), ky=w.ky)
+    if w.dims == 1:
+        idx = (m - 1) * w.N + (n - 1)
+    else:
+        idx = (m - 1) * w.N * w.N + (l - 1) * w.N + (n - 1)
+    got = U.reshape(-1)[torch.from_numpy(idx).cuda()].cpu().numpy()
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-8), ("fp64r", 1e-10), ("fp32", 1e-8)])
+@pytest.mark.parametrize("alpha", [0.3, 0.7])
+def test_config2_full_size(B, prec, tol, alpha):
+    """1D, N = 4095, M = 16384: reaches a 1e-10 relative FP64 residual."""
+    w = W.config2(alpha)
+    f = w.forcing_torch("cuda").contiguous()
+    with B.Solver(w.N, w.M, w.alpha, precision=prec) as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(f, U, tol=1e-10)
+        torch.cuda.synchronize()
+        err = _sampled_modal_error(w, U)
+    assert info["status"] == "ok" and info["relres"] <= 1e-10, info
+    assert err <= tol, err
+
+
+def test_config2_plain_fp64_reaches_its_floor(B):
+    """Plain FP64 stops at the rounding floor of the residual for h = 1/4096
+    (about 2e-9 relative in the max norm) with the solution accurate."""
+    w = W.config2(0.3)
+    f = w.forcing_torch("cuda").contiguous()
+    with B.Solver(w.N, w.M, w.alpha, precision="fp64") as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(f, U, tol=1e-10)
+        torch.cuda.synchronize()
+        err = _sampled_modal_error(w, U)
+    assert info["status"] in ("ok", "stagnated") and info["relres"] <= 1e-8, info
+    assert err <= 1e-10, err
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-8), ("fp64", 1e-10)])
+def test_config3_2d_full_size(B, prec, tol):
+    """2D, N = 511, M = 2048, alpha = 0.4, u = t^2 sin(pi x) sin(pi y)."""
+    w = W.manufactured_2d(511, 2048, 0.4)
+    f = w.forcing_torch("cuda").contiguous()
+    with B.Solver(w.N, w.M, w.alpha, dims=2, precision=prec) as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(f, U, tol=1e-10)
+        torch.cuda.synchronize()
+        err = _sampled_modal_error(w, U)
+    assert info["status"] in ("ok", "stagnated") and info["relres"] <= 1e-9, info
+    assert err <= tol, err
+
+
+def test_config5_2d_nonsmooth_full_size(B):
+    """2D, N = 1023, M = 1024, alpha = 0.3, u = (t^a + t^2) sin sin, split-BF16."""
+    w = W.nonsmooth_2d(1023, 1024, 0.3)
+    f = w.forcing_torch("cuda").contiguous()
+    with B.Solver(w.N, w.M, w.alpha, dims=2, precision="bf16x3") as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(f, U, tol=1e-10)
+        torch.cuda.synchronize()
+        err = _sampled_modal_error(w, U)
+    assert info["status"] == "ok" and info["relres"] <= 1e-10, info
+    assert err <= 1e-8, err
