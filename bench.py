@@ -151,6 +151,22 @@ def roofline_of(records, steps):
     return out
 
 
+def kernel_table(records, steps):
+    """Per (kernel, level, columns) totals of the product launches."""
+    by = {}
+    for r in records:
+        k = (r["name"], r["level"], r["P"])
+        d = by.setdefault(k, [0, 0.0, 0.0])
+        d[0] += 1
+        d[1] += r["ms"]
+        d[2] += r["flops"]
+    rows = []
+    for (name, lev, P), (n, ms, fl) in sorted(by.items(), key=lambda kv: -kv[1][1]):
+        rows.append({"kernel": name, "level": lev, "P": P, "launches_per_step": n / steps,
+                     "ms_per_step": ms / steps, "avg_ms": ms / n, "tflops": fl / (ms * 1e-3) / 1e12})
+    return rows
+
+
 def cpu_baseline(w, seconds):
     """The oracle's direct time-stepping solve on a bounded sample: the first
     Ms time levels of the full problem; its cost is dominated by the O(N M^2)
@@ -209,6 +225,10 @@ def main():
                              not args.no_check, profile=True)
         results[mode] = res
         rooflines[mode] = roofline_of(recs, steps)
+        for row in kernel_table(recs, steps)[:14]:
+            log(f"  {row['kernel']:22s} lvl {row['level']:2d} P {row['P']:6d}: "
+                f"{row['launches_per_step']:5.1f}/step {row['ms_per_step']:8.2f} ms/step "
+                f"avg {row['avg_ms']:7.3f} ms {row['tflops']:7.1f} TFLOP/s")
         log(f"{mode}: {res['value']:.4g} unknowns/s, {res['ms_per_step']:.1f} ms/step, "
             f"iters {res['iters']}, relres {res['relres']}, err {res.get('err_vs_oracle')}")
 

@@ -180,10 +180,12 @@ int mgwr_batch_destroy(mgwr_batch_t b);
  * With profiling on, every Toeplitz-product launch of the handle is bracketed
  * by HIP events recorded on the handle's stream.  kernel identifies the
  * kernel instantiation: (mode << 4) | (epilogue << 1) | narrow, with mode 0 =
- * FP64, 1 = FP32, 2 = split-BF16; epilogue 0 = store, 1 = colour scatter
- * (smoother), 2 = residual, 3 = residual with double-double iterate, 4 =
- * subtract; narrow = 1 for the few-column variant.  flops counts the
- * multiply-adds of the product that are not structurally zero, times 2. */
+ * FP64, 1 = FP32, 2 = split-BF16; epilogue 0 = store (residual product), 1 = colour scatter
+ * (smoother, whole line solve), 2 = colour scatter-add (smoother, history
+ * part), 3 = subtract; narrow = 1 for the few-column variant.
+ * flops counts the multiply-adds of the product that are not structurally
+ * zero, times 2.  ms covers the product and, when its K range is split over
+ * several blocks, the reduce kernel that applies its epilogue. */
 typedef struct {
     int kernel, level, M, P, K;
     double flops;  /* algorithmic flops of the launch                        */

@@ -64,7 +64,7 @@ int fail(int code, const char *fmt, ...)
 
 // Split-BF16 products are used only where a launch has at least this many
 // columns; narrower levels (the coarse grids) run their products in FP32.
-constexpr int kBf16MinCols = 256;
+constexpr int kBf16MinCols = 128;
 
 // ---------------------------------------------------------------------------
 // L1 weights (Section 2, L1 scheme; Section 5, r_i).  d_k for k >= 2 as
@@ -171,6 +171,8 @@ struct mgwr_ctx {
     uint16_t *pk_hi = nullptr, *pk_lo = nullptr;
     long pk_ld = 0;
     double *partials = nullptr, *norms_dev = nullptr, *norms_host = nullptr;
+    void *part = nullptr;            // split-K partials of the Toeplitz products
+    size_t part_cap = 0;
     // per-launch timing of the Toeplitz products
     bool prof = false;
     struct Pending { hipEvent_t a, b; mgwr_kernel_record rec; };
@@ -205,7 +207,7 @@ void free_list(std::vector<void *> &list)
 int upload_coef(mgwr_ctx *h, ToepCoef &c, const std::vector<double> &v)
 {
     c.n = (int)v.size();
-    c.nq = (c.n + 15) / 16 + 2 * kQOff;
+    c.nq = (c.n + 15) / 16 + 4 * kQOff;
     CHK(dmalloc(h, h->alloc, (void **)&c.d64, sizeof(double) * c.n));
     CHK(dmalloc(h, h->alloc, (void **)&c.d32, sizeof(float) * c.n));
     CHK(dmalloc(h, h->alloc, (void **)&c.fhi, sizeof(uint16_t) * 512 * (size_t)c.nq));
@@ -260,8 +262,11 @@ int resolve_profile(mgwr_ctx *h)
     return MGWR_OK;
 }
 
-int run_gemm(mgwr_ctx *h, const GemmArgs &a, int level)
+int run_gemm(mgwr_ctx *h, const GemmArgs &a_in, int level)
 {
+    GemmArgs a = a_in;
+    a.part = h->part;
+    a.part_cap = h->part_cap;
     if (!h->prof) {
         HIPCHK(launch_toep_gemm(a, h->stream));
         return MGWR_OK;
@@ -360,8 +365,8 @@ int level_mode(const Hier &H, long cols)
 // One half-sweep: every point of `colour` on level `lev` gets the solution of
 // (T_M + sigma I) x = b along its time line, as one Toeplitz product with the
 // precomputed inverse column.  In FP64 the product is the whole solve; in
-// FP32 / split-BF16 the product covers the strictly lower (history) part and
-// the epilogue adds lambda_0 b with b rebuilt in FP64.
+// FP32 / split-BF16 the right-hand-side kernel writes lambda_0 b (FP64) into
+// the colour's points and the product adds the strictly lower (history) part.
 int half_sweep(mgwr_t h, const Hier &H, int lev, int colour)
 {
     Level &L = h->lv[lev];
@@ -373,21 +378,19 @@ int half_sweep(mgwr_t h, const Hier &H, int lev, int colour)
     a.mode = level_mode(H, Pc);
     a.M = h->M; a.P = Pc; a.K = h->M; a.off = 0;
     a.ea.out = H.u[lev]; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n; a.ea.colour = colour;
-    a.ea.F = H.f[lev]; a.ea.ld = L.P; a.ea.ih2 = L.ih2; a.ea.cd = h->cd; a.ea.g = g;
     if (a.mode == GM_F64) {
         HIPCHK(launch_rhs_panel(0, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
-                                h->panel64, nullptr, Pc, h->stream));
+                                0.0, h->panel64, nullptr, Pc, h->stream));
         a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
     } else if (a.mode == GM_F32) {
         HIPCHK(launch_rhs_panel(1, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
-                                h->panel32, nullptr, Pc, h->stream));
-        a.coef = &L.inv_h; a.epi = EPI_SMOOTH; a.ea.diag = L.lam0; a.B = h->panel32; a.ldb = Pc;
+                                L.lam0, h->panel32, nullptr, Pc, h->stream));
+        a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.B = h->panel32; a.ldb = Pc;
     } else {
         long ldp = (Pc + 127) / 128 * 128;
         HIPCHK(launch_rhs_panel(2, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
-                                h->pk_hi, h->pk_lo, ldp, h->stream));
-        a.coef = &L.inv_h; a.epi = EPI_SMOOTH; a.ea.diag = L.lam0;
-        a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+                                L.lam0, h->pk_hi, h->pk_lo, ldp, h->stream));
+        a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
     }
     CHK(run_gemm(h, a, lev));
     return MGWR_OK;
@@ -401,7 +404,9 @@ int sweep(mgwr_t h, const Hier &H, int lev)
     return MGWR_OK;
 }
 
-// out = f + c d g - T_M u - A_h u on level lev.
+// out = f + c d g - T_M u - A_h u on level lev: the Toeplitz product (all
+// of T_M u in FP64, its history part otherwise) stored into out, then the
+// stencil part and the diagonal r_1 u applied by a bandwidth kernel.
 int level_residual(mgwr_t h, const Hier &H, int lev, double *out)
 {
     Level &L = h->lv[lev];
@@ -409,21 +414,22 @@ int level_residual(mgwr_t h, const Hier &H, int lev, double *out)
     GemmArgs a;
     a.mode = level_mode(H, L.P);
     a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0;
-    a.epi = EPI_RESID;
+    a.epi = EPI_STORE;
     a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
-    a.ea.F = H.f[lev]; a.ea.U = H.u[lev]; a.ea.ld = L.P; a.ea.ih2 = L.ih2;
-    a.ea.cd = h->cd; a.ea.g = fine ? H.g : nullptr;
+    const double diag = (a.mode == GM_F64) ? 0.0 : h->c;
     if (a.mode == GM_F64) {
         a.coef = &h->tm; a.B = H.u[lev]; a.ldb = L.P;
     } else if (a.mode == GM_F32) {
         HIPCHK(launch_operand(1, h->M, h->Mpad, (int)L.P, H.u[lev], h->op32, nullptr, L.P, h->stream));
-        a.coef = &h->tm_h; a.ea.diag = h->c; a.B = h->op32; a.ldb = L.P;
+        a.coef = &h->tm_h; a.B = h->op32; a.ldb = L.P;
     } else {
         long ldp = (L.P + 127) / 128 * 128;
         HIPCHK(launch_operand(2, h->M, h->Mpad, (int)L.P, H.u[lev], h->pk_hi, h->pk_lo, ldp, h->stream));
-        a.coef = &h->tm_h; a.ea.diag = h->c; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+        a.coef = &h->tm_h; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
     }
     CHK(run_gemm(h, a, lev));
+    HIPCHK(launch_resid_post(h->dims, L.n, h->M, H.f[lev], H.u[lev], nullptr, h->cd, fine ? H.g : nullptr,
+                             L.ih2, diag, out, h->stream));
     return MGWR_OK;
 }
 
@@ -461,18 +467,25 @@ Hier inner_hier(mgwr_t h)
 
 // FP64 residual of the finest level into res (double-double iterate when lo
 // != nullptr) and its norms (host, synchronising).
+// cold: u is the initial iterate g at every time level (lo zero).  Then
+// T_M u = c d_m g exactly (the rows of T_M sum to c d_m), so the product is
+// replaced by writing c d_m g.
 int fine_residual_norms(mgwr_t h, const double *f, const double *g, const double *u, const double *lo,
-                        double *res, double norms[2])
+                        double *res, double norms[2], bool cold = false)
 {
     Level &L = h->lv.back();
-    GemmArgs a;
-    a.mode = GM_F64;
-    a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm;
-    a.epi = lo ? EPI_RESID_DD : EPI_RESID;
-    a.ea.out = res; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
-    a.ea.F = f; a.ea.U = u; a.ea.ulo = lo; a.ea.ld = L.P; a.ea.ih2 = L.ih2; a.ea.cd = h->cd; a.ea.g = g;
-    a.B = u; a.ldb = L.P;
-    CHK(run_gemm(h, a, (int)h->lv.size() - 1));
+    if (cold) {
+        HIPCHK(launch_scaled_fill(h->M, L.P, h->cd, g, res, h->stream));
+    } else {
+        GemmArgs a;
+        a.mode = GM_F64;
+        a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm;
+        a.epi = EPI_STORE;
+        a.ea.out = res; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
+        a.B = u; a.ldb = L.P;
+        CHK(run_gemm(h, a, (int)h->lv.size() - 1));
+    }
+    HIPCHK(launch_resid_post(h->dims, L.n, h->M, f, u, lo, h->cd, g, L.ih2, 0.0, res, h->stream));
     if (norms) {
         int nblk = 0;
         HIPCHK(launch_norm_partials((long)h->M * L.P, res, h->partials, &nblk, h->stream));
@@ -619,6 +632,18 @@ int mgwr_create_ex(int N, int M, double alpha, double T, int dims, const mgwr_op
         CHK(dmalloc(h, h->alloc, (void **)&h->panel64, sizeof(double) * M * h->maxPc));
         CHK(dmalloc(h, h->alloc, (void **)&h->ulo, sizeof(double) * M * Pf));
         CHK(dmalloc(h, h->alloc, (void **)&h->partials, sizeof(double) * 2 * 2048));
+        // split-K scratch: the largest any product of this hierarchy needs
+        size_t part = 0;
+        for (const Level &L : h->lv)
+            for (int mode = GM_F64; mode <= GM_BF16X3; ++mode) {
+                long cols[3] = {L.Pc[0], L.Pc[1], L.P};
+                for (long P : cols)
+                    if (P > 0) part = std::max(part, splitk_bytes(mode, M, (int)P, M, 0, M));
+            }
+        if (part > 0) {
+            CHK(dmalloc(h, h->alloc, &h->part, part));
+            h->part_cap = part;
+        }
         CHK(dmalloc(h, h->alloc, (void **)&h->norms_dev, sizeof(double) * 2));
         HIPCHK(hipHostMalloc((void **)&h->norms_host, 2 * sizeof(double), hipHostMallocDefault));
         CHK(alloc_inner(h, o.precision));
@@ -737,7 +762,8 @@ int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol
     int it = 0, slow = 0;
     for (;; ++it) {
         double nrm[2];
-        CHK(fine_residual_norms(h, f, g, u, refine ? h->ulo : nullptr, h->res64, nrm));
+        CHK(fine_residual_norms(h, f, g, u, refine ? h->ulo : nullptr, h->res64, nrm,
+                                it == 0 && !o.warm_start));
         rn = nrm[o.norm];
         if (!std::isfinite(nrm[1]) || !std::isfinite(rn)) {
             status = MGWR_ENONFINITE;

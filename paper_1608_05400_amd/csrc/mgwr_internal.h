@@ -32,28 +32,20 @@ struct ToepCoef {
 };
 
 // Epilogues of the Toeplitz product acc[i][p] = sum_k t[off + i - k] B[k][p].
+// They are kept light (one load and one store per element) so that the
+// product kernels keep their occupancy; the stencil parts of the residual
+// and of the smoother run in the bandwidth kernels before the product.
 enum EpiKind {
-    EPI_STORE = 0,    // out[i][p] = acc
-    EPI_SCATTER = 1,  // U[i][colour_point(p)] = acc                     (smoother, full product)
-    EPI_SMOOTH = 2,   // U[i][pt] = diag * b + acc, b = F + cd g + nbr(U)/h^2 recomputed in FP64,
-                      // pt = colour_point(p)                              (smoother, history product)
-    EPI_RESID = 3,    // out[i][p] = F + cd g - diag * U - acc - A_h U      (residual)
-    EPI_RESID_DD = 4, // same with U = hi + lo, stencil in double-double
-    EPI_SUB = 5       // out[i][p] -= acc                                   (D&C history update)
+    EPI_STORE = 0,       // out[i][p] = acc                        (residual product)
+    EPI_SCATTER = 1,     // out[i][colour_point(p)] = acc          (smoother, full product)
+    EPI_SCATTER_ADD = 2, // out[i][colour_point(p)] += acc         (smoother, history product)
+    EPI_SUB = 3          // out[i][p] -= acc                       (D&C history update)
 };
 
 struct EpiArgs {
-    double *out = nullptr;     // output (EPI_STORE/RESID/SUB) or the iterate U (SCATTER/SMOOTH)
+    double *out = nullptr;     // output (STORE/SUB) or the iterate U of the level (SCATTER*)
     long ldo = 0;
     int dims = 1, n = 1, colour = 0;   // grid of the level (points per dim) and colour
-    const double *F = nullptr;         // [M][ld] right-hand side of the level
-    const double *U = nullptr;         // [M][ld] iterate of the level (RESID)
-    const double *ulo = nullptr;       // low part of U (EPI_RESID_DD)
-    const double *cd = nullptr;        // c d_{m+1}, m = 0..M-1 (g term), may be null
-    const double *g = nullptr;         // [P] initial condition, may be null
-    long ld = 0;                       // leading dimension of F, U (= points of the level)
-    double ih2 = 0.0;                  // 1 / h^2
-    double diag = 0.0;                 // t[0] when the product holds only the history part
 };
 
 struct GemmArgs {
@@ -69,6 +61,8 @@ struct GemmArgs {
     long ldb = 0;
     int epi = EPI_STORE;
     EpiArgs ea;
+    void *part = nullptr;      // scratch for split-K partials
+    size_t part_cap = 0;       // its size in bytes (0: never split)
 };
 
 // Flat point index of the j-th point of a colour (0: n even / n + l even).
@@ -94,14 +88,24 @@ __host__ __device__ inline int colour_count(int dims, int n, int colour)
 
 // ---- launchers (all asynchronous on `s`) ----
 hipError_t launch_toep_gemm(const GemmArgs &a, hipStream_t s);
+// Scratch a product of this shape uses for split-K partials (0: not split).
+size_t splitk_bytes(int mode, int M, int P, int K, int off, int ncoef);
 
 // Right-hand side of a colour half-sweep, b = F + cd g + (neighbour sum of U)/h^2
 // at the points of the colour, as the B operand of the smoother's product:
 // fmt 0: FP64 panel [M][ldp]; 1: FP32 panel [M][ldp]; 2: split-BF16 k8-packed
 // [Mpad/8][ldp][8] (hi into panel, lo into panel_lo; zero for k >= M, j >= Pc).
+// If lam0 != 0 the kernel also writes lam0 * b into the colour's points of U
+// (the diagonal part of the line solve; the product then adds the history).
 hipError_t launch_rhs_panel(int fmt, int dims, int n, int colour, int M, int Mpad, const double *F,
-                            const double *U, const double *cd, const double *g, double ih2,
+                            double *U, const double *cd, const double *g, double ih2, double lam0,
                             void *panel, void *panel_lo, long ldp, hipStream_t s);
+// Residual from a Toeplitz product already in out (the history part, or all of
+// T_M U when diag = 0): out = (F + cd g - diag U - A_h U) - out, with A_h
+// applied to hi + lo by error-free transformations when lo != nullptr.
+hipError_t launch_resid_post(int dims, int n, int M, const double *F, const double *U, const double *lo,
+                             const double *cd, const double *g, double ih2, double diag, double *out,
+                             hipStream_t s);
 // X [M][P] FP64 -> FP32 copy [M][P] (fmt 1) or split-BF16 k8-packed (fmt 2).
 hipError_t launch_operand(int fmt, int M, int Mpad, int P, const double *X, void *out,
                           void *out_lo, long ldp, hipStream_t s);
@@ -109,6 +113,8 @@ hipError_t launch_restrict(int dims, int nf, int M, const double *rf, double *rc
 hipError_t launch_prolong_add(int dims, int nc, int M, const double *ec, double *uf, hipStream_t s);
 // u[k][p] = g ? g[p] : 0
 hipError_t launch_fill(long M, long P, const double *g, double *u, hipStream_t s);
+// u[k][p] = g ? cd[k] g[p] : 0
+hipError_t launch_scaled_fill(long M, long P, const double *cd, const double *g, double *u, hipStream_t s);
 // Block partials of {max |x|, sum x^2}; partials: [nblk][2]; returns nblk.
 hipError_t launch_norm_partials(long n, const double *x, double *partials, int *nblk,
                                 hipStream_t s);

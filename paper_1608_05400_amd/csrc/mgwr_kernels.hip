@@ -21,6 +21,10 @@
 // norms, precision updates) is bandwidth bound and written for coalescing.
 #include "mgwr_internal.h"
 
+#include <algorithm>
+#include <cstdlib>
+#include <type_traits>
+
 namespace mgwr {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -89,7 +93,6 @@ __device__ inline void stencil_dd(const double *H, const double *Lo, int dims, i
 
 // ---------------------------------------------------------------------------
 // Epilogue of the Toeplitz products, element (i, p) with product value acc.
-// All grid functions are FP64.
 template <int EPI>
 __device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
 {
@@ -100,29 +103,9 @@ __device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
         *o = *o - acc;
     } else if constexpr (EPI == EPI_SCATTER) {
         e.out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = acc;
-    } else if constexpr (EPI == EPI_SMOOTH) {
-        // x = t0 b + (history product); b rebuilt from F and the other colour
-        // of U, which this half-sweep does not write.
-        const int pt = colour_point(e.dims, e.n, e.colour, p);
-        const double *Ui = e.out + (long)i * e.ld;
-        double b = e.F[(long)i * e.ld + pt] + nbr_sum(Ui, e.dims, e.n, pt) * e.ih2;
-        if (e.g) b += e.cd[i] * e.g[pt];
-        e.out[(long)i * e.ldo + pt] = e.diag * b + acc;
-    } else if constexpr (EPI == EPI_RESID) {
-        const double *U = e.U + (long)i * e.ld;
-        double rhs = e.F[(long)i * e.ld + p];
-        if (e.g) rhs += e.cd[i] * e.g[p];
-        double u = U[p];
-        double st = (e.dims == 1 ? 2.0 : 4.0) * u - nbr_sum(U, e.dims, e.n, p);
-        e.out[(long)i * e.ldo + p] = rhs - e.diag * u - acc - st * e.ih2;
-    } else if constexpr (EPI == EPI_RESID_DD) {
-        const double *H = e.U + (long)i * e.ld;
-        const double *Lo = e.ulo + (long)i * e.ld;
-        double rhs = e.F[(long)i * e.ld + p];
-        if (e.g) rhs += e.cd[i] * e.g[p];
-        double shi, slo;
-        stencil_dd(H, Lo, e.dims, e.n, p, shi, slo);
-        e.out[(long)i * e.ldo + p] = ((rhs - acc) - shi * e.ih2) - slo * e.ih2;
+    } else if constexpr (EPI == EPI_SCATTER_ADD) {
+        double *o = e.out + (long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p);
+        *o = *o + acc;
     }
 }
 
@@ -130,13 +113,57 @@ __device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
 struct KP {
     int M, P, K, off, ncoef;
     int tiles_m, tiles_n;
+    int nsplit;                // K split factor (1: the product kernel applies the epilogue)
     const void *coef;          // double* or float* (F64/F32)
     const uint16_t *fhi, *flo; // fragment tables (BF16X3)
     const void *B;
     const uint16_t *Bhi, *Blo;
     long ldb;
+    void *part;                // split partials [nsplit][M][P] (double for F64, float otherwise)
     EpiArgs ea;
 };
+
+// Work item b -> (row tile, column tile, split).  Row tiles in decreasing
+// order (a causal product has the most work in its last rows, so the short
+// tiles fill the tail of the launch); the splits of one tile are consecutive.
+// With tiles_n a multiple of 8 the round-robin dispatch of blocks to the 8
+// XCDs keeps each column strip of B on one XCD's L2.
+struct Item {
+    int tm, tn, s;
+};
+__device__ inline Item item_of(const KP &kp, int b)
+{
+    Item it;
+    int t = b / kp.nsplit;
+    it.s = b - t * kp.nsplit;
+    it.tm = kp.tiles_m - 1 - t / kp.tiles_n;
+    it.tn = t - (t / kp.tiles_n) * kp.tiles_n;
+    return it;
+}
+
+// K range of the row tile [i0, i0 + BM): rows k with a nonzero coefficient
+// t[off + i - k], in steps of BK from kbase; split s takes steps [ks0, ks1).
+template <int BM, int BK>
+__device__ inline void k_range(const KP &kp, int i0, int s, int &kbase, int &ks0, int &ks1)
+{
+    int kend = min(kp.K, i0 + BM + kp.off);
+    int kbeg = max(0, kp.off + i0 - kp.ncoef + 1);
+    kbeg = (kbeg / BK) * BK;
+    int nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
+    kbase = kbeg;
+    ks0 = (int)((long)nk * s / kp.nsplit);
+    ks1 = (int)((long)nk * (s + 1) / kp.nsplit);
+}
+
+// Result of element (i, p): the epilogue, or a partial sum when K is split.
+template <int EPI, typename PT>
+__device__ inline void emit(const KP &kp, int s, int i, int p, double acc)
+{
+    if (kp.nsplit > 1)
+        ((PT *)kp.part)[((long)s * kp.M + i) * kp.P + p] = (PT)acc;
+    else
+        epi_apply<EPI>(kp.ea, i, p, acc);
+}
 
 template <int MODE> struct Tr;
 template <> struct Tr<GM_F64> {
@@ -160,100 +187,121 @@ template <> struct Tr<GM_F32> {
 };
 
 // ---------------------------------------------------------------------------
-// Wide Toeplitz product: block tile 128 x 64, 4 waves in 2 x 2, wave tile
-// 64 x 32 (4 x 2 MFMA blocks of 16 x 16), K step 16, LDS double buffer.
-// Block order: largest row index first (causal products have the most work
-// there), so the short tiles fill the tail of the launch.
-constexpr int WBM = 128, WBN = 64, WBK = 16, WWIN = WBM + WBK;
+// Wide FP64 / FP32 Toeplitz product.  Block of 4 waves arranged WGM x WGN,
+// wave tile (16 FM) x (16 FN) of MFMA blocks; block tile BM x BN with
+// BM = 16 FM WGM, BN = 16 FN WGN; K step 16; LDS double buffer for the B tile
+// and the coefficient window (BM + BK - 1 values, from which every lane
+// gathers its A element t[off + i - k]).
+//   variant 0: 2 x 2 waves of 64 x 32   (block 128 x 64)
+//   variant 1: 4 x 1 waves of 64 x 64   (block 256 x 64)
+constexpr int WBK = 16, WBN = 64;
+template <int V> struct WideCfg;
+template <> struct WideCfg<0> { static constexpr int WGM = 2, WGN = 2, FM = 4, FN = 2; };
+template <> struct WideCfg<1> { static constexpr int WGM = 4, WGN = 1, FM = 4, FN = 4; };
+template <int V> constexpr int wide_bm() { return 16 * WideCfg<V>::FM * WideCfg<V>::WGM; }
 
-template <int MODE, int EPI>
+template <int MODE, int EPI, int V>
 __global__ __launch_bounds__(256) void k_toep_wide(KP kp)
 {
     using T = Tr<MODE>;
     using S = typename T::S;
     using acc_t = typename T::acc_t;
+    using C = WideCfg<V>;
+    constexpr int BM = wide_bm<V>(), WIN = BM + WBK;
+    static_assert(16 * C::FN * C::WGN == WBN, "block is 64 columns wide");
     __shared__ S Bs[2][WBK][WBN];
-    __shared__ S Ws[2][WWIN];
+    __shared__ S Ws[2][WIN];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int wm = wid >> 1, wn = wid & 1;
-    const int t = blockIdx.x;
-    const int tm = kp.tiles_m - 1 - t / kp.tiles_n, tn = t % kp.tiles_n;
-    const int i0 = tm * WBM, p0 = tn * WBN;
+    const int wm = wid / C::WGN, wn = wid % C::WGN;
+    const Item it = item_of(kp, blockIdx.x);
+    const int i0 = it.tm * BM, p0 = it.tn * WBN;
     const S *coef = (const S *)kp.coef;
     const S *B = (const S *)kp.B;
+    int kbase, ks0, ks1;
+    k_range<BM, WBK>(kp, i0, it.s, kbase, ks0, ks1);
+    const int nk = ks1 - ks0;
+    const int kstart = kbase + ks0 * WBK;
 
-    int kend = min(kp.K, i0 + WBM + kp.off);
-    int kbeg = max(0, kp.off + i0 - kp.ncoef + 1);
-    kbeg = (kbeg / WBK) * WBK;
-    const int nk = (kend > kbeg) ? (kend - kbeg + WBK - 1) / WBK : 0;
-
-    acc_t acc[4][2];
+    acc_t acc[C::FM][C::FN];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < C::FM; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
+        for (int y = 0; y < C::FN; ++y) acc[x][y] = acc_t{0, 0, 0, 0};
 
-    const int brow = tid >> 4, bc4 = (tid & 15) * 4;
+    // staging: a wave loads one 64-column row of the B tile per instruction
+    // (rows brow, brow + 4, brow + 8, brow + 12), fully coalesced for any ldb
+    const int brow = tid >> 6, bcol = tid & 63;
+    const bool colok = p0 + bcol < kp.P;
     S breg[4];
-    S wreg = 0;
-    auto gload = [&](int k0) {
-        int k = k0 + brow;
+    S wreg0 = 0, wreg1 = 0;
+    auto gload = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            int p = p0 + bc4 + j;
-            breg[j] = (k < kp.K && p < kp.P) ? B[(long)k * kp.ldb + p] : (S)0;
+            int k = k0 + brow + 4 * j;
+            breg[j] = (k < kp.K && colok) ? B[(long)k * kp.ldb + p0 + bcol] : (S)0;
         }
-        if (tid < WWIN) {
-            int s = kp.off + i0 - k0 - (WBK - 1) + tid;
-            wreg = (s >= 0 && s < kp.ncoef) ? coef[s] : (S)0;
+        const int s0 = kp.off + i0 - k0 - (WBK - 1);
+        if (tid < WIN) {
+            int s = s0 + tid;
+            wreg0 = (s >= 0 && s < kp.ncoef) ? coef[s] : (S)0;
+        }
+        if (tid + 256 < WIN) {
+            int s = s0 + tid + 256;
+            wreg1 = (s >= 0 && s < kp.ncoef) ? coef[s] : (S)0;
         }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) Bs[buf][brow][bc4 + j] = breg[j];
-        if (tid < WWIN) Ws[buf][tid] = wreg;
+        for (int j = 0; j < 4; ++j) Bs[buf][brow + 4 * j][bcol] = breg[j];
+        if (tid < WIN) Ws[buf][tid] = wreg0;
+        if (tid + 256 < WIN) Ws[buf][tid + 256] = wreg1;
     };
 
     if (nk > 0) {
-        gload(kbeg);
+        gload(kstart);
         sstore(0);
     }
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < nk) gload(kbeg + (kt + 1) * WBK);
+        if (kt + 1 < nk) gload(kstart + (kt + 1) * WBK);
 #pragma unroll
         for (int ks = 0; ks < WBK / 4; ++ks) {
             const int kr = 4 * ks + (lane >> 4);
-            S a[4], b[2];
+            S a[C::FM], b[C::FN];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) a[x] = Ws[buf][wm * 64 + 16 * x + (lane & 15) - kr + WBK - 1];
+            for (int x = 0; x < C::FM; ++x)
+                a[x] = Ws[buf][wm * 16 * C::FM + 16 * x + (lane & 15) - kr + WBK - 1];
 #pragma unroll
-            for (int y = 0; y < 2; ++y) b[y] = Bs[buf][kr][wn * 32 + 16 * y + (lane & 15)];
+            for (int y = 0; y < C::FN; ++y) b[y] = Bs[buf][kr][wn * 16 * C::FN + 16 * y + (lane & 15)];
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < C::FM; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y) acc[x][y] = T::mma(a[x], b[y], acc[x][y]);
+                for (int y = 0; y < C::FN; ++y) acc[x][y] = T::mma(a[x], b[y], acc[x][y]);
         }
         if (kt + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
     }
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < C::FM; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < C::FN; ++y) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int i = i0 + wm * 64 + 16 * x + T::crow(lane, v);
-                int p = p0 + wn * 32 + 16 * y + (lane & 15);
-                if (i < kp.M && p < kp.P) epi_apply<EPI>(kp.ea, i, p, (double)acc[x][y][v]);
+                int i = i0 + wm * 16 * C::FM + 16 * x + T::crow(lane, v);
+                int p = p0 + wn * 16 * C::FN + 16 * y + (lane & 15);
+                if (i < kp.M && p < kp.P) emit<EPI, S>(kp, it.s, i, p, (double)acc[x][y][v]);
             }
+            // keep the read-modify-write epilogues from holding every load at once
+            __builtin_amdgcn_sched_barrier(0);
+        }
 }
 
 // ---------------------------------------------------------------------------
 // Narrow Toeplitz product for levels with few columns (coarse grids): block
-// tile 64 x 16; the four waves split the K range (chunks of 16 rows taken
-// round-robin) and their partial tiles are summed in LDS in a fixed order.
+// tile 64 x 16; the four waves share the item's K range in chunks of 16 rows
+// taken round-robin, and their partial tiles are summed in LDS in a fixed
+// order.
 constexpr int NBM = 64, NBN = 16, NCH = 16;
 
 template <int MODE, int EPI>
@@ -264,23 +312,19 @@ __global__ __launch_bounds__(256) void k_toep_narrow(KP kp)
     using acc_t = typename T::acc_t;
     __shared__ S red[4][NBM * NBN];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int t = blockIdx.x;
-    const int tm = kp.tiles_m - 1 - t / kp.tiles_n, tn = t % kp.tiles_n;
-    const int i0 = tm * NBM, p0 = tn * NBN;
+    const Item it = item_of(kp, blockIdx.x);
+    const int i0 = it.tm * NBM, p0 = it.tn * NBN;
     const S *coef = (const S *)kp.coef;
     const S *B = (const S *)kp.B;
-
-    int kend = min(kp.K, i0 + NBM + kp.off);
-    int kbeg = max(0, kp.off + i0 - kp.ncoef + 1);
-    kbeg = (kbeg / NCH) * NCH;
-    const int nch = (kend > kbeg) ? (kend - kbeg + NCH - 1) / NCH : 0;
+    int kbase, ks0, ks1;
+    k_range<NBM, NCH>(kp, i0, it.s, kbase, ks0, ks1);
 
     acc_t acc[4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) acc[x] = acc_t{0, 0, 0, 0};
     const int pc = p0 + (lane & 15);
-    for (int c = wid; c < nch; c += 4) {
-        const int k0 = kbeg + c * NCH;
+    for (int c = ks0 + wid; c < ks1; c += 4) {
+        const int k0 = kbase + c * NCH;
 #pragma unroll
         for (int ks = 0; ks < NCH / 4; ++ks) {
             const int k = k0 + 4 * ks + (lane >> 4);
@@ -304,125 +348,284 @@ __global__ __launch_bounds__(256) void k_toep_narrow(KP kp)
         int row = e / NBN, col = e % NBN;
         double sum = (double)red[0][e] + (double)red[1][e] + (double)red[2][e] + (double)red[3][e];
         int i = i0 + row, p = p0 + col;
-        if (i < kp.M && p < kp.P) epi_apply<EPI>(kp.ea, i, p, sum);
+        if (i < kp.M && p < kp.P) emit<EPI, S>(kp, it.s, i, p, sum);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Split-BF16 Toeplitz product.  Block tile 128 x 128, 4 waves in 2 x 2, wave
-// tile 64 x 64 (4 x 4 blocks of 16 x 16), K step 32.  Per K step the block
-// stages 8 Toeplitz fragments (hi and lo, 16 KB) from the fragment table and
-// the B tile (hi and lo, k8-packed, 16 KB) into LDS (double buffered).
-// B must be k8-packed with rows padded to a multiple of 128 and columns to a
+// Split-BF16 Toeplitz product.  Block tile 256 x 128, 4 waves in 2 x 2, wave
+// tile 128 x 64 (8 x 4 blocks of 16 x 16, three v_mfma_f32_16x16x32_bf16 per
+// block and K step of 32: lo*hi + hi*lo + hi*hi, each pass over all 32
+// blocks so that an accumulator is reused only 32 MFMAs later).
+//   * A (Toeplitz) fragments come straight from the fragment table (L2
+//     resident) into registers.  The fragment of row block a at K step kt is
+//     q = Q0 + a - 2 kt, so from one K step to the next six of the eight
+//     stay in registers and only two new ones are loaded; they live in slot
+//     (a - 2 kt) mod 8, a compile-time index once the K loop is unrolled by 4.
+//   * B (k8-packed hi/lo, 16 KB per K step) goes global -> registers -> LDS
+//     with three LDS buffers: the tile of step kt + 2 is loaded two steps
+//     ahead (two register sets) and stored at the end of step kt, and the B
+//     fragments of step kt + 1 are read from LDS while step kt's MFMAs run.
+// B must be k8-packed with rows padded to a multiple of 256 and columns to a
 // multiple of 128, padding zero.
-constexpr int BBM = 128, BBN = 128, BBK = 32;
+constexpr int QBM = 256, QBN = 128, QBK = 32;
 
 __device__ inline v8bf as_bf8(uint4 v) { return __builtin_bit_cast(v8bf, v); }
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_toep_bf16x3(KP kp)
 {
-    __shared__ uint4 As[2][2][8][64];        // [buf][hi/lo][fragment][lane]
-    __shared__ uint4 Bs[2][2][4][BBN];       // [buf][hi/lo][k/8][column]
+    __shared__ uint4 Bs[3][2][4][QBN];   // [buffer][hi/lo][k/8][column]
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid >> 1, wn = wid & 1;
-    const int t = blockIdx.x;
-    const int tm = kp.tiles_m - 1 - t / kp.tiles_n, tn = t % kp.tiles_n;
-    const int i0 = tm * BBM, p0 = tn * BBN;
+    const Item it = item_of(kp, blockIdx.x);
+    const int i0 = it.tm * QBM, p0 = it.tn * QBN;
+    int kbase, ks0, ks1;
+    k_range<QBM, QBK>(kp, i0, it.s, kbase, ks0, ks1);
+    const int nk = ks1 - ks0;
+    const int kstart = kbase + ks0 * QBK;
+    const int iw = i0 + wm * 128;
+    const long Q0 = (kp.off + iw - kstart) / 16 + kQOff;   // fragment of row block 0 at K step 0
 
-    int kend = min(kp.K, i0 + BBM + kp.off);
-    int kbeg = max(0, kp.off + i0 - kp.ncoef + 1);
-    kbeg = (kbeg / BBK) * BBK;
-    const int nk = (kend > kbeg) ? (kend - kbeg + BBK - 1) / BBK : 0;
-
-    v4f acc[4][4];
+    v4f acc[8][4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = v4f{0, 0, 0, 0};
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
 
     const uint4 *fh = (const uint4 *)kp.fhi, *fl = (const uint4 *)kp.flo;
     const uint4 *bh = (const uint4 *)kp.Bhi, *bl = (const uint4 *)kp.Blo;
-    uint4 ra[4], rb[4];
-    auto gload = [&](int k0) {
-        const int q0 = (kp.off + i0 - k0) / 16 + kQOff;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int u = tid + 256 * r;
-            int hl = u >> 9, a = (u >> 6) & 7, ln = u & 63;
-            ra[r] = (hl ? fl : fh)[(long)(q0 + a) * 64 + ln];
-            int kg = (u >> 7) & 3, col = u & 127;
-            rb[r] = (hl ? bl : bh)[(long)(k0 / 8 + kg) * kp.ldb + p0 + col];
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int u = tid + 256 * r;
-            int hl = u >> 9;
-            As[buf][hl][(u >> 6) & 7][u & 63] = ra[r];
-            Bs[buf][hl][(u >> 7) & 3][u & 127] = rb[r];
-        }
-    };
+    const long ldb = kp.ldb;
+    uint4 Ah[8], Al[8];          // Toeplitz fragment slots
+    uint4 nh0, nl0, nh1, nl1;    // fragments of the next K step
+    // two register sets for B tiles in flight: this thread's share is hi and
+    // lo at rows k/8 = kr and kr + 2, column tc
+    uint4 r00, r01, r02, r03, r10, r11, r12, r13;
+    const int kr = tid >> 7, tc = tid & 127;
+    // B fragments of this and of the next K step (two sets)
+    v8bf fh0[4], fl0[4], fh1[4], fl1[4];
+    const int fcol = wn * 64 + (lane & 15), frow = lane >> 4;
+
+#define BF_GLOAD(R, KT)                                                                \
+    {                                                                                  \
+        const long rr = (kstart / 8) + 4L * (KT) + kr;                                 \
+        R##0 = bh[rr * ldb + p0 + tc];                                                 \
+        R##1 = bh[(rr + 2) * ldb + p0 + tc];                                           \
+        R##2 = bl[rr * ldb + p0 + tc];                                                 \
+        R##3 = bl[(rr + 2) * ldb + p0 + tc];                                           \
+    }
+#define BF_LSTORE(R, BUF)                                                              \
+    {                                                                                  \
+        Bs[BUF][0][kr][tc] = R##0;                                                     \
+        Bs[BUF][0][kr + 2][tc] = R##1;                                                 \
+        Bs[BUF][1][kr][tc] = R##2;                                                     \
+        Bs[BUF][1][kr + 2][tc] = R##3;                                                 \
+    }
+#define BF_FREAD(FH, FL, BUF)                                                          \
+    {                                                                                  \
+        _Pragma("unroll") for (int b = 0; b < 4; ++b)                                  \
+        {                                                                              \
+            FH[b] = as_bf8(Bs[BUF][0][frow][fcol + 16 * b]);                           \
+            FL[b] = as_bf8(Bs[BUF][1][frow][fcol + 16 * b]);                           \
+        }                                                                              \
+    }
+#define BF_PASS(AX, BX, S)                                                             \
+    _Pragma("unroll") for (int a = 0; a < 8; ++a)                                      \
+        _Pragma("unroll") for (int b = 0; b < 4; ++b)                                  \
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(                       \
+                as_bf8(AX[(a - 2 * (S)) & 7]), BX[b], acc[a][b], 0, 0, 0);
+// one K step; S = KT mod 4 (compile time) selects the fragment slots and the
+// register / fragment sets; the LDS buffer index is KT mod 3 (run time).  The
+// loads and stores of a step are unconditional (indices clamped to the last
+// step; a clamped store goes to the buffer no later step reads) so that the
+// compiler's wait counts stay exact and the two-step prefetch survives.
+#define BF_STEP(S, KT, RNEXT, RCUR, FHC, FLC, FHN, FLN)                                 \
+    {                                                                                  \
+        const int kt_ = (KT);                                                          \
+        {                                                                              \
+            const long q = Q0 - 2L * min(kt_ + 1, nk - 1);                             \
+            nh0 = fh[q * 64 + lane];                                                   \
+            nl0 = fl[q * 64 + lane];                                                   \
+            nh1 = fh[(q + 1) * 64 + lane];                                             \
+            nl1 = fl[(q + 1) * 64 + lane];                                             \
+        }                                                                              \
+        BF_GLOAD(RNEXT, min(kt_ + 3, nk - 1));                                         \
+        BF_FREAD(FHN, FLN, (kt_ + 1) % 3);                                             \
+        /* keep the loads above the MFMAs (the scheduler would sink them) */           \
+        __builtin_amdgcn_sched_barrier(0);                                             \
+        BF_PASS(Al, FHC, S)                                                            \
+        BF_PASS(Ah, FLC, S)                                                            \
+        BF_PASS(Ah, FHC, S)                                                            \
+        __builtin_amdgcn_sched_barrier(0);                                             \
+        BF_LSTORE(RCUR, (kt_ + 2) % 3);                                                \
+        Ah[(0 - 2 * ((S) + 1)) & 7] = nh0;                                             \
+        Al[(0 - 2 * ((S) + 1)) & 7] = nl0;                                             \
+        Ah[(1 - 2 * ((S) + 1)) & 7] = nh1;                                             \
+        Al[(1 - 2 * ((S) + 1)) & 7] = nl1;                                             \
+        __syncthreads();                                                               \
+    }
 
     if (nk > 0) {
-        gload(kbeg);
-        sstore(0);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            Ah[a] = fh[(Q0 + a) * 64 + lane];
+            Al[a] = fl[(Q0 + a) * 64 + lane];
+        }
+        BF_GLOAD(r0, 0);
+        BF_GLOAD(r1, min(1, nk - 1));
+        BF_LSTORE(r0, 0);
+        BF_LSTORE(r1, 1);
+        BF_GLOAD(r0, min(2, nk - 1));
     }
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) gload(kbeg + (kt + 1) * BBK);
-        v8bf ah[4], al[4], bhv[4], blv[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            ah[x] = as_bf8(As[buf][0][wm * 4 + x][lane]);
-            al[x] = as_bf8(As[buf][1][wm * 4 + x][lane]);
-        }
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-            bhv[y] = as_bf8(Bs[buf][0][lane >> 4][wn * 64 + 16 * y + (lane & 15)]);
-            blv[y] = as_bf8(Bs[buf][1][lane >> 4][wn * 64 + 16 * y + (lane & 15)]);
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], bhv[y], acc[x][y], 0, 0, 0);
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], blv[y], acc[x][y], 0, 0, 0);
-                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[x], bhv[y], acc[x][y], 0, 0, 0);
-            }
-        if (kt + 1 < nk) sstore(buf ^ 1);
-        __syncthreads();
+    if (nk > 0) BF_FREAD(fh0, fl0, 0);
+    // step kt: tile kt + 2 is in register set kt % 2, tile kt + 3 goes to the other
+    int kt = 0;
+    for (; kt + 4 <= nk; kt += 4) {
+        BF_STEP(0, kt, r1, r0, fh0, fl0, fh1, fl1);
+        BF_STEP(1, kt + 1, r0, r1, fh1, fl1, fh0, fl0);
+        BF_STEP(2, kt + 2, r1, r0, fh0, fl0, fh1, fl1);
+        BF_STEP(3, kt + 3, r0, r1, fh1, fl1, fh0, fl0);
     }
+    if (kt < nk) {
+        BF_STEP(0, kt, r1, r0, fh0, fl0, fh1, fl1);
+        if (kt + 1 < nk) {
+            BF_STEP(1, kt + 1, r0, r1, fh1, fl1, fh0, fl0);
+            if (kt + 2 < nk) BF_STEP(2, kt + 2, r1, r0, fh0, fl0, fh1, fl1);
+        }
+    }
+#undef BF_STEP
+#undef BF_PASS
+#undef BF_FREAD
+#undef BF_LSTORE
+#undef BF_GLOAD
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int i = i0 + wm * 64 + 16 * x + 4 * (lane >> 4) + v;
-                int p = p0 + wn * 64 + 16 * y + (lane & 15);
-                if (i < kp.M && p < kp.P) epi_apply<EPI>(kp.ea, i, p, (double)acc[x][y][v]);
+                int i = iw + 16 * a + 4 * (lane >> 4) + v;
+                int p = p0 + wn * 64 + 16 * b + (lane & 15);
+                if (i < kp.M && p < kp.P) emit<EPI, float>(kp, it.s, i, p, (double)acc[a][b][v]);
             }
 }
 
+// Sum of the split partials in a fixed order, then the epilogue.
+template <int EPI, typename PT>
+__global__ void k_splitk_reduce(KP kp)
+{
+    const long MP = (long)kp.M * kp.P;
+    const PT *part = (const PT *)kp.part;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < MP; e += (long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int s = 0; s < kp.nsplit; ++s) acc += (double)part[s * MP + e];
+        int i = (int)(e / kp.P), p = (int)(e - (long)i * kp.P);
+        epi_apply<EPI>(kp.ea, i, p, acc);
+    }
+}
+
 // ---------------------------------------------------------------------------
+// Launch geometry.  A launch with few tiles (coarse levels) would leave most
+// CUs idle while its last row tile walks the whole K range, so its K range
+// is split over several blocks and a reduce kernel applies the epilogue.
+struct Geo {
+    int BM, BN, BK, tiles_m, tiles_n, nsplit, variant;
+    size_t part_bytes;
+};
+
+// Wide-kernel variant per mode (0: 128 x 64 blocks, 1: 256 x 64 blocks,
+// -1: by launch size); the environment variable MGWR_WIDE_VARIANT
+// ("<fp64><fp32>", e.g. "10") fixes it for tuning runs.
+static int wide_variant(int mode)
+{
+    static int v[2] = {-2, -2};
+    if (v[0] == -2) {
+        v[0] = -1; v[1] = -1;   // -1: choose by launch size
+        const char *e = getenv("MGWR_WIDE_VARIANT");
+        if (e && e[0] >= '0' && e[0] <= '1') v[0] = e[0] - '0';
+        if (e && e[0] && e[1] >= '0' && e[1] <= '1') v[1] = e[1] - '0';
+    }
+    return v[mode == GM_F64 ? 0 : 1];
+}
+
+static Geo geometry(int mode, int M, int P, int K, int off, int ncoef, size_t part_cap)
+{
+    Geo g;
+    g.variant = 0;
+    if (mode == GM_BF16X3) { g.BM = QBM; g.BN = QBN; g.BK = QBK; }
+    else if (P <= 32) { g.BM = NBM; g.BN = NBN; g.BK = NCH; }
+    else {
+        // 256-row blocks help launches that are too small to fill the chip
+        // with 128-row blocks several times over
+        const long t0 = (long)((M + wide_bm<0>() - 1) / wide_bm<0>()) * ((P + WBN - 1) / WBN);
+        g.variant = wide_variant(mode);
+        if (g.variant < 0) g.variant = (t0 < 4096) ? 1 : 0;
+        g.BM = g.variant ? wide_bm<1>() : wide_bm<0>(); g.BN = WBN; g.BK = WBK;
+    }
+    g.tiles_m = (M + g.BM - 1) / g.BM;
+    g.tiles_n = (P + g.BN - 1) / g.BN;
+    const long T = (long)g.tiles_m * g.tiles_n;
+    // K steps of the longest row tile
+    int i0 = (g.tiles_m - 1) * g.BM;
+    int kend = std::min(K, i0 + g.BM + off);
+    int kbeg = std::max(0, off + i0 - ncoef + 1);
+    int nk = (kend > kbeg) ? (kend - kbeg + g.BK - 1) / g.BK : 0;
+    // target number of work items: the narrow kernel's items are short, so
+    // it takes more of them; MGWR_SPLIT_TARGET overrides it for tuning runs
+    static long tgt_env = -2;
+    if (tgt_env == -2) {
+        const char *e = getenv("MGWR_SPLIT_TARGET");
+        tgt_env = e ? atol(e) : -1;
+    }
+    const long target = tgt_env > 0 ? tgt_env : (g.BM == NBM) ? 8192 : (mode == GM_BF16X3) ? 1024 : 2048;
+    int ns = 1;
+    if (T < target) {
+        ns = (int)((target + T - 1) / T);
+        ns = std::min(ns, 64);
+        ns = std::min(ns, std::max(1, nk / 8));
+    }
+    const size_t esz = (mode == GM_F64) ? 8 : 4;
+    while (ns > 1 && (size_t)ns * M * P * esz > part_cap) --ns;
+    g.nsplit = ns;
+    g.part_bytes = ns > 1 ? (size_t)ns * M * P * esz : 0;
+    return g;
+}
+
+size_t splitk_bytes(int mode, int M, int P, int K, int off, int ncoef)
+{
+    return geometry(mode, M, P, K, off, ncoef, (size_t)-1).part_bytes;
+}
+
+static inline dim3 grid_for(long total, int threads = 256)
+{
+    long b = (total + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return dim3((unsigned)b);
+}
+
 template <int MODE, int EPI>
 static hipError_t launch_mode_epi(const GemmArgs &a, KP &kp, hipStream_t s)
 {
+    Geo g = geometry(MODE, a.M, a.P, a.K, a.off, a.coef->n, a.part ? a.part_cap : 0);
+    kp.tiles_m = g.tiles_m;
+    kp.tiles_n = g.tiles_n;
+    kp.nsplit = g.nsplit;
+    kp.part = a.part;
+    const unsigned blocks = (unsigned)((long)g.tiles_m * g.tiles_n * g.nsplit);
     if constexpr (MODE == GM_BF16X3) {
-        kp.tiles_m = (a.M + BBM - 1) / BBM;
-        kp.tiles_n = (a.P + BBN - 1) / BBN;
-        hipLaunchKernelGGL((k_toep_bf16x3<EPI>), dim3(kp.tiles_m * kp.tiles_n), dim3(256), 0, s, kp);
+        hipLaunchKernelGGL((k_toep_bf16x3<EPI>), dim3(blocks), dim3(256), 0, s, kp);
     } else if (a.P <= 32) {
-        kp.tiles_m = (a.M + NBM - 1) / NBM;
-        kp.tiles_n = (a.P + NBN - 1) / NBN;
-        hipLaunchKernelGGL((k_toep_narrow<MODE, EPI>), dim3(kp.tiles_m * kp.tiles_n), dim3(256), 0, s, kp);
+        hipLaunchKernelGGL((k_toep_narrow<MODE, EPI>), dim3(blocks), dim3(256), 0, s, kp);
+    } else if (g.variant == 1) {
+        hipLaunchKernelGGL((k_toep_wide<MODE, EPI, 1>), dim3(blocks), dim3(256), 0, s, kp);
     } else {
-        kp.tiles_m = (a.M + WBM - 1) / WBM;
-        kp.tiles_n = (a.P + WBN - 1) / WBN;
-        hipLaunchKernelGGL((k_toep_wide<MODE, EPI>), dim3(kp.tiles_m * kp.tiles_n), dim3(256), 0, s, kp);
+        hipLaunchKernelGGL((k_toep_wide<MODE, EPI, 0>), dim3(blocks), dim3(256), 0, s, kp);
+    }
+    if (g.nsplit > 1) {
+        using PT = typename std::conditional<MODE == GM_F64, double, float>::type;
+        hipLaunchKernelGGL((k_splitk_reduce<EPI, PT>), grid_for((long)a.M * a.P), dim3(256), 0, s, kp);
     }
     return hipGetLastError();
 }
@@ -433,12 +636,8 @@ static hipError_t launch_mode(const GemmArgs &a, KP &kp, hipStream_t s)
     switch (a.epi) {
     case EPI_STORE: return launch_mode_epi<MODE, EPI_STORE>(a, kp, s);
     case EPI_SCATTER: return launch_mode_epi<MODE, EPI_SCATTER>(a, kp, s);
-    case EPI_SMOOTH: return launch_mode_epi<MODE, EPI_SMOOTH>(a, kp, s);
-    case EPI_RESID: return launch_mode_epi<MODE, EPI_RESID>(a, kp, s);
+    case EPI_SCATTER_ADD: return launch_mode_epi<MODE, EPI_SCATTER_ADD>(a, kp, s);
     case EPI_SUB: return launch_mode_epi<MODE, EPI_SUB>(a, kp, s);
-    case EPI_RESID_DD:
-        if constexpr (MODE == GM_F64) return launch_mode_epi<MODE, EPI_RESID_DD>(a, kp, s);
-        return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
@@ -465,8 +664,8 @@ hipError_t launch_toep_gemm(const GemmArgs &a, hipStream_t s)
 // eq. red-black_2d): b = f + c d g + (neighbour sum) / h^2 at the points of
 // one colour, gathered into a dense panel (the B operand of the product).
 template <typename S>
-__global__ void k_rhs_panel(int dims, int n, int colour, int M, int Pc, const double *F,
-                            const double *U, const double *cd, const double *g, double ih2, S *panel,
+__global__ void k_rhs_panel(int dims, int n, int colour, int M, int Pc, const double *F, double *U,
+                            const double *cd, const double *g, double ih2, double lam0, S *panel,
                             long ldp)
 {
     long P = (dims == 1) ? n : (long)n * n;
@@ -475,10 +674,11 @@ __global__ void k_rhs_panel(int dims, int n, int colour, int M, int Pc, const do
          e += (long)gridDim.x * blockDim.x) {
         int k = (int)(e / Pc), j = (int)(e - (long)k * Pc);
         int pt = colour_point(dims, n, colour, j);
-        const double *Uk = U + (long)k * P;
+        double *Uk = U + (long)k * P;
         double b = F[(long)k * P + pt] + nbr_sum(Uk, dims, n, pt) * ih2;
         if (g) b += cd[k] * g[pt];
         panel[(long)k * ldp + j] = (S)b;
+        if (lam0 != 0.0) Uk[pt] = lam0 * b;
     }
 }
 
@@ -504,8 +704,8 @@ __device__ inline void store_split8(const float *b, uint16_t *hi, uint16_t *lo, 
 // [Mpad/8][ldp][8] (zero outside k < M, j < Pc).  One thread builds the 8
 // time rows of one column.
 __global__ void k_rhs_panel_packed(int dims, int n, int colour, int M, int Mpad, int Pc,
-                                   const double *F, const double *U, const double *cd,
-                                   const double *g, double ih2, uint16_t *hi, uint16_t *lo, long ldp)
+                                   const double *F, double *U, const double *cd, const double *g,
+                                   double ih2, double lam0, uint16_t *hi, uint16_t *lo, long ldp)
 {
     long P = (dims == 1) ? n : (long)n * n;
     long total = (long)(Mpad / 8) * ldp;
@@ -519,13 +719,43 @@ __global__ void k_rhs_panel_packed(int dims, int n, int colour, int M, int Mpad,
             int k = kg * 8 + q;
             double b = 0.0;
             if (k < M && j < Pc) {
-                const double *Uk = U + (long)k * P;
+                double *Uk = U + (long)k * P;
                 b = F[(long)k * P + pt] + nbr_sum(Uk, dims, n, pt) * ih2;
                 if (g) b += cd[k] * g[pt];
+                if (lam0 != 0.0) Uk[pt] = lam0 * b;
             }
             b8[q] = (float)b;
         }
         store_split8(b8, hi, lo, e);
+    }
+}
+
+// Residual (Section 2, eq. discrete_model_IVP_1; Section 6) from the Toeplitz
+// product already stored in out: out = (f + c d g - diag u - A_h u) - out.
+// With lo != nullptr the iterate is the double-double hi + lo and A_h is
+// applied with error-free transformations.
+__global__ void k_resid_post(int dims, int n, int M, const double *F, const double *U, const double *lo,
+                             const double *cd, const double *g, double ih2, double diag, double *out)
+{
+    long P = (dims == 1) ? n : (long)n * n;
+    long total = (long)M * P;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        int k = (int)(e / P), p = (int)(e - (long)k * P);
+        const double *Uk = U + (long)k * P;
+        double rhs = F[e];
+        if (g) rhs += cd[k] * g[p];
+        if (diag != 0.0) rhs -= diag * Uk[p];
+        double r;
+        if (lo) {
+            double shi, slo;
+            stencil_dd(Uk, lo + (long)k * P, dims, n, p, shi, slo);
+            r = (rhs - shi * ih2) - slo * ih2;
+        } else {
+            double st = (dims == 1 ? 2.0 : 4.0) * Uk[p] - nbr_sum(Uk, dims, n, p);
+            r = rhs - st * ih2;
+        }
+        out[e] = r - out[e];
     }
 }
 
@@ -617,6 +847,15 @@ __global__ void k_prolong_add(int dims, int nc, int M, const double *ec, double 
             v = 0.25 * (at(xa, ya) + at(xb, ya) + at(xa, yb) + at(xb, yb));
         }
         uf[e] += v;
+    }
+}
+
+__global__ void k_scaled_fill(long M, long P, const double *cd, const double *g, double *u)
+{
+    long total = M * P;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+         e += (long)gridDim.x * blockDim.x) {
+        u[e] = g ? cd[e / P] * g[e % P] : 0.0;
     }
 }
 
@@ -736,30 +975,32 @@ __global__ void k_build_coef(int n, const double *d64, float *d32, int nq, uint1
 }
 
 // ---------------------------------------------------------------------------
-static inline dim3 grid_for(long total, int threads = 256)
-{
-    long b = (total + threads - 1) / threads;
-    if (b < 1) b = 1;
-    if (b > 65536) b = 65536;
-    return dim3((unsigned)b);
-}
-
 hipError_t launch_rhs_panel(int fmt, int dims, int n, int colour, int M, int Mpad, const double *F,
-                            const double *U, const double *cd, const double *g, double ih2,
+                            double *U, const double *cd, const double *g, double ih2, double lam0,
                             void *panel, void *panel_lo, long ldp, hipStream_t s)
 {
     int Pc = colour_count(dims, n, colour);
     if (fmt == 2) {
         long total = (long)(Mpad / 8) * ldp;
         hipLaunchKernelGGL(k_rhs_panel_packed, grid_for(total), dim3(256), 0, s, dims, n, colour, M, Mpad,
-                           Pc, F, U, cd, g, ih2, (uint16_t *)panel, (uint16_t *)panel_lo, ldp);
+                           Pc, F, U, cd, g, ih2, lam0, (uint16_t *)panel, (uint16_t *)panel_lo, ldp);
     } else if (fmt == 0) {
         hipLaunchKernelGGL(k_rhs_panel<double>, grid_for((long)M * Pc), dim3(256), 0, s, dims, n, colour,
-                           M, Pc, F, U, cd, g, ih2, (double *)panel, ldp);
+                           M, Pc, F, U, cd, g, ih2, lam0, (double *)panel, ldp);
     } else {
         hipLaunchKernelGGL(k_rhs_panel<float>, grid_for((long)M * Pc), dim3(256), 0, s, dims, n, colour,
-                           M, Pc, F, U, cd, g, ih2, (float *)panel, ldp);
+                           M, Pc, F, U, cd, g, ih2, lam0, (float *)panel, ldp);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_post(int dims, int n, int M, const double *F, const double *U, const double *lo,
+                             const double *cd, const double *g, double ih2, double diag, double *out,
+                             hipStream_t s)
+{
+    long total = (long)M * ((dims == 1) ? n : (long)n * n);
+    hipLaunchKernelGGL(k_resid_post, grid_for(total), dim3(256), 0, s, dims, n, M, F, U, lo, cd, g, ih2, diag,
+                       out);
     return hipGetLastError();
 }
 
@@ -796,6 +1037,12 @@ hipError_t launch_prolong_add(int dims, int nc, int M, const double *ec, double 
     int nf = 2 * nc + 1;
     long total = (long)M * ((dims == 1) ? nf : (long)nf * nf);
     hipLaunchKernelGGL(k_prolong_add, grid_for(total), dim3(256), 0, s, dims, nc, M, ec, uf);
+    return hipGetLastError();
+}
+
+hipError_t launch_scaled_fill(long M, long P, const double *cd, const double *g, double *u, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scaled_fill, grid_for(M * P), dim3(256), 0, s, M, P, cd, g, u);
     return hipGetLastError();
 }
 
