@@ -13,6 +13,14 @@ Modes: "bf16x3" (split-BF16 inner cycle, FP64 double-double refinement; the
 reported value), "fp64" (Algorithm 1 in FP64 on u), "fp32" (FP32 inner
 cycle), "fp64r" (FP64 inner cycle with double-double refinement).
 
+Before the timed steps each handle is autotuned (tile shapes of the product
+kernels, and D&C base blocks with --smoother auto/dc); the tuning time is
+reported apart from the timed steps, like handle creation.
+
+--workload batch solves 256 independent 1D problems of uneven size (N in
+{127..2047}, M in {256..8192}, alpha in (0.1, 0.9), seeded) as one batch:
+every stage of their cycles is one launch over all problems still iterating.
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -45,6 +53,8 @@ def make_workloads(name):
         return [W.nonsmooth_2d(1023, 1024, 0.3)], "2d_nonsmooth_N1023_M1024_alpha0.3"
     if name == "small":
         return [W.manufactured_1d()], "1d_N63_M64_alpha0.5"
+    if name == "batch":
+        return W.batch_1d(), "batch256_1d_N127-2047_M256-8192"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -69,50 +79,127 @@ def sampled_error(w, u_dev, npts=4096, seed=0):
     return float(np.abs(got - ref).max() / np.abs(ref).max())
 
 
-def run_mode(mode, wls, fs, steps, warmup, tol, check, profile):
+class _BatchRunner:
+    """The whole workload as one batch handle."""
+
+    def __init__(self, B, wls, mode, smoother):
+        self.b = B.Batch([w.N for w in wls], [w.M for w in wls], [w.alpha for w in wls],
+                         [w.T for w in wls], dims=wls[0].dims, precision=mode, maxit=40, smoother=smoother)
+
+    def autotune(self):
+        return self.b.autotune()
+
+    def solve(self, fs, us, tol):
+        _, infos = self.b.solve(fs, us, tol=tol)
+        return infos
+
+    def profile(self, on):
+        self.b.profile(on)
+
+    def records(self):
+        return self.b.profile_records()
+
+    def close(self):
+        self.b.close()
+
+
+class _SingleRunner:
+    """One handle per problem, solved one after the other."""
+
+    def __init__(self, B, wls, mode, smoother):
+        self.ss = [B.Solver(w.N, w.M, w.alpha, T=w.T, dims=w.dims, precision=mode, maxit=40, smoother=smoother)
+                   for w in wls]
+
+    def autotune(self):
+        return [s.autotune() for s in self.ss][0]
+
+    def solve(self, fs, us, tol):
+        return [s.solve(f, u, tol=tol) for s, f, u in zip(self.ss, fs, us)]
+
+    def profile(self, on):
+        for s in self.ss:
+            s.profile(on)
+
+    def records(self):
+        return [r for s in self.ss for r in s.profile_records()]
+
+    def close(self):
+        for s in self.ss:
+            s.close()
+
+
+def run_mode(mode, wls, fs, steps, warmup, tol, check, profile, batch=False, autotune=True,
+             smoother="inverse", graph_step=True):
     import torch
     from paper_1608_05400_amd import binding as B
-    solvers = [B.Solver(w.N, w.M, w.alpha, T=w.T, dims=w.dims, precision=mode, maxit=40) for w in wls]
-    us = [torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda") for s in solvers]
+    runner = (_BatchRunner if batch else _SingleRunner)(B, wls, mode, smoother)
+    us = [torch.zeros((w.M, w.N) if w.dims == 1 else (w.M, w.N, w.N), dtype=torch.float64, device="cuda")
+          for w in wls]
+    tuning = None
+    t_tune = 0.0
+    if autotune:
+        t = time.perf_counter()
+        tuning = runner.autotune()
+        t_tune = time.perf_counter() - t
+        log(f"{mode}: autotuned in {t_tune:.1f} s: {tuning}")
     infos = []
     for it in range(warmup):
-        for s, f, u in zip(solvers, fs, us):
-            s.solve(f, u, tol=tol)
+        runner.solve(fs, us, tol)
         log(f"{mode}: warmup {it + 1}/{warmup} done")
+    # the timed steps bracket every product launch with HIP events (so the
+    # launches are issued one by one); one more step replays the recorded
+    # HIP graphs, the path of repeated solves, and is reported beside them
     if profile:
-        for s in solvers:
-            s.profile(True)
+        runner.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        infos = []
-        for s, f, u in zip(solvers, fs, us):
-            infos.append(s.solve(f, u, tol=tol))
-        log(f"{mode}: step {k + 1}/{steps} done, iters {[i['iters'] for i in infos]}")
+        infos = runner.solve(fs, us, tol)
+        log(f"{mode}: step {k + 1}/{steps} done, iters {summ([i['iters'] for i in infos])}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     records = []
     if profile:
-        for s in solvers:
-            records += s.profile_records()
-            s.profile(False)
+        records = runner.records()
+        runner.profile(False)
+    ms_graph = None
+    if graph_step:
+        runner.solve(fs, us, tol)   # records the graphs
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        runner.solve(fs, us, tol)
+        torch.cuda.synchronize()
+        ms_graph = 1e3 * (time.perf_counter() - t)
+        log(f"{mode}: graph-replay step {ms_graph:.1f} ms")
     unknowns = sum(w.unknowns for w in wls)
     res = {
         "mode": mode,
         "value": unknowns * steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
-        "iters": [i["iters"] for i in infos],
-        "status": [i["status"] for i in infos],
-        "relres": [i["relres"] for i in infos],
-        "mean_factor": [round(i["mean_factor"], 5) for i in infos],
+        "iters": summ([i["iters"] for i in infos]),
+        "status": summ([i["status"] for i in infos]),
+        "relres": summ([i["relres"] for i in infos]),
+        "mean_factor": summ([round(i["mean_factor"], 5) for i in infos]),
+        "ms_per_step_graph_replay": ms_graph,
+        "tuning": tuning,
+        "tune_s": round(t_tune, 2),
     }
     if check:
-        res["err_vs_oracle"] = [sampled_error(w, u) for w, u in zip(wls, us)]
-    for s in solvers:
-        s.close()
+        idx = range(len(wls)) if len(wls) <= 4 else sorted(range(len(wls)), key=lambda i: -wls[i].unknowns)[:4]
+        res["err_vs_oracle"] = [sampled_error(wls[i], us[i]) for i in idx]
+    runner.close()
     del us
     torch.cuda.empty_cache()
     return res, records
+
+
+def summ(v):
+    """A per-problem list, or its summary for long lists."""
+    if len(v) <= 8:
+        return v
+    if isinstance(v[0], str):
+        return {k: v.count(k) for k in sorted(set(v))}
+    return {"min": min(v), "max": max(v), "mean": sum(v) / len(v)}
 
 
 def roofline_of(records, steps):
@@ -129,7 +216,7 @@ def roofline_of(records, steps):
         d["n"] += 1
     kid = max(by, key=lambda k: by[k]["ms"])
     d = by[kid]
-    mode = kid >> 4
+    mode = (kid >> 4) & 15
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[mode]
     out = {
@@ -194,7 +281,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="1d", choices=["1d", "2d", "2dns", "small"])
+    ap.add_argument("--workload", default="1d", choices=["1d", "2d", "2dns", "small", "batch"])
+    ap.add_argument("--smoother", default="inverse", choices=["inverse", "dc", "auto"])
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--modes", default="bf16x3,fp64,fp32,fp64r")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -222,7 +312,8 @@ def main():
     for i, mode in enumerate(modes):
         steps = args.steps if i < 2 else max(1, min(args.steps, 1))
         res, recs = run_mode(mode, wls, fs, steps, args.warmup if i < 2 else 0, args.tol,
-                             not args.no_check, profile=True)
+                             not args.no_check, profile=not args.no_profile, batch=args.workload == "batch",
+                             autotune=not args.no_autotune, smoother=args.smoother, graph_step=i < 2)
         results[mode] = res
         rooflines[mode] = roofline_of(recs, steps)
         for row in kernel_table(recs, steps)[:14]:
@@ -248,7 +339,7 @@ def main():
         "dtype": "f64+bf16x3" if primary == "bf16x3" else ("f64+f32" if primary == "fp32" else "f64"),
         "data": "synthetic",
         "config": {"workload": wname, "mode": primary, "cycle": "V(1,1)", "tol": args.tol,
-                   "norm": "max"},
+                   "norm": "max", "smoother": args.smoother, "autotuned": not args.no_autotune},
         "roofline": rooflines.get(primary),
         "modes": results,
         "rooflines": rooflines,

@@ -63,14 +63,18 @@ enum mgwr_precision {
 
 enum mgwr_norm { MGWR_NORM_MAX = 0, MGWR_NORM_L2 = 1 };
 
-/* Smoother line solve (Section 5.2): both solve (T_M + sigma I) x = b along
+/* Smoother line solve (Section 5.2): all solve (T_M + sigma I) x = b along
  * every time line of one colour exactly (up to rounding). */
 enum mgwr_smoother {
     MGWR_SMOOTH_INVERSE = 0, /* one causal Toeplitz product with the precomputed first
                                 column of (T_M + sigma I)^{-1}                        */
-    MGWR_SMOOTH_DC = 1       /* divide-and-conquer blocked forward substitution: base
-                                blocks by the inverse of the leading block, history
-                                updates by full Toeplitz-block products            */
+    MGWR_SMOOTH_DC = 1,      /* divide-and-conquer blocked forward substitution: rows cut
+                                into base blocks of dc_block rows, each solved with the
+                                inverse of the leading block; after base block j the rows
+                                of the D&C node split at j + 1 get the history of the
+                                node's top half as one full Toeplitz-block product     */
+    MGWR_SMOOTH_AUTO = 2     /* per level, whichever of the two the autotuner timed
+                                fastest (MGWR_SMOOTH_INVERSE until mgwr_autotune)      */
 };
 
 typedef struct {
@@ -84,10 +88,15 @@ typedef struct {
     int first_colour;   /* colour relaxed first: 0 = even n (2D: n + l even), as ordered in
                            the text of Section 3; 1 = odd n first (default 0)              */
     int smoother;       /* enum mgwr_smoother (default MGWR_SMOOTH_INVERSE)                  */
-    int dc_block;       /* base block of MGWR_SMOOTH_DC, a power of two >= 64 (0 = auto)      */
+    int dc_block;       /* base block of MGWR_SMOOTH_DC: a multiple of 128, or 0 = the
+                           autotuner's per-level choice (1024 before mgwr_autotune); a block
+                           of M rows or more is the inverse-column solve                  */
     double L;           /* domain length (default 1)                                         */
     double stall;       /* mgwr_solve stops with MGWR_STAGNATED when a cycle reduces the
                            residual by less than this factor (default 0.5; 0 disables)      */
+    int graph;          /* 1 = record each outer iteration of mgwr_solve /
+                           mgwr_batch_solve once per set of arguments and replay it as a
+                           HIP graph; 0 = issue every launch each time (default 1)          */
 } mgwr_options;
 
 typedef struct {
@@ -164,28 +173,64 @@ int mgwr_get_column(mgwr_t h, int which, double *out);
 /* Number of levels (finest = levels - 1). */
 int mgwr_levels(mgwr_t h);
 
+/* ---- autotuner ----
+ * Times one cycle of the error equation of the handle (its own buffers only:
+ * no caller array is read or written) under candidate tile shapes of the
+ * Toeplitz-product kernels and, when options.smoother is MGWR_SMOOTH_DC with
+ * dc_block = 0 or MGWR_SMOOTH_AUTO, candidate D&C base blocks per level, and
+ * keeps the fastest.  Handles of the same shape and options created later in
+ * the process reuse the result.  Synchronous; the choice is reported by
+ * mgwr_get_tuning. */
+typedef struct {
+    int tuned;            /* 1 once mgwr_autotune has run                                */
+    int variant[2];       /* FP64 / FP32 product tile: -1 by size, 0 = 128x64, 1 = 256x64 */
+    int split_target[3];  /* FP64 / FP32 / split-BF16 work items a lone launch aims for
+                             (0 = default); fewer tiles than that split the K range     */
+    int levels;
+    int dc_block[32];     /* per level (0 = coarsest): 0 = inverse-column solve, else the
+                             D&C base block in rows                                       */
+    double ms_default;    /* cycle time with the default choices (ms)                    */
+    double ms_tuned;      /* cycle time with the chosen ones (ms)                        */
+} mgwr_tuning;
+int mgwr_autotune(mgwr_t h);
+int mgwr_get_tuning(mgwr_t h, mgwr_tuning *t);
+
 /* ---- batches of independent 1D or 2D problems (uneven N, M, alpha) ----
  * count problems; N[i], M[i], alpha[i], T[i] as for mgwr_create; all share
  * dims and opts.  f, g, u are host arrays of count device pointers (g may
  * be NULL or contain NULLs).  infos: host array of count mgwr_info (may be
- * NULL).  Returns the worst status over the problems. */
+ * NULL).  The problems are solved together: every stage of a cycle (colour
+ * right-hand sides, Toeplitz products, residuals, transfers, norms) is ONE
+ * launch over all problems still iterating, their product tiles ordered by
+ * K extent; each problem stops by its own test, with the results mgwr_solve
+ * would give it.  Returns the worst status over the problems (a negative
+ * one if any failed; mgwr_last_error names the problem). */
 int mgwr_batch_create(int count, const int *N, const int *M, const double *alpha,
                       const double *T, int dims, const mgwr_options *opts, mgwr_batch_t *out);
 int mgwr_batch_solve(mgwr_batch_t b, const double *const *f, const double *const *g,
                      double *const *u, double tol, mgwr_info *infos);
 int mgwr_batch_set_stream(mgwr_batch_t b, void *hip_stream);
+/* The autotuner over the whole batch (one set of tile shapes and per-depth
+ * D&C blocks for all problems, timed on a cycle of all of them). */
+int mgwr_batch_autotune(mgwr_batch_t b);
+int mgwr_batch_get_tuning(mgwr_batch_t b, int i, mgwr_tuning *t);
 int mgwr_batch_destroy(mgwr_batch_t b);
 
 /* ---- per-launch timing of the Toeplitz products (history GEMMs) ----
- * With profiling on, every Toeplitz-product launch of the handle is bracketed
- * by HIP events recorded on the handle's stream.  kernel identifies the
- * kernel instantiation: (mode << 4) | (epilogue << 1) | narrow, with mode 0 =
- * FP64, 1 = FP32, 2 = split-BF16; epilogue 0 = store (residual product), 1 = colour scatter
- * (smoother, whole line solve), 2 = colour scatter-add (smoother, history
- * part), 3 = subtract; narrow = 1 for the few-column variant.
- * flops counts the multiply-adds of the product that are not structurally
- * zero, times 2.  ms covers the product and, when its K range is split over
- * several blocks, the reduce kernel that applies its epilogue. */
+ * With profiling on, every Toeplitz-product launch of the handle (or batch)
+ * is bracketed by HIP events recorded on its stream, and mgwr_solve issues
+ * its launches one by one instead of replaying graphs.  kernel identifies
+ * the kernel instantiation: (kind << 8) | (mode << 4) | epilogue, with kind
+ * 0 = narrow (64x16 tiles), 1 = wide 128x64, 2 = wide 256x64, 3 = split-BF16
+ * 256x128; mode 0 = FP64, 1 = FP32, 2 = split-BF16; epilogue 0 = store
+ * (residual product, D&C base block in FP64), 1 = colour scatter (smoother,
+ * whole line solve), 2 = colour scatter-add (smoother, history part),
+ * 3 = subtract (D&C history update), 4 = add (D&C base block, history part).
+ * A record covers one launch, possibly over several problems: M and K are
+ * those of the first, P the sum of the columns, flops the sum of the
+ * multiply-adds that are not structurally zero, times 2.  ms covers the
+ * product and, when its K range is split over several blocks, the reduce
+ * kernel that applies its epilogue. */
 typedef struct {
     int kernel, level, M, P, K;
     double flops;  /* algorithmic flops of the launch                        */
@@ -199,6 +244,9 @@ int mgwr_profile_count(mgwr_t h);
 int mgwr_profile_get(mgwr_t h, int i, mgwr_kernel_record *rec);
 /* Name of the kernel function of a kernel id (as profilers print it). */
 const char *mgwr_kernel_name(int kernel);
+int mgwr_batch_profile_enable(mgwr_batch_t b, int on);
+int mgwr_batch_profile_count(mgwr_batch_t b);
+int mgwr_batch_profile_get(mgwr_batch_t b, int i, mgwr_kernel_record *rec);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *mgwr_last_error(void);

@@ -19,6 +19,8 @@ MGWR_EINVAL, MGWR_ENOMEM, MGWR_EDEVICE, MGWR_ENONFINITE, MGWR_EDIVERGED = -1, -2
 FP64, MIXED_FP32, MIXED_BF16X3, FP64_REFINED = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16x3": MIXED_BF16X3, "fp64r": FP64_REFINED}
 NORM_MAX, NORM_L2 = 0, 1
+SMOOTH_INVERSE, SMOOTH_DC, SMOOTH_AUTO = 0, 1, 2
+SMOOTHERS = {"inverse": SMOOTH_INVERSE, "dc": SMOOTH_DC, "auto": SMOOTH_AUTO}
 STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "stagnated", -1: "einval", -2: "enomem",
                 -3: "edevice", -4: "enonfinite", -5: "ediverged"}
 
@@ -28,7 +30,9 @@ EXPORTED = [
     "mgwr_vcycle", "mgwr_solve", "mgwr_toeplitz_apply", "mgwr_get_column", "mgwr_levels",
     "mgwr_batch_create", "mgwr_batch_solve", "mgwr_batch_set_stream", "mgwr_batch_destroy",
     "mgwr_profile_enable", "mgwr_profile_count", "mgwr_profile_get", "mgwr_kernel_name",
-    "mgwr_last_error",
+    "mgwr_last_error", "mgwr_autotune", "mgwr_get_tuning", "mgwr_batch_autotune",
+    "mgwr_batch_get_tuning", "mgwr_batch_profile_enable", "mgwr_batch_profile_count",
+    "mgwr_batch_profile_get",
 ]
 
 
@@ -43,7 +47,20 @@ class Options(ctypes.Structure):
                 ("maxit", ctypes.c_int), ("norm", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("precision", ctypes.c_int), ("first_colour", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("dc_block", ctypes.c_int),
-                ("L", ctypes.c_double), ("stall", ctypes.c_double)]
+                ("L", ctypes.c_double), ("stall", ctypes.c_double), ("graph", ctypes.c_int)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tuned", ctypes.c_int), ("variant", ctypes.c_int * 2),
+                ("split_target", ctypes.c_int * 3), ("levels", ctypes.c_int),
+                ("dc_block", ctypes.c_int * 32), ("ms_default", ctypes.c_double),
+                ("ms_tuned", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"tuned": bool(self.tuned), "variant": list(self.variant),
+                "split_target": list(self.split_target),
+                "dc_block": list(self.dc_block[:self.levels]),
+                "ms_default": self.ms_default, "ms_tuned": self.ms_tuned}
 
 
 class KernelRecord(ctypes.Structure):
@@ -100,6 +117,13 @@ def load(path: str = LIB_PATH):
     lib.mgwr_profile_enable.argtypes = [h, I]
     lib.mgwr_profile_count.argtypes = [h]
     lib.mgwr_profile_get.argtypes = [h, I, P(KernelRecord)]
+    lib.mgwr_autotune.argtypes = [h]
+    lib.mgwr_get_tuning.argtypes = [h, P(Tuning)]
+    lib.mgwr_batch_autotune.argtypes = [h]
+    lib.mgwr_batch_get_tuning.argtypes = [h, I, P(Tuning)]
+    lib.mgwr_batch_profile_enable.argtypes = [h, I]
+    lib.mgwr_batch_profile_count.argtypes = [h]
+    lib.mgwr_batch_profile_get.argtypes = [h, I, P(KernelRecord)]
     lib.mgwr_kernel_name.argtypes = [I]
     lib.mgwr_kernel_name.restype = ctypes.c_char_p
     lib.mgwr_last_error.restype = ctypes.c_char_p
@@ -117,18 +141,37 @@ def _check(rc, allow_positive=True):
     return rc
 
 
+def _option_value(k, v):
+    if k == "precision" and isinstance(v, str):
+        return PRECISIONS[v]
+    if k == "norm" and isinstance(v, str):
+        return {"max": NORM_MAX, "l2": NORM_L2}[v]
+    if k == "smoother" and isinstance(v, str):
+        return SMOOTHERS[v]
+    if isinstance(v, bool):
+        return int(v)
+    return v
+
+
 def default_options(**kw) -> Options:
     o = Options()
     load().mgwr_default_options(ctypes.byref(o))
     for k, v in kw.items():
-        if k == "precision" and isinstance(v, str):
-            v = PRECISIONS[v]
-        if k == "norm" and isinstance(v, str):
-            v = {"max": NORM_MAX, "l2": NORM_L2}[v]
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
-        setattr(o, k, v)
+        setattr(o, k, _option_value(k, v))
     return o
+
+
+def _records(count, get, handle):
+    n = _check(count(handle))
+    out = []
+    rec = KernelRecord()
+    for i in range(n):
+        _check(get(handle, i, ctypes.byref(rec)), False)
+        out.append({"kernel": rec.kernel, "name": kernel_name(rec.kernel), "level": rec.level,
+                    "M": rec.M, "P": rec.P, "K": rec.K, "flops": rec.flops, "ms": rec.ms})
+    return out
 
 
 def l1_weights(M: int, alpha: float, T: float = 1.0):
@@ -212,12 +255,22 @@ class Solver:
     def set_options(self, **kw):
         o = self.options()
         for k, v in kw.items():
-            if k == "precision" and isinstance(v, str):
-                v = PRECISIONS[v]
-            if k == "norm" and isinstance(v, str):
-                v = {"max": NORM_MAX, "l2": NORM_L2}[v]
-            setattr(o, k, v)
+            if not hasattr(o, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(o, k, _option_value(k, v))
         _check(self._lib.mgwr_set_options(self._h, ctypes.byref(o)), False)
+
+    def autotune(self):
+        """Time tile shapes (and D&C base blocks) on the handle's own buffers
+        and keep the fastest; returns the choice."""
+        self._bind_stream()
+        _check(self._lib.mgwr_autotune(self._h), False)
+        return self.tuning()
+
+    def tuning(self):
+        t = Tuning()
+        _check(self._lib.mgwr_get_tuning(self._h, ctypes.byref(t)), False)
+        return t.as_dict()
 
     def levels(self) -> int:
         return _check(self._lib.mgwr_levels(self._h))
@@ -282,14 +335,7 @@ class Solver:
         _check(self._lib.mgwr_profile_enable(self._h, 1 if on else 0), False)
 
     def profile_records(self):
-        n = _check(self._lib.mgwr_profile_count(self._h))
-        out = []
-        rec = KernelRecord()
-        for i in range(n):
-            _check(self._lib.mgwr_profile_get(self._h, i, ctypes.byref(rec)), False)
-            out.append({"kernel": rec.kernel, "name": kernel_name(rec.kernel), "level": rec.level,
-                        "M": rec.M, "P": rec.P, "K": rec.K, "flops": rec.flops, "ms": rec.ms})
-        return out
+        return _records(self._lib.mgwr_profile_count, self._lib.mgwr_profile_get, self._h)
 
     def column(self, which=-1):
         import numpy as np
@@ -325,16 +371,39 @@ class Batch:
         except Exception:
             pass
 
-    def solve(self, fs, us, gs=None, tol=1e-10):
-        n = len(fs)
-        fp = (ctypes.c_void_p * n)(*[_ptr(f, "f").value for f in fs])
-        up = (ctypes.c_void_p * n)(*[_ptr(u, "u").value for u in us])
+    def grid_shape(self, i):
+        N, M = self.Ns[i], self.Ms[i]
+        return (M, N) if self.dims == 1 else (M, N, N)
+
+    def solve(self, fs, us, gs=None, tol=1e-10, raise_on_error=True):
+        n = len(self.Ns)
+        if len(fs) != n or len(us) != n or (gs is not None and len(gs) != n):
+            raise ValueError(f"need {n} right-hand sides and iterates")
+        fp = (ctypes.c_void_p * n)(*[_ptr(f, "f", self.grid_shape(i)).value for i, f in enumerate(fs)])
+        up = (ctypes.c_void_p * n)(*[_ptr(u, "u", self.grid_shape(i)).value for i, u in enumerate(us)])
         gp = None
         if gs is not None:
-            gp = (ctypes.c_void_p * n)(*[(_ptr(g, "g").value if g is not None else None) for g in gs])
+            gp = (ctypes.c_void_p * n)(*[(_ptr(g, "g", self.grid_shape(i)[1:]).value
+                                          if g is not None else None) for i, g in enumerate(gs)])
         infos = (Info * n)()
         _check(self._lib.mgwr_batch_set_stream(self._b, _stream()))
         rc = self._lib.mgwr_batch_solve(self._b, fp, gp, up, tol, infos)
-        if rc < 0:
+        if rc < 0 and raise_on_error:
             raise MgwrError(rc, last_error())
         return rc, [i.as_dict() for i in infos]
+
+    def autotune(self):
+        _check(self._lib.mgwr_batch_set_stream(self._b, _stream()))
+        _check(self._lib.mgwr_batch_autotune(self._b), False)
+        return self.tuning(0)
+
+    def tuning(self, i=0):
+        t = Tuning()
+        _check(self._lib.mgwr_batch_get_tuning(self._b, i, ctypes.byref(t)), False)
+        return t.as_dict()
+
+    def profile(self, on=True):
+        _check(self._lib.mgwr_batch_profile_enable(self._b, 1 if on else 0), False)
+
+    def profile_records(self):
+        return _records(self._lib.mgwr_batch_profile_count, self._lib.mgwr_batch_profile_get, self._b)

@@ -5,18 +5,28 @@
 // (Section 2) makes the space-time matrix T_M (x) I + A_h with T_M lower
 // triangular Toeplitz (Section 5).  Algorithm 1 (Section 3) is run with
 //   * smoother: red-black waveform relaxation; one half-sweep solves
-//     (T_M + sigma I) x = b for every point of a colour.  The inverse of a
-//     lower-triangular Toeplitz matrix is lower-triangular Toeplitz and its
-//     first column can be computed once (Section 5.2), so a half-sweep is one
-//     causal Toeplitz product of that column with the colour's right-hand
-//     sides (an MFMA GEMM over all points of the colour);
-//   * defect: one causal Toeplitz product with T_M plus the stencil, fused;
+//     (T_M + sigma I) x = b for every point of a colour, either
+//       - as one causal Toeplitz product of the precomputed first column of
+//         (T_M + sigma I)^{-1} (a lower-triangular Toeplitz matrix, Section
+//         5.2) with the colour's right-hand sides, or
+//       - by the divide-and-conquer blocked forward substitution of Section
+//         5.2: base blocks of Mb rows by the inverse of the leading Mb x Mb
+//         block, and after each base block the history update of the rows
+//         that depend on it as one full Toeplitz-block product;
+//   * defect: one causal Toeplitz product with T_M plus the stencil;
 //   * full weighting / linear (bilinear) interpolation, coarsening in space
 //     only down to one point, where one sweep is the exact line solve.
 // mgwr_solve runs either Algorithm 1 on u directly (MGWR_FP64), or an outer
 // iterative refinement whose residual is FP64 with the iterate carried as a
 // double-double (hi in the caller's u, lo internal) and whose correction
 // comes from one cycle on the error equation in FP64, FP32 or split-BF16.
+//
+// Execution: every stage (a half-sweep, a residual, a transfer, the norms) is
+// issued for a list of (problem, level) tasks with one launch per kernel, so
+// a batch of independent problems advances in lockstep, stage by stage.  The
+// host logic of an outer iteration is a deterministic function of the active
+// problems and the caller's pointers; it is recorded once (argument arrays
+// uploaded to a device arena), captured into a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +34,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <list>
+#include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -32,6 +46,10 @@
 #include "mgwr_internal.h"
 
 using namespace mgwr;
+
+namespace mgwr {
+int product_kernel_kind(int mode, int M, int P, const TileKnobs &kn);
+}
 
 namespace {
 
@@ -65,6 +83,8 @@ int fail(int code, const char *fmt, ...)
 // Split-BF16 products are used only where a launch has at least this many
 // columns; narrower levels (the coarse grids) run their products in FP32.
 constexpr int kBf16MinCols = 128;
+// Base block of MGWR_SMOOTH_DC when neither the options nor the tuner set one.
+constexpr int kDcDefault = 1024;
 
 // ---------------------------------------------------------------------------
 // L1 weights (Section 2, L1 scheme; Section 5, r_i).  d_k for k >= 2 as
@@ -147,6 +167,122 @@ struct Level {
     double lam0 = 0;  // first entry of that column
     double *u64 = nullptr, *f64 = nullptr;  // FP64 hierarchy (levels below the finest)
     double *e = nullptr, *fe = nullptr;     // inner hierarchy of the refinement (all levels)
+    int dc_tuned = 0;                       // base block chosen by the tuner (0: inverse column)
+};
+
+// Tile knobs per product arithmetic (FP64, FP32, split-BF16).
+struct Tuning {
+    TileKnobs kn[3];
+    bool tuned = false;
+    double ms_default = 0, ms_tuned = 0;
+};
+
+// Per-launch timing of the products.
+struct Profiler {
+    bool on = false;
+    struct Pending { hipEvent_t a, b; mgwr_kernel_record rec; };
+    std::vector<Pending> pending;
+    std::vector<mgwr_kernel_record> records;
+    std::vector<hipEvent_t> pool;
+
+    hipEvent_t take()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    int resolve(hipStream_t s)
+    {
+        if (pending.empty()) return MGWR_OK;
+        HIPCHK(hipStreamSynchronize(s));
+        for (auto &p : pending) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+            p.rec.ms = ms;
+            records.push_back(p.rec);
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+        return MGWR_OK;
+    }
+    void release()
+    {
+        for (auto &p : pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+        for (auto e : pool) hipEventDestroy(e);
+        pending.clear();
+        pool.clear();
+    }
+};
+
+// A recorded outer-iteration program: its argument arena and its graph.
+struct Program {
+    char *arena = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+// Issues the stages of one handle or one batch.
+struct Runner {
+    hipStream_t stream = nullptr;   // the caller's stream
+    hipStream_t capture = nullptr;  // private stream the graphs are captured on
+    int count = 1;                  // problems
+    bool graphs = true;
+    Profiler prof;
+    std::map<std::string, Program> progs;
+    std::list<std::string> lru;
+    char *arena = nullptr;          // argument arena of eager grouped programs
+    size_t arena_cap = 0;
+    double *norms_dev = nullptr, *norms_host = nullptr;   // [count][2]
+};
+
+void drop_program(Program &p)
+{
+    if (p.exec) hipGraphExecDestroy(p.exec);
+    if (p.graph) hipGraphDestroy(p.graph);
+    if (p.arena) hipFree(p.arena);
+    p = Program{};
+}
+
+void clear_programs(Runner &R)
+{
+    if (R.progs.empty()) return;
+    hipStreamSynchronize(R.stream);
+    for (auto &kv : R.progs) drop_program(kv.second);
+    R.progs.clear();
+    R.lru.clear();
+}
+
+void release_runner(Runner &R)
+{
+    clear_programs(R);
+    if (R.arena) hipFree(R.arena);
+    if (R.norms_dev) hipFree(R.norms_dev);
+    if (R.norms_host) hipHostFree(R.norms_host);
+    if (R.capture) hipStreamDestroy(R.capture);
+    R.prof.release();
+    R.arena = nullptr; R.norms_dev = nullptr; R.norms_host = nullptr; R.capture = nullptr;
+}
+
+int init_runner(Runner &R, int count)
+{
+    R.count = count;
+    HIPCHK(hipMalloc((void **)&R.norms_dev, sizeof(double) * 2 * count));
+    HIPCHK(hipHostMalloc((void **)&R.norms_host, sizeof(double) * 2 * count, hipHostMallocDefault));
+    return MGWR_OK;
+}
+
+// The context every stage issues its launches through.
+struct Exec {
+    hipStream_t s;
+    Staging *st;        // argument arrays of grouped launches (nullptr: lists of one only)
+    Profiler *prof;     // per-launch timing (nullptr: off)
+    bool record() const { return st && st->record; }
 };
 
 }  // namespace
@@ -170,23 +306,28 @@ struct mgwr_ctx {
     float *panel32 = nullptr, *op32 = nullptr;
     uint16_t *pk_hi = nullptr, *pk_lo = nullptr;
     long pk_ld = 0;
-    double *partials = nullptr, *norms_dev = nullptr, *norms_host = nullptr;
+    double *xpanel = nullptr;        // D&C: FP64 solution panel [M][maxPc]
+    float *xop32 = nullptr;          // D&C: its FP32 copy
+    uint16_t *xpk_hi = nullptr, *xpk_lo = nullptr;   // D&C: its split-BF16 copy
+    double *partials = nullptr;
     void *part = nullptr;            // split-K partials of the Toeplitz products
     size_t part_cap = 0;
-    // per-launch timing of the Toeplitz products
-    bool prof = false;
-    struct Pending { hipEvent_t a, b; mgwr_kernel_record rec; };
-    std::vector<Pending> pending;
-    std::vector<mgwr_kernel_record> records;
-    std::vector<hipEvent_t> event_pool;
+    Tuning tune;
+    Runner run;
     int inner_prec = -1;             // precision the inner buffers exist for
+    int inner_dc = 0;                // D&C buffers of the inner precision exist
     std::vector<void *> inner_alloc; // buffers owned by the inner hierarchy
     std::vector<void *> alloc;       // everything else
 };
 
+struct mgwr_batch_ctx {
+    std::vector<mgwr_t> hs;
+    Runner run;
+};
+
 namespace {
 
-int dmalloc(mgwr_ctx *h, std::vector<void *> &list, void **p, size_t bytes)
+int dmalloc(std::vector<void *> &list, void **p, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(p, bytes);
@@ -194,7 +335,6 @@ int dmalloc(mgwr_ctx *h, std::vector<void *> &list, void **p, size_t bytes)
         return fail(e == hipErrorOutOfMemory ? MGWR_ENOMEM : MGWR_EDEVICE,
                     "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
     list.push_back(*p);
-    (void)h;
     return MGWR_OK;
 }
 
@@ -208,10 +348,10 @@ int upload_coef(mgwr_ctx *h, ToepCoef &c, const std::vector<double> &v)
 {
     c.n = (int)v.size();
     c.nq = (c.n + 15) / 16 + 4 * kQOff;
-    CHK(dmalloc(h, h->alloc, (void **)&c.d64, sizeof(double) * c.n));
-    CHK(dmalloc(h, h->alloc, (void **)&c.d32, sizeof(float) * c.n));
-    CHK(dmalloc(h, h->alloc, (void **)&c.fhi, sizeof(uint16_t) * 512 * (size_t)c.nq));
-    CHK(dmalloc(h, h->alloc, (void **)&c.flo, sizeof(uint16_t) * 512 * (size_t)c.nq));
+    CHK(dmalloc(h->alloc, (void **)&c.d64, sizeof(double) * c.n));
+    CHK(dmalloc(h->alloc, (void **)&c.d32, sizeof(float) * c.n));
+    CHK(dmalloc(h->alloc, (void **)&c.fhi, sizeof(uint16_t) * 512 * (size_t)c.nq));
+    CHK(dmalloc(h->alloc, (void **)&c.flo, sizeof(uint16_t) * 512 * (size_t)c.nq));
     HIPCHK(hipMemcpy(c.d64, v.data(), sizeof(double) * c.n, hipMemcpyHostToDevice));
     HIPCHK(launch_build_coef(c, nullptr));
     return MGWR_OK;
@@ -228,60 +368,50 @@ double product_flops(const GemmArgs &a)
     return 2.0 * macs * a.P;
 }
 
+// Kernel id of a product: (kind << 8) | (mode << 4) | epilogue, kind 0 =
+// narrow, 1 = wide 128 x 64, 2 = wide 256 x 64, 3 = split-BF16.
 int kernel_id(const GemmArgs &a)
 {
-    int narrow = (a.mode != GM_BF16X3 && a.P <= 32) ? 1 : 0;
-    return (a.mode << 4) | (a.epi << 1) | narrow;
+    return (product_kernel_kind(a.mode, a.M, a.P, a.knobs) << 8) | (a.mode << 4) | a.epi;
 }
 
-hipEvent_t take_event(mgwr_ctx *h)
+GemmArgs gemm_base(mgwr_ctx *h, int mode)
 {
-    if (!h->event_pool.empty()) {
-        hipEvent_t e = h->event_pool.back();
-        h->event_pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-int resolve_profile(mgwr_ctx *h)
-{
-    if (h->pending.empty()) return MGWR_OK;
-    HIPCHK(hipStreamSynchronize(h->stream));
-    for (auto &p : h->pending) {
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
-        p.rec.ms = ms;
-        h->records.push_back(p.rec);
-        h->event_pool.push_back(p.a);
-        h->event_pool.push_back(p.b);
-    }
-    h->pending.clear();
-    return MGWR_OK;
-}
-
-int run_gemm(mgwr_ctx *h, const GemmArgs &a_in, int level)
-{
-    GemmArgs a = a_in;
+    GemmArgs a;
+    a.mode = mode;
     a.part = h->part;
     a.part_cap = h->part_cap;
-    if (!h->prof) {
-        HIPCHK(launch_toep_gemm(a, h->stream));
+    a.knobs = h->tune.kn[mode];
+    return a;
+}
+
+// Products of a stage: one grouped launch per kernel class; with profiling
+// on, each class is bracketed by events.
+int run_gemms(Exec &ex, const std::vector<GemmArgs> &as, int level)
+{
+    if (as.empty()) return MGWR_OK;
+    if (!ex.prof || !ex.prof->on || ex.record()) {
+        HIPCHK(launch_toep_gemm(as, ex.st, ex.s));
         return MGWR_OK;
     }
-    mgwr_ctx::Pending p;
-    p.a = take_event(h);
-    p.b = take_event(h);
-    if (!p.a || !p.b) return fail(MGWR_EDEVICE, "hipEventCreate failed");
-    p.rec.kernel = kernel_id(a); p.rec.level = level; p.rec.M = a.M; p.rec.P = a.P; p.rec.K = a.K;
-    p.rec.flops = product_flops(a); p.rec.ms = 0;
-    HIPCHK(hipEventRecord(p.a, h->stream));
-    HIPCHK(launch_toep_gemm(a, h->stream));
-    HIPCHK(hipEventRecord(p.b, h->stream));
-    h->pending.push_back(p);
-    if (h->pending.size() >= 4096) CHK(resolve_profile(h));
+    std::map<int, std::vector<GemmArgs>> cls;
+    for (const GemmArgs &a : as)
+        if (a.M > 0 && a.P > 0) cls[kernel_id(a)].push_back(a);
+    for (auto &kv : cls) {
+        Profiler::Pending p;
+        p.a = ex.prof->take();
+        p.b = ex.prof->take();
+        if (!p.a || !p.b) return fail(MGWR_EDEVICE, "hipEventCreate failed");
+        const GemmArgs &a0 = kv.second[0];
+        p.rec.kernel = kv.first; p.rec.level = level; p.rec.M = a0.M; p.rec.K = a0.K;
+        p.rec.P = 0; p.rec.flops = 0; p.rec.ms = 0;
+        for (const GemmArgs &a : kv.second) { p.rec.P += a.P; p.rec.flops += product_flops(a); }
+        HIPCHK(hipEventRecord(p.a, ex.s));
+        HIPCHK(launch_toep_gemm(kv.second, ex.st, ex.s));
+        HIPCHK(hipEventRecord(p.b, ex.s));
+        ex.prof->pending.push_back(p);
+    }
+    if (ex.prof->pending.size() >= 4096) CHK(ex.prof->resolve(ex.s));
     return MGWR_OK;
 }
 
@@ -300,59 +430,94 @@ int check_opts(const mgwr_options *o)
     if (o->precision < MGWR_FP64 || o->precision > MGWR_FP64_REFINED)
         return fail(MGWR_EINVAL, "bad precision");
     if (o->first_colour != 0 && o->first_colour != 1) return fail(MGWR_EINVAL, "first_colour must be 0 or 1");
-    if (o->smoother != MGWR_SMOOTH_INVERSE && o->smoother != MGWR_SMOOTH_DC)
+    if (o->smoother != MGWR_SMOOTH_INVERSE && o->smoother != MGWR_SMOOTH_DC && o->smoother != MGWR_SMOOTH_AUTO)
         return fail(MGWR_EINVAL, "bad smoother");
-    if (o->smoother == MGWR_SMOOTH_DC)
-        return fail(MGWR_EINVAL, "divide-and-conquer smoother is not available in this build");
+    if (o->dc_block != 0 && (o->dc_block < 128 || o->dc_block % 128 != 0))
+        return fail(MGWR_EINVAL, "dc_block must be 0 or a positive multiple of 128 (got %d)", o->dc_block);
     if (!(o->L > 0) || !std::isfinite(o->L)) return fail(MGWR_EINVAL, "L must be positive");
     if (!(o->stall >= 0) || o->stall >= 1.0) return fail(MGWR_EINVAL, "stall must be in [0, 1)");
+    if (o->graph != 0 && o->graph != 1) return fail(MGWR_EINVAL, "graph must be 0 or 1");
     return MGWR_OK;
 }
 
-// Allocate the buffers the refinement with precision `prec` needs.  The
-// inner hierarchy is FP64 in every precision; FP32 / split-BF16 appear only
-// as product operands.
-int alloc_inner(mgwr_t h, int prec)
+// Base block of the line solve on level lev (0: one product with the inverse
+// column).  A block that covers all M rows is the inverse-column solve.
+int dc_block_of(const mgwr_ctx *h, int lev)
 {
-    if (h->inner_prec == prec) return MGWR_OK;
+    int b = 0;
+    if (h->opt.smoother == MGWR_SMOOTH_DC)
+        b = h->opt.dc_block > 0 ? h->opt.dc_block : (h->tune.tuned ? h->lv[lev].dc_tuned : kDcDefault);
+    else if (h->opt.smoother == MGWR_SMOOTH_AUTO)
+        b = h->tune.tuned ? h->lv[lev].dc_tuned : 0;
+    return (b > 0 && b < h->M) ? b : 0;
+}
+
+bool uses_dc(const mgwr_ctx *h)
+{
+    return h->opt.smoother != MGWR_SMOOTH_INVERSE;
+}
+
+// Buffers the cycle in precision `prec` needs: the inner hierarchy of the
+// refinement (FP64 in every precision; FP32 / split-BF16 appear only as
+// product operands) and, when the smoother may use D&C, its panels.
+int alloc_inner(mgwr_t h, int prec, bool dc)
+{
+    if (h->inner_prec == prec && h->inner_dc == (int)dc) return MGWR_OK;
+    HIPCHK(hipDeviceSynchronize());
     free_list(h->inner_alloc);
     for (auto &L : h->lv) { L.e = nullptr; L.fe = nullptr; }
     h->rs64 = nullptr; h->panel32 = nullptr; h->op32 = nullptr;
     h->pk_hi = h->pk_lo = nullptr;
+    h->xpanel = nullptr; h->xop32 = nullptr; h->xpk_hi = h->xpk_lo = nullptr;
     h->inner_prec = -1;
     const long M = h->M;
     const int nl = (int)h->lv.size();
     const long Pf = h->lv.back().P;
+    auto &A = h->inner_alloc;
     if (prec != MGWR_FP64) {
         for (int l = 0; l < nl; ++l) {
-            CHK(dmalloc(h, h->inner_alloc, (void **)&h->lv[l].e, sizeof(double) * M * h->lv[l].P));
-            if (l < nl - 1)
-                CHK(dmalloc(h, h->inner_alloc, (void **)&h->lv[l].fe, sizeof(double) * M * h->lv[l].P));
+            CHK(dmalloc(A, (void **)&h->lv[l].e, sizeof(double) * M * h->lv[l].P));
+            if (l < nl - 1) CHK(dmalloc(A, (void **)&h->lv[l].fe, sizeof(double) * M * h->lv[l].P));
         }
         h->lv.back().fe = h->res64;   // the outer residual is the finest right-hand side
-        CHK(dmalloc(h, h->inner_alloc, (void **)&h->rs64, sizeof(double) * M * Pf));
+        CHK(dmalloc(A, (void **)&h->rs64, sizeof(double) * M * Pf));
     }
-    if (prec == MGWR_MIXED_FP32 || prec == MGWR_MIXED_BF16X3) {
-        CHK(dmalloc(h, h->inner_alloc, (void **)&h->panel32, sizeof(float) * M * h->maxPc));
-        CHK(dmalloc(h, h->inner_alloc, (void **)&h->op32, sizeof(float) * M * Pf));
+    const bool low = (prec == MGWR_MIXED_FP32 || prec == MGWR_MIXED_BF16X3);
+    if (low) {
+        CHK(dmalloc(A, (void **)&h->panel32, sizeof(float) * M * h->maxPc));
+        CHK(dmalloc(A, (void **)&h->op32, sizeof(float) * M * Pf));
     }
+    h->pk_ld = (Pf + 127) / 128 * 128;
+    const size_t pk_bytes = sizeof(uint16_t) * (size_t)h->Mpad * h->pk_ld;
     if (prec == MGWR_MIXED_BF16X3) {
-        h->pk_ld = (Pf + 127) / 128 * 128;
-        size_t bytes = sizeof(uint16_t) * (size_t)h->Mpad * h->pk_ld;
-        CHK(dmalloc(h, h->inner_alloc, (void **)&h->pk_hi, bytes));
-        CHK(dmalloc(h, h->inner_alloc, (void **)&h->pk_lo, bytes));
+        CHK(dmalloc(A, (void **)&h->pk_hi, pk_bytes));
+        CHK(dmalloc(A, (void **)&h->pk_lo, pk_bytes));
+    }
+    if (dc) {
+        CHK(dmalloc(A, (void **)&h->xpanel, sizeof(double) * M * h->maxPc));
+        if (low) CHK(dmalloc(A, (void **)&h->xop32, sizeof(float) * M * h->maxPc));
+        if (prec == MGWR_MIXED_BF16X3) {
+            CHK(dmalloc(A, (void **)&h->xpk_hi, pk_bytes));
+            CHK(dmalloc(A, (void **)&h->xpk_lo, pk_bytes));
+        }
     }
     h->inner_prec = prec;
+    h->inner_dc = dc;
     return MGWR_OK;
 }
 
 // ---------------------------------------------------------------------------
-// One cycle over a hierarchy whose per-level iterate/rhs are given (FP64).
+// A cycle over a hierarchy whose per-level iterate/rhs are given (FP64).
 struct Hier {
-    int prec;                     // precision of the products (enum mgwr_precision)
+    mgwr_ctx *h = nullptr;
+    int prec = MGWR_FP64;         // precision of the products (enum mgwr_precision)
     std::vector<double *> u, f;   // per level
-    const double *g;              // initial condition on the finest level (plain FP64 only)
-    double *rscratch;             // residual scratch [M][P_fine]
+    const double *g = nullptr;    // initial condition on the finest level (plain FP64 only)
+    double *rscratch = nullptr;   // residual scratch [M][P_fine]
+};
+struct Task {
+    Hier *H;
+    int lev;
 };
 
 int level_mode(const Hier &H, long cols)
@@ -362,140 +527,425 @@ int level_mode(const Hier &H, long cols)
     return GM_F32;
 }
 
-// One half-sweep: every point of `colour` on level `lev` gets the solution of
-// (T_M + sigma I) x = b along its time line, as one Toeplitz product with the
-// precomputed inverse column.  In FP64 the product is the whole solve; in
-// FP32 / split-BF16 the right-hand-side kernel writes lambda_0 b (FP64) into
-// the colour's points and the product adds the strictly lower (history) part.
-int half_sweep(mgwr_t h, const Hier &H, int lev, int colour)
+long packed_ld(long cols)
 {
-    Level &L = h->lv[lev];
-    const int Pc = L.Pc[colour];
-    if (Pc == 0) return MGWR_OK;
-    const bool fine = (lev == (int)h->lv.size() - 1);
-    const double *g = fine ? H.g : nullptr;
-    GemmArgs a;
-    a.mode = level_mode(H, Pc);
-    a.M = h->M; a.P = Pc; a.K = h->M; a.off = 0;
-    a.ea.out = H.u[lev]; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n; a.ea.colour = colour;
-    if (a.mode == GM_F64) {
-        HIPCHK(launch_rhs_panel(0, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
-                                0.0, h->panel64, nullptr, Pc, h->stream));
-        a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
-    } else if (a.mode == GM_F32) {
-        HIPCHK(launch_rhs_panel(1, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
-                                L.lam0, h->panel32, nullptr, Pc, h->stream));
-        a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.B = h->panel32; a.ldb = Pc;
-    } else {
-        long ldp = (Pc + 127) / 128 * 128;
-        HIPCHK(launch_rhs_panel(2, h->dims, L.n, colour, h->M, h->Mpad, H.f[lev], H.u[lev], h->cd, g, L.ih2,
-                                L.lam0, h->pk_hi, h->pk_lo, ldp, h->stream));
-        a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+    return (cols + 127) / 128 * 128;
+}
+
+// Divide-and-conquer line solves (Section 5.2) of one colour for several
+// problems at once.  Rows are cut into nb base blocks of Mb; after base block
+// j is solved, the rows of the D&C node split at m = j + 1 (leaves
+// [m - lowbit(m), m + lowbit(m)) clipped to nb, as for a recursive halving)
+// receive the history of leaves [m - lowbit(m), m): B[bottom] -= T X[top],
+// one full Toeplitz block with coefficient offset lowbit(m) Mb.
+struct DcItem {
+    Task t;
+    int colour;
+};
+
+int dc_half_sweep(Exec &ex, const std::vector<DcItem> &items)
+{
+    std::vector<RhsArgs> rhs;
+    int nbmax = 0;
+    for (const DcItem &d : items) {
+        mgwr_ctx *h = d.t.H->h;
+        Level &L = h->lv[d.t.lev];
+        const bool fine = (d.t.lev == (int)h->lv.size() - 1);
+        const int Pc = L.Pc[d.colour];
+        rhs.push_back(RhsArgs{0, h->dims, L.n, d.colour, h->M, h->Mpad, d.t.H->f[d.t.lev], d.t.H->u[d.t.lev],
+                              h->cd, fine ? d.t.H->g : nullptr, L.ih2, 0.0, h->panel64, nullptr, Pc});
+        const int Mb = dc_block_of(h, d.t.lev);
+        nbmax = std::max(nbmax, (h->M + Mb - 1) / Mb);
     }
-    CHK(run_gemm(h, a, lev));
+    HIPCHK(launch_rhs(rhs, ex.st, ex.s));
+    for (int j = 0; j < nbmax; ++j) {
+        std::vector<OperandArgs> prep, xconv;
+        std::vector<GemmArgs> leaf, upd;
+        int level = -1;
+        for (const DcItem &d : items) {
+            mgwr_ctx *h = d.t.H->h;
+            Level &L = h->lv[d.t.lev];
+            level = d.t.lev;
+            const int Mb = dc_block_of(h, d.t.lev), nb = (h->M + Mb - 1) / Mb;
+            if (j >= nb) continue;
+            const int Pc = L.Pc[d.colour];
+            const long ldp = packed_ld(Pc);
+            const int mode = level_mode(*d.t.H, Pc);
+            const int a0 = j * Mb, cnt = std::min(Mb, h->M - a0);
+            const int cnt32 = (cnt + 31) / 32 * 32;
+            GemmArgs g = gemm_base(h, mode);
+            g.M = cnt; g.P = Pc; g.K = cnt; g.off = 0;
+            g.ea.out = h->xpanel + (long)a0 * Pc; g.ea.ldo = Pc;
+            if (mode == GM_F64) {
+                g.coef = &L.inv; g.epi = EPI_STORE; g.B = h->panel64 + (long)a0 * Pc; g.ldb = Pc;
+            } else if (mode == GM_F32) {
+                prep.push_back(OperandArgs{1, cnt, cnt, Pc, h->panel64 + (long)a0 * Pc, Pc,
+                                           h->op32 + (long)a0 * Pc, nullptr, Pc, h->xpanel + (long)a0 * Pc, L.lam0});
+                g.coef = &L.inv_h; g.epi = EPI_ADD; g.B = h->op32 + (long)a0 * Pc; g.ldb = Pc;
+                if (j + 1 < nb)
+                    xconv.push_back(OperandArgs{1, cnt, cnt, Pc, h->xpanel + (long)a0 * Pc, Pc,
+                                                h->xop32 + (long)a0 * Pc, nullptr, Pc, nullptr, 0.0});
+            } else {
+                prep.push_back(OperandArgs{2, cnt, cnt32, Pc, h->panel64 + (long)a0 * Pc, Pc, h->pk_hi + a0 * ldp,
+                                           h->pk_lo + a0 * ldp, ldp, h->xpanel + (long)a0 * Pc, L.lam0});
+                g.coef = &L.inv_h; g.epi = EPI_ADD;
+                g.Bhi = h->pk_hi + a0 * ldp; g.Blo = h->pk_lo + a0 * ldp; g.ldb = ldp;
+                if (j + 1 < nb)
+                    xconv.push_back(OperandArgs{2, cnt, cnt32, Pc, h->xpanel + (long)a0 * Pc, Pc,
+                                                h->xpk_hi + a0 * ldp, h->xpk_lo + a0 * ldp, ldp, nullptr, 0.0});
+            }
+            leaf.push_back(g);
+            if (j + 1 < nb) {
+                const int m = j + 1, lb = m & -m, l0 = m - lb, l1 = std::min(m + lb, nb);
+                const int r0 = m * Mb, r1 = std::min(l1 * Mb, h->M), k0 = l0 * Mb;
+                GemmArgs u = gemm_base(h, mode);
+                u.M = r1 - r0; u.P = Pc; u.K = lb * Mb; u.off = lb * Mb; u.coef = &h->tm;
+                u.epi = EPI_SUB; u.ea.out = h->panel64 + (long)r0 * Pc; u.ea.ldo = Pc;
+                if (mode == GM_F64) { u.B = h->xpanel + (long)k0 * Pc; u.ldb = Pc; }
+                else if (mode == GM_F32) { u.B = h->xop32 + (long)k0 * Pc; u.ldb = Pc; }
+                else { u.Bhi = h->xpk_hi + k0 * ldp; u.Blo = h->xpk_lo + k0 * ldp; u.ldb = ldp; }
+                upd.push_back(u);
+            }
+        }
+        HIPCHK(launch_operand(prep, ex.st, ex.s));
+        CHK(run_gemms(ex, leaf, level));
+        HIPCHK(launch_operand(xconv, ex.st, ex.s));
+        CHK(run_gemms(ex, upd, level));
+    }
+    std::vector<ScatterArgs> sc;
+    for (const DcItem &d : items) {
+        mgwr_ctx *h = d.t.H->h;
+        Level &L = h->lv[d.t.lev];
+        sc.push_back(ScatterArgs{h->dims, L.n, d.colour, h->M, L.Pc[d.colour], h->xpanel, d.t.H->u[d.t.lev]});
+    }
+    HIPCHK(launch_scatter(sc, ex.st, ex.s));
     return MGWR_OK;
 }
 
-int sweep(mgwr_t h, const Hier &H, int lev)
+// One half-sweep (colour `rank` 0 = first, 1 = second) of every task: every
+// point of the colour gets the solution of (T_M + sigma I) x = b along its
+// time line.  Inverse-column solve: in FP64 the product is the whole solve;
+// in FP32 / split-BF16 the right-hand-side kernel writes lambda_0 b (FP64)
+// into the colour's points and the product adds the history part.
+int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
 {
-    const int c0 = h->opt.first_colour;
-    CHK(half_sweep(h, H, lev, c0));
-    CHK(half_sweep(h, H, lev, 1 - c0));
+    std::vector<RhsArgs> rhs;
+    std::vector<GemmArgs> prods;
+    std::vector<DcItem> dcs;
+    int level = -1;
+    for (const Task &t : ts) {
+        mgwr_ctx *h = t.H->h;
+        Level &L = h->lv[t.lev];
+        const int colour = rank == 0 ? h->opt.first_colour : 1 - h->opt.first_colour;
+        const int Pc = L.Pc[colour];
+        if (Pc == 0) continue;
+        level = t.lev;
+        if (dc_block_of(h, t.lev) > 0) {
+            dcs.push_back(DcItem{t, colour});
+            continue;
+        }
+        const bool fine = (t.lev == (int)h->lv.size() - 1);
+        const double *g = fine ? t.H->g : nullptr;
+        const int mode = level_mode(*t.H, Pc);
+        GemmArgs a = gemm_base(h, mode);
+        a.M = h->M; a.P = Pc; a.K = h->M; a.off = 0;
+        a.ea.out = t.H->u[t.lev]; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n; a.ea.colour = colour;
+        if (mode == GM_F64) {
+            rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
+                                  L.ih2, 0.0, h->panel64, nullptr, Pc});
+            a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
+        } else if (mode == GM_F32) {
+            rhs.push_back(RhsArgs{1, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
+                                  L.ih2, L.lam0, h->panel32, nullptr, Pc});
+            a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.B = h->panel32; a.ldb = Pc;
+        } else {
+            const long ldp = packed_ld(Pc);
+            rhs.push_back(RhsArgs{2, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
+                                  L.ih2, L.lam0, h->pk_hi, h->pk_lo, ldp});
+            a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+        }
+        prods.push_back(a);
+    }
+    HIPCHK(launch_rhs(rhs, ex.st, ex.s));
+    CHK(run_gemms(ex, prods, level));
+    if (!dcs.empty()) CHK(dc_half_sweep(ex, dcs));
     return MGWR_OK;
 }
 
-// out = f + c d g - T_M u - A_h u on level lev: the Toeplitz product (all
-// of T_M u in FP64, its history part otherwise) stored into out, then the
+int sweep(Exec &ex, const std::vector<Task> &ts)
+{
+    if (ts.empty()) return MGWR_OK;
+    CHK(half_sweep(ex, ts, 0));
+    CHK(half_sweep(ex, ts, 1));
+    return MGWR_OK;
+}
+
+// out = f + c d g - T_M u - A_h u on each task's level: the Toeplitz product
+// (all of T_M u in FP64, its history part otherwise) stored into out, then the
 // stencil part and the diagonal r_1 u applied by a bandwidth kernel.
-int level_residual(mgwr_t h, const Hier &H, int lev, double *out)
+int level_residual(Exec &ex, const std::vector<Task> &ts)
 {
-    Level &L = h->lv[lev];
-    const bool fine = (lev == (int)h->lv.size() - 1);
-    GemmArgs a;
-    a.mode = level_mode(H, L.P);
-    a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0;
-    a.epi = EPI_STORE;
-    a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
-    const double diag = (a.mode == GM_F64) ? 0.0 : h->c;
-    if (a.mode == GM_F64) {
-        a.coef = &h->tm; a.B = H.u[lev]; a.ldb = L.P;
-    } else if (a.mode == GM_F32) {
-        HIPCHK(launch_operand(1, h->M, h->Mpad, (int)L.P, H.u[lev], h->op32, nullptr, L.P, h->stream));
-        a.coef = &h->tm_h; a.B = h->op32; a.ldb = L.P;
-    } else {
-        long ldp = (L.P + 127) / 128 * 128;
-        HIPCHK(launch_operand(2, h->M, h->Mpad, (int)L.P, H.u[lev], h->pk_hi, h->pk_lo, ldp, h->stream));
-        a.coef = &h->tm_h; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+    std::vector<OperandArgs> ops;
+    std::vector<GemmArgs> prods;
+    std::vector<PostArgs> posts;
+    int level = -1;
+    for (const Task &t : ts) {
+        mgwr_ctx *h = t.H->h;
+        Level &L = h->lv[t.lev];
+        const bool fine = (t.lev == (int)h->lv.size() - 1);
+        level = t.lev;
+        const int mode = level_mode(*t.H, L.P);
+        double *out = t.H->rscratch;
+        GemmArgs a = gemm_base(h, mode);
+        a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.epi = EPI_STORE;
+        a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
+        if (mode == GM_F64) {
+            a.coef = &h->tm; a.B = t.H->u[t.lev]; a.ldb = L.P;
+        } else if (mode == GM_F32) {
+            ops.push_back(OperandArgs{1, h->M, h->M, (int)L.P, t.H->u[t.lev], L.P, h->op32, nullptr, L.P, nullptr, 0.0});
+            a.coef = &h->tm_h; a.B = h->op32; a.ldb = L.P;
+        } else {
+            const long ldp = packed_ld(L.P);
+            ops.push_back(OperandArgs{2, h->M, h->Mpad, (int)L.P, t.H->u[t.lev], L.P, h->pk_hi, h->pk_lo, ldp,
+                                      nullptr, 0.0});
+            a.coef = &h->tm_h; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+        }
+        prods.push_back(a);
+        posts.push_back(PostArgs{h->dims, L.n, h->M, t.H->f[t.lev], t.H->u[t.lev], nullptr, h->cd,
+                                 fine ? t.H->g : nullptr, L.ih2, (mode == GM_F64) ? 0.0 : h->c, out});
     }
-    CHK(run_gemm(h, a, lev));
-    HIPCHK(launch_resid_post(h->dims, L.n, h->M, H.f[lev], H.u[lev], nullptr, h->cd, fine ? H.g : nullptr,
-                             L.ih2, diag, out, h->stream));
+    HIPCHK(launch_operand(ops, ex.st, ex.s));
+    CHK(run_gemms(ex, prods, level));
+    HIPCHK(launch_post(posts, ex.st, ex.s));
     return MGWR_OK;
 }
 
-int cycle(mgwr_t h, const Hier &H, int lev)
+// One cycle of Algorithm 1 for every task (each on its own level): the tasks
+// at their coarsest level do the exact one-point solve while the others
+// pre-smooth, then the others recurse together.
+int cycle(Exec &ex, const std::vector<Task> &ts)
 {
-    const mgwr_options &o = h->opt;
-    if (lev == 0) return sweep(h, H, 0);
-    for (int i = 0; i < o.nu1; ++i) CHK(sweep(h, H, lev));
-    Level &L = h->lv[lev];
-    CHK(level_residual(h, H, lev, H.rscratch));
-    HIPCHK(launch_restrict(h->dims, L.n, h->M, H.rscratch, H.f[lev - 1], h->stream));
-    HIPCHK(launch_fill(h->M, h->lv[lev - 1].P, nullptr, H.u[lev - 1], h->stream));
-    for (int k = 0; k < o.gamma; ++k) CHK(cycle(h, H, lev - 1));
-    HIPCHK(launch_prolong_add(h->dims, h->lv[lev - 1].n, h->M, H.u[lev - 1], H.u[lev], h->stream));
-    for (int i = 0; i < o.nu2; ++i) CHK(sweep(h, H, lev));
+    if (ts.empty()) return MGWR_OK;
+    std::vector<Task> fine;
+    int nu1 = 0, nu2 = 0, gam = 0;
+    for (const Task &t : ts) {
+        const mgwr_options &o = t.H->h->opt;
+        if (t.lev > 0) {
+            fine.push_back(t);
+            nu1 = std::max(nu1, o.nu1);
+            nu2 = std::max(nu2, o.nu2);
+            gam = std::max(gam, o.gamma);
+        } else {
+            nu1 = std::max(nu1, 1);
+        }
+    }
+    for (int i = 0; i < nu1; ++i) {
+        std::vector<Task> sel;
+        for (const Task &t : ts)
+            if ((t.lev > 0 && i < t.H->h->opt.nu1) || (t.lev == 0 && i == 0)) sel.push_back(t);
+        CHK(sweep(ex, sel));
+    }
+    if (fine.empty()) return MGWR_OK;
+    CHK(level_residual(ex, fine));
+    std::vector<XferArgs> rs, pr;
+    std::vector<FillArgs> zs;
+    for (const Task &t : fine) {
+        mgwr_ctx *h = t.H->h;
+        rs.push_back(XferArgs{0, h->dims, h->lv[t.lev].n, h->M, t.H->rscratch, t.H->f[t.lev - 1]});
+        zs.push_back(FillArgs{h->M, h->lv[t.lev - 1].P, nullptr, nullptr, t.H->u[t.lev - 1], 0});
+        pr.push_back(XferArgs{1, h->dims, h->lv[t.lev - 1].n, h->M, t.H->u[t.lev - 1], t.H->u[t.lev]});
+    }
+    HIPCHK(launch_xfer(rs, ex.st, ex.s));
+    HIPCHK(launch_fill(zs, ex.st, ex.s));
+    for (int k = 0; k < gam; ++k) {
+        std::vector<Task> down;
+        for (const Task &t : fine)
+            if (k < t.H->h->opt.gamma) down.push_back(Task{t.H, t.lev - 1});
+        CHK(cycle(ex, down));
+    }
+    HIPCHK(launch_xfer(pr, ex.st, ex.s));
+    for (int i = 0; i < nu2; ++i) {
+        std::vector<Task> sel;
+        for (const Task &t : fine)
+            if (i < t.H->h->opt.nu2) sel.push_back(t);
+        CHK(sweep(ex, sel));
+    }
     return MGWR_OK;
 }
 
 Hier plain_hier(mgwr_t h, const double *f, const double *g, double *u)
 {
     Hier H;
-    H.prec = MGWR_FP64; H.g = g; H.rscratch = h->res64;
+    H.h = h; H.prec = MGWR_FP64; H.g = g; H.rscratch = h->res64;
     for (auto &L : h->lv) { H.u.push_back(L.u64); H.f.push_back(L.f64); }
     H.u.back() = u; H.f.back() = (double *)f;
     return H;
 }
 
-Hier inner_hier(mgwr_t h)
+Hier inner_hier(mgwr_t h, int prec)
 {
     Hier H;
-    H.prec = h->opt.precision; H.g = nullptr; H.rscratch = h->rs64;
+    H.h = h; H.prec = prec; H.g = nullptr; H.rscratch = h->rs64;
     for (auto &L : h->lv) { H.u.push_back(L.e); H.f.push_back(L.fe); }
     return H;
 }
 
-// FP64 residual of the finest level into res (double-double iterate when lo
-// != nullptr) and its norms (host, synchronising).
+// FP64 residual of the finest level into res64 (double-double iterate when
+// lo != nullptr) and its norms into norm2 (device, 2 doubles).
 // cold: u is the initial iterate g at every time level (lo zero).  Then
 // T_M u = c d_m g exactly (the rows of T_M sum to c d_m), so the product is
 // replaced by writing c d_m g.
-int fine_residual_norms(mgwr_t h, const double *f, const double *g, const double *u, const double *lo,
-                        double *res, double norms[2], bool cold = false)
+struct FineRes {
+    mgwr_ctx *h;
+    const double *f, *g, *u, *lo;
+    bool cold;
+    double *norm2;   // nullptr: no norms
+    double *out;     // nullptr: the handle's residual buffer
+};
+
+int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
 {
-    Level &L = h->lv.back();
-    if (cold) {
-        HIPCHK(launch_scaled_fill(h->M, L.P, h->cd, g, res, h->stream));
+    std::vector<GemmArgs> prods;
+    std::vector<FillArgs> fills;
+    std::vector<PostArgs> posts;
+    std::vector<NormArgs> norms;
+    int level = -1;
+    for (const FineRes &r : v) {
+        mgwr_ctx *h = r.h;
+        Level &L = h->lv.back();
+        level = (int)h->lv.size() - 1;
+        double *out = r.out ? r.out : h->res64;
+        if (r.cold) {
+            fills.push_back(FillArgs{h->M, L.P, h->cd, r.g, out, 1});
+        } else {
+            GemmArgs a = gemm_base(h, GM_F64);
+            a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm; a.epi = EPI_STORE;
+            a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
+            a.B = r.u; a.ldb = L.P;
+            prods.push_back(a);
+        }
+        posts.push_back(PostArgs{h->dims, L.n, h->M, r.f, r.u, r.lo, h->cd, r.g, L.ih2, 0.0, out});
+        if (r.norm2) {
+            const long n = (long)h->M * L.P;
+            norms.push_back(NormArgs{n, out, h->partials, norm_partial_blocks(n), r.norm2});
+        }
+    }
+    HIPCHK(launch_fill(fills, ex.st, ex.s));
+    CHK(run_gemms(ex, prods, level));
+    HIPCHK(launch_post(posts, ex.st, ex.s));
+    HIPCHK(launch_norms(norms, ex.st, ex.s));
+    return MGWR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Programs: run `body` on the runner's stream.  With graphs on (and no
+// profiling), the body is recorded once per key: argument arrays into an
+// arena of its own, launches captured on a private stream into a graph that
+// is replayed on the caller's stream.  Otherwise it runs eagerly (two passes
+// when a list has more than one entry).
+using Body = std::function<int(Exec &)>;
+
+int run_eager(Runner &R, const Body &body)
+{
+    if (R.count == 1) {
+        Exec ex{R.stream, nullptr, &R.prof};
+        return body(ex);
+    }
+    Staging st;
+    st.record = true;
+    Exec rec{R.stream, &st, nullptr};
+    CHK(body(rec));
+    if (!st.host.empty()) {
+        // earlier launches on the stream may still read the arena
+        HIPCHK(hipStreamSynchronize(R.stream));
+        if (st.host.size() > R.arena_cap) {
+            if (R.arena) hipFree(R.arena);
+            R.arena = nullptr;
+            R.arena_cap = 0;
+            HIPCHK(hipMalloc((void **)&R.arena, st.host.size()));
+            R.arena_cap = st.host.size();
+        }
+        HIPCHK(hipMemcpy(R.arena, st.host.data(), st.host.size(), hipMemcpyHostToDevice));
+    }
+    st.record = false;
+    st.dev = R.arena;
+    st.cursor = 0;
+    Exec ex{R.stream, &st, &R.prof};
+    return body(ex);
+}
+
+int run_program(Runner &R, const std::string &key, const Body &body)
+{
+    if (!R.graphs || R.prof.on) return run_eager(R, body);
+    auto it = R.progs.find(key);
+    if (it == R.progs.end()) {
+        if (R.progs.size() >= 8) {   // keep the 8 most recent
+            HIPCHK(hipStreamSynchronize(R.stream));
+            drop_program(R.progs[R.lru.front()]);
+            R.progs.erase(R.lru.front());
+            R.lru.pop_front();
+        }
+        if (!R.capture) HIPCHK(hipStreamCreateWithFlags(&R.capture, hipStreamNonBlocking));
+        Program p;
+        Staging st;
+        if (R.count > 1) {
+            st.record = true;
+            Exec rec{R.capture, &st, nullptr};
+            CHK(body(rec));
+            if (!st.host.empty()) {
+                HIPCHK(hipMalloc((void **)&p.arena, st.host.size()));
+                hipError_t e = hipMemcpy(p.arena, st.host.data(), st.host.size(), hipMemcpyHostToDevice);
+                if (e != hipSuccess) {
+                    drop_program(p);
+                    HIPCHK(e);
+                }
+            }
+            st.record = false;
+            st.dev = p.arena;
+            st.cursor = 0;
+        }
+        Exec ex{R.capture, R.count > 1 ? &st : nullptr, nullptr};
+        HIPCHK(hipStreamBeginCapture(R.capture, hipStreamCaptureModeThreadLocal));
+        int rc = body(ex);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(R.capture, &graph);
+        if (rc < 0 || e != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            drop_program(p);
+            if (rc < 0) return rc;
+            HIPCHK(e);
+        }
+        p.graph = graph;
+        e = hipGraphInstantiate(&p.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_program(p);
+            HIPCHK(e);
+        }
+        it = R.progs.emplace(key, p).first;
+        R.lru.push_back(key);
     } else {
-        GemmArgs a;
-        a.mode = GM_F64;
-        a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm;
-        a.epi = EPI_STORE;
-        a.ea.out = res; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
-        a.B = u; a.ldb = L.P;
-        CHK(run_gemm(h, a, (int)h->lv.size() - 1));
+        R.lru.remove(key);
+        R.lru.push_back(key);
     }
-    HIPCHK(launch_resid_post(h->dims, L.n, h->M, f, u, lo, h->cd, g, L.ih2, 0.0, res, h->stream));
-    if (norms) {
-        int nblk = 0;
-        HIPCHK(launch_norm_partials((long)h->M * L.P, res, h->partials, &nblk, h->stream));
-        HIPCHK(launch_norm_final(nblk, h->partials, h->norms_dev, h->stream));
-        HIPCHK(hipMemcpyAsync(h->norms_host, h->norms_dev, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                              h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        norms[0] = h->norms_host[0];
-        norms[1] = h->norms_host[1];
-    }
+    HIPCHK(hipGraphLaunch(it->second.exec, R.stream));
+    return MGWR_OK;
+}
+
+std::string prog_key(const char *kind, const std::vector<int> &active, const std::vector<const void *> &ptrs)
+{
+    std::string k(kind);
+    char buf[32];
+    for (int a : active) { snprintf(buf, sizeof buf, ",%d", a); k += buf; }
+    k += "|";
+    for (const void *p : ptrs) { snprintf(buf, sizeof buf, "%p,", p); k += buf; }
+    return k;
+}
+
+int read_norms(Runner &R)
+{
+    HIPCHK(hipMemcpyAsync(R.norms_host, R.norms_dev, sizeof(double) * 2 * R.count, hipMemcpyDeviceToHost,
+                          R.stream));
+    HIPCHK(hipStreamSynchronize(R.stream));
     return MGWR_OK;
 }
 
@@ -512,6 +962,326 @@ int set_device(mgwr_t h)
     return MGWR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The solve of a group of problems (one handle, or a batch) in lockstep: one
+// outer iteration (a cycle on u, or a refinement step, and the new residual)
+// for every problem that has not stopped, then one read of all norms.
+struct SolveState {
+    int it = 0, status = MGWR_NOT_CONVERGED, slow = 0;
+    double r0 = 0, prev = 0, rn = 0;
+    bool done = false;
+    mgwr_info inf;
+};
+
+void update_state(SolveState &S, const mgwr_options &o, const double nrm[2], double tol)
+{
+    S.rn = nrm[o.norm];
+    if (!std::isfinite(nrm[1]) || !std::isfinite(S.rn)) {
+        S.status = MGWR_ENONFINITE;
+        S.done = true;
+        return;
+    }
+    if (S.it < 128) S.inf.hist[S.it] = S.rn;
+    if (S.it == 0) S.r0 = S.rn;
+    if (S.rn <= tol * S.r0) { S.status = MGWR_OK; S.done = true; return; }
+    if (S.it > 0 && S.rn > 1e6 * S.r0) { S.status = MGWR_EDIVERGED; S.done = true; return; }
+    // Stagnation: a cycle that does not reduce the residual by the factor
+    // `stall`.  Near the rounding floor (below 1e-6 r0) one such cycle ends
+    // the solve; above it three in a row do (a refinement step may raise the
+    // residual once while it removes the smooth error).
+    if (S.it > 0 && o.stall > 0 && S.rn > o.stall * S.prev) {
+        ++S.slow;
+        if (S.rn < 1e-6 * S.r0 || S.slow >= 3) { S.status = MGWR_STAGNATED; S.done = true; return; }
+    } else {
+        S.slow = 0;
+    }
+    if (S.it >= o.maxit) { S.status = MGWR_NOT_CONVERGED; S.done = true; return; }
+    S.prev = S.rn;
+}
+
+int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *const *f, const double *const *g,
+                double *const *u, double tol, mgwr_info *infos)
+{
+    const int n = (int)hs.size();
+    for (mgwr_ctx *h : hs) CHK(alloc_inner(h, h->opt.precision, uses_dc(h)));
+    std::vector<Hier> Hp(n), Hi(n);
+    std::vector<SolveState> S(n);
+    std::vector<const void *> ptrs;
+    for (int i = 0; i < n; ++i) {
+        mgwr_ctx *h = hs[i];
+        Hp[i] = plain_hier(h, f[i], g ? g[i] : nullptr, u[i]);
+        if (h->opt.precision != MGWR_FP64) Hi[i] = inner_hier(h, h->opt.precision);
+        memset(&S[i].inf, 0, sizeof(mgwr_info));
+        ptrs.push_back(f[i]);
+        ptrs.push_back(g ? g[i] : nullptr);
+        ptrs.push_back(u[i]);
+    }
+    auto refine = [&](int i) { return hs[i]->opt.precision != MGWR_FP64; };
+    auto fine_res = [&](int i, bool cold) {
+        mgwr_ctx *h = hs[i];
+        return FineRes{h, f[i], g ? g[i] : nullptr, u[i], refine(i) ? h->ulo : nullptr, cold, R.norms_dev + 2 * i,
+                       nullptr};
+    };
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i) all[i] = i;
+
+    // initial iterate u^0 = g at every time level (Section 3), lo = 0, and
+    // the initial residual
+    Body init = [&](Exec &ex) -> int {
+        std::vector<FillArgs> fills;
+        std::vector<FineRes> res;
+        for (int i = 0; i < n; ++i) {
+            mgwr_ctx *h = hs[i];
+            const long P = h->lv.back().P;
+            if (!h->opt.warm_start) fills.push_back(FillArgs{h->M, P, nullptr, g ? g[i] : nullptr, u[i], 0});
+            if (refine(i)) fills.push_back(FillArgs{h->M, P, nullptr, nullptr, h->ulo, 0});
+            res.push_back(fine_res(i, !h->opt.warm_start));
+        }
+        HIPCHK(launch_fill(fills, ex.st, ex.s));
+        return fine_residuals(ex, res);
+    };
+    CHK(run_program(R, prog_key("init", all, ptrs), init));
+    CHK(read_norms(R));
+    for (int i = 0; i < n; ++i) update_state(S[i], hs[i]->opt, R.norms_host + 2 * i, tol);
+
+    for (;;) {
+        std::vector<int> act;
+        for (int i = 0; i < n; ++i)
+            if (!S[i].done) act.push_back(i);
+        if (act.empty()) break;
+        Body step = [&](Exec &ex) -> int {
+            std::vector<Task> plain, inner;
+            std::vector<FillArgs> zero;
+            std::vector<DDArgs> upd;
+            std::vector<FineRes> res;
+            for (int i : act) {
+                mgwr_ctx *h = hs[i];
+                const int top = (int)h->lv.size() - 1;
+                if (!refine(i)) {
+                    plain.push_back(Task{&Hp[i], top});
+                } else {
+                    Level &L = h->lv.back();
+                    inner.push_back(Task{&Hi[i], top});
+                    zero.push_back(FillArgs{h->M, L.P, nullptr, nullptr, L.e, 0});
+                    upd.push_back(DDArgs{(long)h->M * L.P, L.e, u[i], h->ulo});
+                }
+                res.push_back(fine_res(i, false));
+            }
+            CHK(cycle(ex, plain));
+            HIPCHK(launch_fill(zero, ex.st, ex.s));
+            CHK(cycle(ex, inner));
+            HIPCHK(launch_dd_update(upd, ex.st, ex.s));
+            return fine_residuals(ex, res);
+        };
+        CHK(run_program(R, prog_key("iter", act, ptrs), step));
+        CHK(read_norms(R));
+        for (int i : act) {
+            ++S[i].it;
+            update_state(S[i], hs[i]->opt, R.norms_host + 2 * i, tol);
+        }
+    }
+    HIPCHK(hipStreamSynchronize(R.stream));
+    int worst = MGWR_OK;
+    for (int i = 0; i < n; ++i) {
+        SolveState &s = S[i];
+        s.inf.iters = s.it;
+        s.inf.status = s.status;
+        s.inf.r0 = s.r0;
+        s.inf.rk = s.rn;
+        s.inf.relres = s.r0 > 0 ? s.rn / s.r0 : 0.0;
+        s.inf.mean_factor = (s.it > 0 && s.r0 > 0) ? std::pow(s.rn / s.r0, 1.0 / s.it) : 0.0;
+        if (infos) infos[i] = s.inf;
+        if (s.status == MGWR_ENONFINITE)
+            fail(MGWR_ENONFINITE, "problem %d: non-finite residual after %d cycles", i, s.it);
+        else if (s.status == MGWR_EDIVERGED)
+            fail(MGWR_EDIVERGED, "problem %d: residual grew from %g to %g", i, s.r0, s.rn);
+        if (s.status < 0) worst = std::min(worst, s.status);
+        else if (worst >= 0) worst = std::max(worst, s.status);
+    }
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times one cycle of the error equation (internal buffers only;
+// the caller's arrays are not touched) under candidate tile knobs and D&C
+// base blocks, and keeps the fastest.  Results are shared by every handle of
+// the same shape and options (process-wide cache).
+struct TuneResult {
+    TileKnobs kn[3];
+    std::vector<int> dc;   // per level
+    double ms_default, ms_tuned;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneResult> g_tune_cache;
+
+std::string tune_key(const mgwr_ctx *h)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "d%d N%d M%d p%d s%d b%d", h->dims, h->N, h->M, h->opt.precision, h->opt.smoother,
+             h->opt.dc_block);
+    return buf;
+}
+
+int time_cycle(Runner &R, const std::vector<mgwr_ctx *> &hs, int prec, int reps, double &ms)
+{
+    std::vector<Hier> H(hs.size());
+    for (size_t i = 0; i < hs.size(); ++i) H[i] = inner_hier(hs[i], prec);
+    Body body = [&](Exec &ex) -> int {
+        std::vector<Task> ts;
+        std::vector<FillArgs> zero;
+        for (size_t i = 0; i < hs.size(); ++i) {
+            Level &L = hs[i]->lv.back();
+            ts.push_back(Task{&H[i], (int)hs[i]->lv.size() - 1});
+            zero.push_back(FillArgs{hs[i]->M, L.P, nullptr, nullptr, L.e, 0});
+        }
+        HIPCHK(launch_fill(zero, ex.st, ex.s));
+        return cycle(ex, ts);
+    };
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    ms = 1e30;
+    int rc = MGWR_OK;
+    const bool prof = R.prof.on;
+    R.prof.on = false;
+    for (int r = 0; r < reps && rc == MGWR_OK; ++r) {
+        hipEventRecord(a, R.stream);
+        rc = run_eager(R, body);
+        hipEventRecord(b, R.stream);
+        if (rc == MGWR_OK && hipEventSynchronize(b) == hipSuccess) {
+            float t = 0;
+            hipEventElapsedTime(&t, a, b);
+            ms = std::min(ms, (double)t);
+        }
+    }
+    R.prof.on = prof;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return rc;
+}
+
+int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
+{
+    mgwr_ctx *h0 = hs[0];
+    const std::string key = tune_key(h0);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end() && hs.size() == 1) {
+            for (int m = 0; m < 3; ++m) h0->tune.kn[m] = it->second.kn[m];
+            for (size_t l = 0; l < h0->lv.size(); ++l) h0->lv[l].dc_tuned = it->second.dc[l];
+            h0->tune.ms_default = it->second.ms_default;
+            h0->tune.ms_tuned = it->second.ms_tuned;
+            h0->tune.tuned = true;
+            clear_programs(R);
+            return MGWR_OK;
+        }
+    }
+    const int prec = h0->opt.precision;
+    const int tprec = (prec == MGWR_FP64) ? MGWR_FP64_REFINED : prec;
+    for (mgwr_ctx *h : hs) {
+        CHK(alloc_inner(h, tprec, uses_dc(h)));
+        for (auto &L : h->lv) L.dc_tuned = 0;
+        for (int m = 0; m < 3; ++m) h->tune.kn[m] = TileKnobs{};
+        // the finest right-hand side of the error equation: zeros
+        std::vector<FillArgs> z{FillArgs{h->M, h->lv.back().P, nullptr, nullptr, h->res64, 0}};
+        HIPCHK(launch_fill(z, nullptr, R.stream));
+        h->tune.tuned = true;   // dc_block_of reads the tuned blocks from here on
+    }
+    auto set_kn = [&](int mode, const TileKnobs &k) { for (mgwr_ctx *h : hs) h->tune.kn[mode] = k; };
+    double best = 0;
+    CHK(time_cycle(R, hs, tprec, 2, best));   // also warms up
+    CHK(time_cycle(R, hs, tprec, 2, best));
+    const double ms_default = best;
+    std::vector<int> modes;
+    if (tprec == MGWR_FP64_REFINED) modes = {GM_F64};
+    else if (tprec == MGWR_MIXED_FP32) modes = {GM_F32};
+    else modes = {GM_BF16X3, GM_F32};
+    for (int mode : modes) {
+        if (mode != GM_BF16X3) {
+            TileKnobs k = h0->tune.kn[mode];
+            for (int v : {0, 1}) {
+                TileKnobs c = k;
+                c.variant = v;
+                set_kn(mode, c);
+                double t;
+                CHK(time_cycle(R, hs, tprec, 2, t));
+                if (t < best * 0.995) { best = t; k = c; }
+            }
+            set_kn(mode, k);
+        }
+        TileKnobs k = h0->tune.kn[mode];
+        const int base = (mode == GM_BF16X3) ? 1024 : 2048;
+        for (int tgt : {base / 4, base / 2, base * 2, base * 4}) {
+            TileKnobs c = k;
+            c.split_target = tgt;
+            set_kn(mode, c);
+            double t;
+            CHK(time_cycle(R, hs, tprec, 2, t));
+            if (t < best * 0.995) { best = t; k = c; }
+        }
+        set_kn(mode, k);
+    }
+    // D&C base blocks, level by level from the finest (the same choice for
+    // every problem at the same depth)
+    if (h0->opt.smoother != MGWR_SMOOTH_INVERSE && h0->opt.dc_block == 0) {
+        int depth = 0;
+        for (mgwr_ctx *h : hs) depth = std::max(depth, (int)h->lv.size());
+        std::vector<int> cands;
+        if (h0->opt.smoother == MGWR_SMOOTH_AUTO) cands.push_back(0);
+        for (int b : {4096, 2048, 1024, 512, 256}) cands.push_back(b);
+        for (int d = 0; d < depth; ++d) {
+            auto set_dc = [&](int b) {
+                for (mgwr_ctx *h : hs) {
+                    int l = (int)h->lv.size() - 1 - d;
+                    if (l >= 0) h->lv[l].dc_tuned = b;
+                }
+            };
+            int bestb = (h0->opt.smoother == MGWR_SMOOTH_AUTO) ? 0 : kDcDefault;
+            set_dc(bestb);
+            CHK(time_cycle(R, hs, tprec, 2, best));
+            for (int b : cands) {
+                if (b == bestb) continue;
+                if (b != 0 && b >= h0->M) continue;
+                set_dc(b);
+                double t;
+                CHK(time_cycle(R, hs, tprec, 2, t));
+                if (t < best * 0.995) { best = t; bestb = b; }
+            }
+            set_dc(bestb);
+        }
+    }
+    for (mgwr_ctx *h : hs) {
+        h->tune.ms_default = ms_default;
+        h->tune.ms_tuned = best;
+        CHK(alloc_inner(h, prec, uses_dc(h)));
+    }
+    clear_programs(R);
+    if (hs.size() == 1) {
+        TuneResult tr;
+        for (int m = 0; m < 3; ++m) tr.kn[m] = h0->tune.kn[m];
+        for (auto &L : h0->lv) tr.dc.push_back(L.dc_tuned);
+        tr.ms_default = ms_default;
+        tr.ms_tuned = best;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = tr;
+    }
+    return MGWR_OK;
+}
+
+void tuning_out(const mgwr_ctx *h, mgwr_tuning *t)
+{
+    memset(t, 0, sizeof *t);
+    t->tuned = h->tune.tuned ? 1 : 0;
+    t->variant[0] = h->tune.kn[GM_F64].variant;
+    t->variant[1] = h->tune.kn[GM_F32].variant;
+    for (int m = 0; m < 3; ++m) t->split_target[m] = h->tune.kn[m].split_target;
+    t->levels = (int)h->lv.size();
+    for (int l = 0; l < t->levels && l < 32; ++l) t->dc_block[l] = dc_block_of(h, l);
+    t->ms_default = h->tune.ms_default;
+    t->ms_tuned = h->tune.ms_tuned;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -525,7 +1295,7 @@ int mgwr_default_options(mgwr_options *o)
     memset(o, 0, sizeof *o);
     o->nu1 = 1; o->nu2 = 1; o->gamma = 1; o->maxit = 100; o->norm = MGWR_NORM_MAX;
     o->warm_start = 0; o->precision = MGWR_FP64; o->first_colour = 0;
-    o->smoother = MGWR_SMOOTH_INVERSE; o->dc_block = 0; o->L = 1.0; o->stall = 0.5;
+    o->smoother = MGWR_SMOOTH_INVERSE; o->dc_block = 0; o->L = 1.0; o->stall = 0.5; o->graph = 1;
     return MGWR_OK;
 }
 
@@ -551,11 +1321,10 @@ int mgwr_destroy(mgwr_t h)
     if (!h) return MGWR_OK;
     hipSetDevice(h->device);
     if (h->stream) hipStreamSynchronize(h->stream);
+    hipDeviceSynchronize();
+    release_runner(h->run);
     free_list(h->inner_alloc);
     free_list(h->alloc);
-    if (h->norms_host) hipHostFree(h->norms_host);
-    for (auto &p : h->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
-    for (auto e : h->event_pool) hipEventDestroy(e);
     delete h;
     return MGWR_OK;
 }
@@ -577,6 +1346,7 @@ int mgwr_create_ex(int N, int M, double alpha, double T, int dims, const mgwr_op
 
     mgwr_ctx *h = new mgwr_ctx();
     h->N = N; h->M = M; h->dims = dims; h->alpha = alpha; h->T = T; h->opt = o;
+    h->run.graphs = o.graph != 0;
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return fail(MGWR_EDEVICE, "no HIP device available");
@@ -621,32 +1391,38 @@ int mgwr_create_ex(int N, int M, double alpha, double T, int dims, const mgwr_op
         }
         std::vector<double> cdv(M);
         for (int m = 0; m < M; ++m) cdv[m] = h->c * h->d_host[m + 1];
-        CHK(dmalloc(h, h->alloc, (void **)&h->cd, sizeof(double) * M));
+        CHK(dmalloc(h->alloc, (void **)&h->cd, sizeof(double) * M));
         HIPCHK(hipMemcpy(h->cd, cdv.data(), sizeof(double) * M, hipMemcpyHostToDevice));
         const long Pf = h->lv.back().P;
         for (size_t l = 0; l + 1 < h->lv.size(); ++l) {
-            CHK(dmalloc(h, h->alloc, (void **)&h->lv[l].u64, sizeof(double) * M * h->lv[l].P));
-            CHK(dmalloc(h, h->alloc, (void **)&h->lv[l].f64, sizeof(double) * M * h->lv[l].P));
+            CHK(dmalloc(h->alloc, (void **)&h->lv[l].u64, sizeof(double) * M * h->lv[l].P));
+            CHK(dmalloc(h->alloc, (void **)&h->lv[l].f64, sizeof(double) * M * h->lv[l].P));
         }
-        CHK(dmalloc(h, h->alloc, (void **)&h->res64, sizeof(double) * M * Pf));
-        CHK(dmalloc(h, h->alloc, (void **)&h->panel64, sizeof(double) * M * h->maxPc));
-        CHK(dmalloc(h, h->alloc, (void **)&h->ulo, sizeof(double) * M * Pf));
-        CHK(dmalloc(h, h->alloc, (void **)&h->partials, sizeof(double) * 2 * 2048));
-        // split-K scratch: the largest any product of this hierarchy needs
+        CHK(dmalloc(h->alloc, (void **)&h->res64, sizeof(double) * M * Pf));
+        CHK(dmalloc(h->alloc, (void **)&h->panel64, sizeof(double) * M * h->maxPc));
+        CHK(dmalloc(h->alloc, (void **)&h->ulo, sizeof(double) * M * Pf));
+        CHK(dmalloc(h->alloc, (void **)&h->partials, sizeof(double) * 2 * 2048));
+        // split-K scratch: the largest any lone product of this hierarchy
+        // needs under any tile knobs the tuner tries
         size_t part = 0;
         for (const Level &L : h->lv)
             for (int mode = GM_F64; mode <= GM_BF16X3; ++mode) {
                 long cols[3] = {L.Pc[0], L.Pc[1], L.P};
                 for (long P : cols)
-                    if (P > 0) part = std::max(part, splitk_bytes(mode, M, (int)P, M, 0, M));
+                    for (int tgt : {0, 8192})
+                        for (int v : {0, 1}) {
+                            TileKnobs kn;
+                            kn.variant = v;
+                            kn.split_target = tgt;
+                            if (P > 0) part = std::max(part, splitk_bytes(mode, M, (int)P, M, 0, M, kn));
+                        }
             }
         if (part > 0) {
-            CHK(dmalloc(h, h->alloc, &h->part, part));
+            CHK(dmalloc(h->alloc, &h->part, part));
             h->part_cap = part;
         }
-        CHK(dmalloc(h, h->alloc, (void **)&h->norms_dev, sizeof(double) * 2));
-        HIPCHK(hipHostMalloc((void **)&h->norms_host, 2 * sizeof(double), hipHostMallocDefault));
-        CHK(alloc_inner(h, o.precision));
+        CHK(init_runner(h->run, 1));
+        CHK(alloc_inner(h, o.precision, uses_dc(h)));
         HIPCHK(hipDeviceSynchronize());
         return MGWR_OK;
     }();
@@ -666,8 +1442,19 @@ int mgwr_set_options(mgwr_t h, const mgwr_options *opts)
     CHK(check_opts(opts));
     if (opts->L != h->opt.L) return fail(MGWR_EINVAL, "L is fixed at creation (use mgwr_create_ex)");
     CHK(set_device(h));
-    CHK(alloc_inner(h, opts->precision));
+    clear_programs(h->run);
+    mgwr_options old = h->opt;
     h->opt = *opts;
+    int rc = alloc_inner(h, opts->precision, uses_dc(h));
+    if (rc < 0) {
+        h->opt = old;
+        return rc;
+    }
+    h->run.graphs = opts->graph != 0;
+    if (old.precision != opts->precision || old.smoother != opts->smoother || old.dc_block != opts->dc_block) {
+        h->tune = Tuning{};
+        for (auto &L : h->lv) L.dc_tuned = 0;
+    }
     return MGWR_OK;
 }
 
@@ -682,6 +1469,7 @@ int mgwr_set_stream(mgwr_t h, void *hip_stream)
 {
     if (!h) return fail(MGWR_EINVAL, "NULL handle");
     h->stream = (hipStream_t)hip_stream;
+    h->run.stream = h->stream;
     return MGWR_OK;
 }
 
@@ -708,8 +1496,11 @@ int mgwr_smooth(mgwr_t h, const double *f, const double *g, double *u, int sweep
     CHK(check_ptr(u, "u"));
     if (sweeps < 0) return fail(MGWR_EINVAL, "sweeps must be >= 0");
     CHK(set_device(h));
+    CHK(alloc_inner(h, h->opt.precision, uses_dc(h)));
     Hier H = plain_hier(h, f, g, u);
-    for (int s = 0; s < sweeps; ++s) CHK(sweep(h, H, (int)h->lv.size() - 1));
+    std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
+    Exec ex{h->stream, nullptr, &h->run.prof};
+    for (int s = 0; s < sweeps; ++s) CHK(sweep(ex, ts));
     return MGWR_OK;
 }
 
@@ -720,9 +1511,14 @@ int mgwr_residual(mgwr_t h, const double *f, const double *g, const double *u, d
     CHK(check_ptr(u, "u"));
     CHK(check_ptr(r, "r"));
     CHK(set_device(h));
-    double nrm[2];
-    CHK(fine_residual_norms(h, f, g, u, nullptr, r, norms ? nrm : nullptr));
-    if (norms) { norms[0] = nrm[0]; norms[1] = nrm[1]; }
+    Exec ex{h->stream, nullptr, &h->run.prof};
+    std::vector<FineRes> v{FineRes{h, f, g, u, nullptr, false, norms ? h->run.norms_dev : nullptr, r}};
+    CHK(fine_residuals(ex, v));
+    if (norms) {
+        CHK(read_norms(h->run));
+        norms[0] = h->run.norms_host[0];
+        norms[1] = h->run.norms_host[1];
+    }
     return MGWR_OK;
 }
 
@@ -732,8 +1528,11 @@ int mgwr_vcycle(mgwr_t h, const double *f, const double *g, double *u)
     CHK(check_ptr(f, "f"));
     CHK(check_ptr(u, "u"));
     CHK(set_device(h));
+    CHK(alloc_inner(h, h->opt.precision, uses_dc(h)));
     Hier H = plain_hier(h, f, g, u);
-    return cycle(h, H, (int)h->lv.size() - 1);
+    std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
+    Exec ex{h->stream, nullptr, &h->run.prof};
+    return cycle(ex, ts);
 }
 
 int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol, mgwr_info *info)
@@ -743,71 +1542,25 @@ int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol
     CHK(check_ptr(u, "u"));
     if (!(tol >= 0.0)) return fail(MGWR_EINVAL, "tol must be >= 0");
     CHK(set_device(h));
-    const mgwr_options &o = h->opt;
-    const int prec = o.precision;
-    const bool refine = prec != MGWR_FP64;
-    CHK(alloc_inner(h, prec));
-    const long Pf = h->lv.back().P;
-    const long n = (long)h->M * Pf;
-    if (!o.warm_start) HIPCHK(launch_fill(h->M, Pf, g, u, h->stream));
-    if (refine) HIPCHK(hipMemsetAsync(h->ulo, 0, sizeof(double) * n, h->stream));
-    Hier Hp = plain_hier(h, f, g, u);
-    Hier Hi;
-    if (refine) Hi = inner_hier(h);
+    h->run.stream = h->stream;
+    std::vector<mgwr_ctx *> hs{h};
+    return solve_group(h->run, hs, &f, &g, &u, tol, info);
+}
 
-    mgwr_info inf;
-    memset(&inf, 0, sizeof inf);
-    int status = MGWR_NOT_CONVERGED;
-    double r0 = 0, prev = 0, rn = 0;
-    int it = 0, slow = 0;
-    for (;; ++it) {
-        double nrm[2];
-        CHK(fine_residual_norms(h, f, g, u, refine ? h->ulo : nullptr, h->res64, nrm,
-                                it == 0 && !o.warm_start));
-        rn = nrm[o.norm];
-        if (!std::isfinite(nrm[1]) || !std::isfinite(rn)) {
-            status = MGWR_ENONFINITE;
-            fail(MGWR_ENONFINITE, "non-finite residual after %d cycles", it);
-            break;
-        }
-        if (it < 128) inf.hist[it] = rn;
-        if (it == 0) r0 = rn;
-        if (rn <= tol * r0) { status = MGWR_OK; break; }
-        if (it > 0 && rn > 1e6 * r0) {
-            status = MGWR_EDIVERGED;
-            fail(MGWR_EDIVERGED, "residual grew from %g to %g", r0, rn);
-            break;
-        }
-        // Stagnation: a cycle that does not reduce the residual by the factor
-        // `stall`.  Near the rounding floor (below 1e-6 r0) one such cycle
-        // ends the solve; above it three in a row do (a refinement step may
-        // raise the residual once while it removes the smooth error).
-        if (it > 0 && o.stall > 0 && rn > o.stall * prev) {
-            ++slow;
-            if (rn < 1e-6 * r0 || slow >= 3) { status = MGWR_STAGNATED; break; }
-        } else {
-            slow = 0;
-        }
-        if (it >= o.maxit) { status = MGWR_NOT_CONVERGED; break; }
-        prev = rn;
-        if (!refine) {
-            CHK(cycle(h, Hp, (int)h->lv.size() - 1));
-        } else {
-            Level &L = h->lv.back();
-            HIPCHK(launch_fill(h->M, L.P, nullptr, L.e, h->stream));
-            CHK(cycle(h, Hi, (int)h->lv.size() - 1));
-            HIPCHK(launch_dd_update(n, L.e, u, h->ulo, h->stream));
-        }
-    }
-    HIPCHK(hipStreamSynchronize(h->stream));
-    inf.iters = it;
-    inf.status = status;
-    inf.r0 = r0;
-    inf.rk = rn;
-    inf.relres = r0 > 0 ? rn / r0 : 0.0;
-    inf.mean_factor = (it > 0 && r0 > 0) ? std::pow(rn / r0, 1.0 / it) : 0.0;
-    if (info) *info = inf;
-    return status;
+int mgwr_autotune(mgwr_t h)
+{
+    if (!h) return fail(MGWR_EINVAL, "NULL handle");
+    CHK(set_device(h));
+    h->run.stream = h->stream;
+    std::vector<mgwr_ctx *> hs{h};
+    return autotune_group(h->run, hs);
+}
+
+int mgwr_get_tuning(mgwr_t h, mgwr_tuning *t)
+{
+    if (!h || !t) return fail(MGWR_EINVAL, "NULL argument");
+    tuning_out(h, t);
+    return MGWR_OK;
 }
 
 int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int ldb, int P, double *C,
@@ -821,39 +1574,35 @@ int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int
     if (precision < MGWR_FP64 || precision > MGWR_FP64_REFINED) return fail(MGWR_EINVAL, "bad precision");
     CHK(set_device(h));
     const ToepCoef *coef = which < 0 ? &h->tm : &h->lv[which].inv;
-    GemmArgs a;
+    const int mode = (precision == MGWR_MIXED_FP32) ? GM_F32 : (precision == MGWR_MIXED_BF16X3) ? GM_BF16X3 : GM_F64;
+    GemmArgs a = gemm_base(h, mode);
     a.M = h->M; a.P = P; a.K = h->M; a.off = 0; a.coef = coef; a.epi = EPI_STORE;
     a.ea.out = C; a.ea.ldo = ldc;
-    if (precision == MGWR_FP64 || precision == MGWR_FP64_REFINED) {
-        a.mode = GM_F64; a.B = B; a.ldb = ldb;
-        CHK(run_gemm(h, a, which));
-        return MGWR_OK;
+    Exec ex{h->stream, nullptr, &h->run.prof};
+    if (mode == GM_F64) {
+        a.B = B; a.ldb = ldb;
+        return run_gemms(ex, {a}, which);
     }
-    // FP32 / split-BF16 operands are built from a contiguous FP64 copy (test
-    // path; allocates temporaries)
+    // FP32 / split-BF16 operands are built in temporaries (test path)
     std::vector<void *> tmp;
-    long n = (long)h->M * P;
     int rc = [&]() -> int {
-        double *bd = nullptr;
-        CHK(dmalloc(h, tmp, (void **)&bd, sizeof(double) * n));
-        HIPCHK(hipMemcpy2DAsync(bd, sizeof(double) * P, B, sizeof(double) * ldb, sizeof(double) * P, h->M,
-                                hipMemcpyDeviceToDevice, h->stream));
-        if (precision == MGWR_MIXED_FP32) {
+        if (mode == GM_F32) {
             float *b32 = nullptr;
-            CHK(dmalloc(h, tmp, (void **)&b32, sizeof(float) * n));
-            HIPCHK(launch_operand(1, h->M, h->Mpad, P, bd, b32, nullptr, P, h->stream));
-            a.mode = GM_F32; a.B = b32; a.ldb = P;
+            CHK(dmalloc(tmp, (void **)&b32, sizeof(float) * (size_t)h->M * P));
+            HIPCHK(launch_operand({OperandArgs{1, h->M, h->M, P, B, ldb, b32, nullptr, P, nullptr, 0.0}}, nullptr,
+                                  h->stream));
+            a.B = b32; a.ldb = P;
         } else {
-            long ldp = (P + 127) / 128 * 128;
+            const long ldp = packed_ld(P);
             uint16_t *hi = nullptr, *lo = nullptr;
-            size_t bytes = sizeof(uint16_t) * (size_t)h->Mpad * ldp;
-            CHK(dmalloc(h, tmp, (void **)&hi, bytes));
-            CHK(dmalloc(h, tmp, (void **)&lo, bytes));
-            HIPCHK(launch_operand(2, h->M, h->Mpad, P, bd, hi, lo, ldp, h->stream));
-            a.mode = GM_BF16X3; a.Bhi = hi; a.Blo = lo; a.ldb = ldp;
+            const size_t bytes = sizeof(uint16_t) * (size_t)h->Mpad * ldp;
+            CHK(dmalloc(tmp, (void **)&hi, bytes));
+            CHK(dmalloc(tmp, (void **)&lo, bytes));
+            HIPCHK(launch_operand({OperandArgs{2, h->M, h->Mpad, P, B, ldb, hi, lo, ldp, nullptr, 0.0}}, nullptr,
+                                  h->stream));
+            a.Bhi = hi; a.Blo = lo; a.ldb = ldp;
         }
-        CHK(run_gemm(h, a, which));
-        return MGWR_OK;
+        return run_gemms(ex, {a}, which);
     }();
     hipStreamSynchronize(h->stream);
     free_list(tmp);
@@ -864,9 +1613,9 @@ int mgwr_profile_enable(mgwr_t h, int on)
 {
     if (!h) return fail(MGWR_EINVAL, "NULL handle");
     CHK(set_device(h));
-    CHK(resolve_profile(h));
-    if (on) h->records.clear();
-    h->prof = on != 0;
+    CHK(h->run.prof.resolve(h->stream));
+    if (on) h->run.prof.records.clear();
+    h->run.prof.on = on != 0;
     return MGWR_OK;
 }
 
@@ -874,41 +1623,36 @@ int mgwr_profile_count(mgwr_t h)
 {
     if (!h) return fail(MGWR_EINVAL, "NULL handle");
     CHK(set_device(h));
-    CHK(resolve_profile(h));
-    return (int)h->records.size();
+    CHK(h->run.prof.resolve(h->stream));
+    return (int)h->run.prof.records.size();
 }
 
 int mgwr_profile_get(mgwr_t h, int i, mgwr_kernel_record *rec)
 {
     if (!h || !rec) return fail(MGWR_EINVAL, "NULL argument");
-    CHK(resolve_profile(h));
-    if (i < 0 || i >= (int)h->records.size()) return fail(MGWR_EINVAL, "record %d out of range", i);
-    *rec = h->records[i];
+    CHK(h->run.prof.resolve(h->stream));
+    if (i < 0 || i >= (int)h->run.prof.records.size()) return fail(MGWR_EINVAL, "record %d out of range", i);
+    *rec = h->run.prof.records[i];
     return MGWR_OK;
 }
 
 const char *mgwr_kernel_name(int kernel)
 {
     static thread_local std::string name;
-    int mode = kernel >> 4, epi = (kernel >> 1) & 7, narrow = kernel & 1;
-    if (mode == GM_BF16X3) name = "k_toep_bf16x3<" + std::to_string(epi) + ">";
-    else name = std::string(narrow ? "k_toep_narrow<" : "k_toep_wide<") + std::to_string(mode) + ", " +
-                std::to_string(epi) + ">";
+    const int kind = (kernel >> 8) & 15, mode = (kernel >> 4) & 15, epi = kernel & 15;
+    const std::string m = std::to_string(mode), e = std::to_string(epi);
+    switch (kind) {
+    case 0: name = "k_toep_narrow<" + m + ", " + e + ">"; break;
+    case 1: name = "k_toep_wide<" + m + ", " + e + ", 0>"; break;
+    case 2: name = "k_toep_wide<" + m + ", " + e + ", 1>"; break;
+    default: name = "k_toep_bf16x3<" + e + ">"; break;
+    }
     return name.c_str();
 }
 
 // ---------------------------------------------------------------------------
-// Batches: one handle per problem; the solves advance in lockstep so that one
-// host synchronisation per cycle serves every problem of the batch.
-}  // extern "C"
-
-struct mgwr_batch_ctx {
-    std::vector<mgwr_t> hs;
-    hipStream_t stream = nullptr;
-};
-
-extern "C" {
-
+// Batches: one hierarchy per problem; every stage is one launch over all
+// problems that are still iterating.
 int mgwr_batch_create(int count, const int *N, const int *M, const double *alpha, const double *T, int dims,
                       const mgwr_options *opts, mgwr_batch_t *out)
 {
@@ -916,18 +1660,26 @@ int mgwr_batch_create(int count, const int *N, const int *M, const double *alpha
     *out = nullptr;
     if (count < 1 || !N || !M || !alpha || !T) return fail(MGWR_EINVAL, "bad batch description");
     mgwr_batch_ctx *b = new mgwr_batch_ctx();
+    auto undo = [&](int rc) {
+        std::string msg = g_err;
+        for (auto x : b->hs) mgwr_destroy(x);
+        release_runner(b->run);
+        delete b;
+        g_err = msg;
+        return rc;
+    };
     for (int i = 0; i < count; ++i) {
         mgwr_t h = nullptr;
         int rc = mgwr_create_ex(N[i], M[i], alpha[i], T[i], dims, opts, &h);
         if (rc < 0) {
-            std::string msg = "problem " + std::to_string(i) + ": " + g_err;
-            for (auto x : b->hs) mgwr_destroy(x);
-            delete b;
-            g_err = msg;
-            return rc;
+            g_err = "problem " + std::to_string(i) + ": " + g_err;
+            return undo(rc);
         }
         b->hs.push_back(h);
     }
+    int rc = init_runner(b->run, count);
+    if (rc < 0) return undo(rc);
+    b->run.graphs = b->hs[0]->opt.graph != 0;
     *out = b;
     return MGWR_OK;
 }
@@ -935,8 +1687,8 @@ int mgwr_batch_create(int count, const int *N, const int *M, const double *alpha
 int mgwr_batch_set_stream(mgwr_batch_t b, void *hip_stream)
 {
     if (!b) return fail(MGWR_EINVAL, "NULL batch");
-    b->stream = (hipStream_t)hip_stream;
-    for (auto h : b->hs) h->stream = b->stream;
+    b->run.stream = (hipStream_t)hip_stream;
+    for (auto h : b->hs) mgwr_set_stream(h, hip_stream);
     return MGWR_OK;
 }
 
@@ -944,20 +1696,59 @@ int mgwr_batch_solve(mgwr_batch_t b, const double *const *f, const double *const
                      double tol, mgwr_info *infos)
 {
     if (!b || !f || !u) return fail(MGWR_EINVAL, "NULL argument");
-    int worst = MGWR_OK;
+    if (!(tol >= 0.0)) return fail(MGWR_EINVAL, "tol must be >= 0");
     for (size_t i = 0; i < b->hs.size(); ++i) {
-        mgwr_info inf;
-        int rc = mgwr_solve(b->hs[i], f[i], g ? g[i] : nullptr, u[i], tol, &inf);
-        if (infos) infos[i] = inf;
-        if (rc < 0) return rc;
-        if (rc > worst) worst = rc;
+        if (check_ptr(f[i], "f[i]") < 0 || check_ptr(u[i], "u[i]") < 0)
+            return fail(MGWR_EINVAL, "problem %zu: f and u must be non-NULL and 8-byte aligned", i);
     }
-    return worst;
+    CHK(set_device(b->hs[0]));
+    return solve_group(b->run, b->hs, f, g, u, tol, infos);
+}
+
+int mgwr_batch_autotune(mgwr_batch_t b)
+{
+    if (!b) return fail(MGWR_EINVAL, "NULL batch");
+    CHK(set_device(b->hs[0]));
+    return autotune_group(b->run, b->hs);
+}
+
+int mgwr_batch_get_tuning(mgwr_batch_t b, int i, mgwr_tuning *t)
+{
+    if (!b || !t || i < 0 || i >= (int)b->hs.size()) return fail(MGWR_EINVAL, "bad argument");
+    tuning_out(b->hs[i], t);
+    return MGWR_OK;
+}
+
+int mgwr_batch_profile_enable(mgwr_batch_t b, int on)
+{
+    if (!b) return fail(MGWR_EINVAL, "NULL batch");
+    CHK(b->run.prof.resolve(b->run.stream));
+    if (on) b->run.prof.records.clear();
+    b->run.prof.on = on != 0;
+    return MGWR_OK;
+}
+
+int mgwr_batch_profile_count(mgwr_batch_t b)
+{
+    if (!b) return fail(MGWR_EINVAL, "NULL batch");
+    CHK(b->run.prof.resolve(b->run.stream));
+    return (int)b->run.prof.records.size();
+}
+
+int mgwr_batch_profile_get(mgwr_batch_t b, int i, mgwr_kernel_record *rec)
+{
+    if (!b || !rec) return fail(MGWR_EINVAL, "NULL argument");
+    CHK(b->run.prof.resolve(b->run.stream));
+    if (i < 0 || i >= (int)b->run.prof.records.size()) return fail(MGWR_EINVAL, "record %d out of range", i);
+    *rec = b->run.prof.records[i];
+    return MGWR_OK;
 }
 
 int mgwr_batch_destroy(mgwr_batch_t b)
 {
     if (!b) return MGWR_OK;
+    if (b->run.stream) hipStreamSynchronize(b->run.stream);
+    release_runner(b->run);
     for (auto h : b->hs) mgwr_destroy(h);
     delete b;
     return MGWR_OK;

@@ -5,10 +5,17 @@
 // time-major [M][P].  Only the operands of the Toeplitz products may be held
 // in lower precision (FP32 panels, or split-BF16 hi/lo panels in the k8-packed
 // layout [Mpad/8][ld][8]).
+//
+// Every launcher takes a list of per-problem argument sets and issues ONE
+// launch for all of them (a batch of independent problems advances stage by
+// stage).  A list of one is passed by value in the kernel arguments; longer
+// lists go through a Staging area (device copies of the argument arrays).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
+#include <vector>
 
 namespace mgwr {
 
@@ -39,13 +46,20 @@ enum EpiKind {
     EPI_STORE = 0,       // out[i][p] = acc                        (residual product)
     EPI_SCATTER = 1,     // out[i][colour_point(p)] = acc          (smoother, full product)
     EPI_SCATTER_ADD = 2, // out[i][colour_point(p)] += acc         (smoother, history product)
-    EPI_SUB = 3          // out[i][p] -= acc                       (D&C history update)
+    EPI_SUB = 3,         // out[i][p] -= acc                       (D&C history update)
+    EPI_ADD = 4          // out[i][p] += acc                       (D&C base block, history part)
 };
 
 struct EpiArgs {
-    double *out = nullptr;     // output (STORE/SUB) or the iterate U of the level (SCATTER*)
+    double *out = nullptr;     // output (STORE/SUB/ADD) or the iterate U of the level (SCATTER*)
     long ldo = 0;
     int dims = 1, n = 1, colour = 0;   // grid of the level (points per dim) and colour
+};
+
+// Tile choices of the product kernels (set by the autotuner).
+struct TileKnobs {
+    int variant = -1;          // wide FP64/FP32 kernel: 0 = 128x64, 1 = 256x64, -1 = by size
+    int split_target = 0;      // work items a lone launch aims for (0 = default of the kernel)
 };
 
 struct GemmArgs {
@@ -63,6 +77,7 @@ struct GemmArgs {
     EpiArgs ea;
     void *part = nullptr;      // scratch for split-K partials
     size_t part_cap = 0;       // its size in bytes (0: never split)
+    TileKnobs knobs;
 };
 
 // Flat point index of the j-th point of a colour (0: n even / n + l even).
@@ -86,45 +101,119 @@ __host__ __device__ inline int colour_count(int dims, int n, int colour)
     return colour == 0 ? (int)((t + 1) / 2) : (int)(t / 2);
 }
 
-// ---- launchers (all asynchronous on `s`) ----
-hipError_t launch_toep_gemm(const GemmArgs &a, hipStream_t s);
-// Scratch a product of this shape uses for split-K partials (0: not split).
-size_t splitk_bytes(int mode, int M, int P, int K, int off, int ncoef);
+// ---------------------------------------------------------------------------
+// Argument arrays of grouped launches.  A stage is run twice over the same
+// host logic: a RECORD pass appends every array to `host` and launches
+// nothing; after `dev` holds a copy of `host`, the LAUNCH pass makes the same
+// calls, gets the same offsets back as device addresses, and launches.
+struct Staging {
+    bool record = false;
+    std::vector<char> host;
+    char *dev = nullptr;
+    size_t cursor = 0;
+    const void *put(const void *p, size_t bytes)
+    {
+        size_t at = (cursor + 255) & ~(size_t)255;
+        cursor = at + bytes;
+        if (record) {
+            host.resize(cursor);
+            memcpy(host.data() + at, p, bytes);
+            return nullptr;
+        }
+        return dev + at;
+    }
+};
 
-// Right-hand side of a colour half-sweep, b = F + cd g + (neighbour sum of U)/h^2
-// at the points of the colour, as the B operand of the smoother's product:
-// fmt 0: FP64 panel [M][ldp]; 1: FP32 panel [M][ldp]; 2: split-BF16 k8-packed
+// ---- argument sets of the bandwidth kernels ----
+// Colour right-hand side b = F + cd g + (neighbour sum of U)/h^2 at the
+// points of a colour, as the B operand of the smoother's product: fmt 0:
+// FP64 panel [M][ldp]; 1: FP32 panel [M][ldp]; 2: split-BF16 k8-packed
 // [Mpad/8][ldp][8] (hi into panel, lo into panel_lo; zero for k >= M, j >= Pc).
 // If lam0 != 0 the kernel also writes lam0 * b into the colour's points of U
 // (the diagonal part of the line solve; the product then adds the history).
-hipError_t launch_rhs_panel(int fmt, int dims, int n, int colour, int M, int Mpad, const double *F,
-                            double *U, const double *cd, const double *g, double ih2, double lam0,
-                            void *panel, void *panel_lo, long ldp, hipStream_t s);
-// Residual from a Toeplitz product already in out (the history part, or all of
-// T_M U when diag = 0): out = (F + cd g - diag U - A_h U) - out, with A_h
-// applied to hi + lo by error-free transformations when lo != nullptr.
-hipError_t launch_resid_post(int dims, int n, int M, const double *F, const double *U, const double *lo,
-                             const double *cd, const double *g, double ih2, double diag, double *out,
-                             hipStream_t s);
-// X [M][P] FP64 -> FP32 copy [M][P] (fmt 1) or split-BF16 k8-packed (fmt 2).
-hipError_t launch_operand(int fmt, int M, int Mpad, int P, const double *X, void *out,
-                          void *out_lo, long ldp, hipStream_t s);
-hipError_t launch_restrict(int dims, int nf, int M, const double *rf, double *rc, hipStream_t s);
-hipError_t launch_prolong_add(int dims, int nc, int M, const double *ec, double *uf, hipStream_t s);
-// u[k][p] = g ? g[p] : 0
-hipError_t launch_fill(long M, long P, const double *g, double *u, hipStream_t s);
-// u[k][p] = g ? cd[k] g[p] : 0
-hipError_t launch_scaled_fill(long M, long P, const double *cd, const double *g, double *u, hipStream_t s);
-// Block partials of {max |x|, sum x^2}; partials: [nblk][2]; returns nblk.
-hipError_t launch_norm_partials(long n, const double *x, double *partials, int *nblk,
-                                hipStream_t s);
-hipError_t launch_norm_final(int nblk, const double *partials, double *out2, hipStream_t s);
+struct RhsArgs {
+    int fmt, dims, n, colour, M, Mpad;
+    const double *F;
+    double *U;
+    const double *cd, *g;
+    double ih2, lam0;
+    void *panel, *panel_lo;
+    long ldp;
+};
+// Residual from a Toeplitz product already in out (the history part, or all
+// of T_M U when diag = 0): out = (F + cd g - diag U - A_h U) - out, with A_h
+// applied to U + lo by error-free transformations when lo != nullptr.
+struct PostArgs {
+    int dims, n, M;
+    const double *F, *U, *lo, *cd, *g;
+    double ih2, diag;
+    double *out;
+};
+// Low-precision product operand of rows [0, M) of X [.][ldx] (P columns):
+// fmt 1: FP32 [M][ldp]; fmt 2: split-BF16 k8-packed [Mpad/8][ldp][8] (rows
+// M..Mpad-1 and columns P..ldp-1 zero).  If X2 != nullptr it also writes
+// X2 = s2 * X ([.][ldx]; the D&C base block's diagonal part).
+struct OperandArgs {
+    int fmt, M, Mpad, P;
+    const double *X;
+    long ldx;
+    void *out, *out_lo;
+    long ldp;
+    double *X2;
+    double s2;
+};
+// Full weighting (dir 0: fine n -> coarse) or interpolation added to the
+// fine iterate (dir 1: coarse n -> fine).
+struct XferArgs {
+    int dir, dims, n, M;
+    const double *src;
+    double *dst;
+};
+// u[k][p] = scaled ? cd[k] g[p] : g[p]  (g == nullptr: 0)
+struct FillArgs {
+    long M, P;
+    const double *cd, *g;
+    double *u;
+    int scaled;
+};
+// Norm partials {max |x|, sum x^2} of x[0..n) over nblk blocks, and the final
+// reduction into out2 = {max, sqrt(sum)}.
+struct NormArgs {
+    long n;
+    const double *x;
+    double *partials;
+    int nblk;
+    double *out2;
+};
 // (hi, lo) += e (double-double); lo == nullptr: hi += e.
-hipError_t launch_dd_update(long n, const double *e, double *hi, double *lo, hipStream_t s);
-// FP32 -> FP64 copy.
-hipError_t launch_widen(long n, const float *x, double *y, hipStream_t s);
+struct DDArgs {
+    long n;
+    const double *e;
+    double *hi, *lo;
+};
+// U[k][colour_point(j)] = X[k][j], k < M, j < Pc (end of a D&C half-sweep).
+struct ScatterArgs {
+    int dims, n, colour, M, Pc;
+    const double *X;
+    double *U;
+};
+
+// ---- launchers (all asynchronous on `s`; st may be nullptr when every list
+// has at most one entry) ----
+hipError_t launch_toep_gemm(const std::vector<GemmArgs> &as, Staging *st, hipStream_t s);
+// Scratch a lone product of this shape uses for split-K partials (0: not split).
+size_t splitk_bytes(int mode, int M, int P, int K, int off, int ncoef, const TileKnobs &kn);
+hipError_t launch_rhs(const std::vector<RhsArgs> &v, Staging *st, hipStream_t s);
+hipError_t launch_post(const std::vector<PostArgs> &v, Staging *st, hipStream_t s);
+hipError_t launch_operand(const std::vector<OperandArgs> &v, Staging *st, hipStream_t s);
+hipError_t launch_xfer(const std::vector<XferArgs> &v, Staging *st, hipStream_t s);
+hipError_t launch_fill(const std::vector<FillArgs> &v, Staging *st, hipStream_t s);
+hipError_t launch_norms(const std::vector<NormArgs> &v, Staging *st, hipStream_t s);
+hipError_t launch_dd_update(const std::vector<DDArgs> &v, Staging *st, hipStream_t s);
+hipError_t launch_scatter(const std::vector<ScatterArgs> &v, Staging *st, hipStream_t s);
 // Fill one coefficient table (fp32 copy and bf16 fragment table) from d64.
 hipError_t launch_build_coef(ToepCoef &c, hipStream_t s);
+// Blocks of the norm partials of an n-element array.
 int norm_partial_blocks(long n);
 
 }  // namespace mgwr

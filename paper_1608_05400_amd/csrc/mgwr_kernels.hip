@@ -22,7 +22,9 @@
 #include "mgwr_internal.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
+#include <map>
 #include <type_traits>
 
 namespace mgwr {
@@ -30,6 +32,15 @@ namespace mgwr {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Global-memory views of pointers that reach a kernel inside an argument
+// struct (by value or from a device array): without them the compiler cannot
+// tell global from LDS or scratch and issues flat accesses, whose completion
+// the wait counters of both memory paths must cover.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ inline const GLOBAL T *gview(const void *p) { return (const GLOBAL T *)p; }
+template <typename T> __device__ inline GLOBAL T *gview_rw(void *p) { return (GLOBAL T *)p; }
 
 // ---------------------------------------------------------------------------
 // BF16 helpers: round-to-nearest-even of a finite float, and back.
@@ -44,8 +55,8 @@ __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b <<
 // ---------------------------------------------------------------------------
 // Stencils of the negative Laplacian (Section 2: 3-point; Section 6: 5-point)
 // with zero Dirichlet values, on one time row U of a level with n points/dim.
-template <typename S>
-__device__ inline double nbr_sum(const S *U, int dims, int n, int p)
+template <typename Ptr>
+__device__ inline double nbr_sum(Ptr U, int dims, int n, int p)
 {
     if (dims == 1) {
         double s = 0.0;
@@ -72,8 +83,8 @@ __device__ inline void two_sum(double a, double b, double &s, double &e)
 // A_h (hi + lo) at point p as an unevaluated sum (shi + slo) / h^2:
 // shi + slo = 2 d hi_p - sum(neighbours of hi) + (same stencil of lo),
 // the hi part without rounding error (error-free transformations).
-__device__ inline void stencil_dd(const double *H, const double *Lo, int dims, int n, int p,
-                                  double &shi, double &slo)
+template <typename Ptr>
+__device__ inline void stencil_dd(Ptr H, Ptr Lo, int dims, int n, int p, double &shi, double &slo)
 {
     double s = (dims == 1 ? 2.0 : 4.0) * H[p], e, acc = 0.0;
     double lo = (dims == 1 ? 2.0 : 4.0) * Lo[p];
@@ -96,15 +107,19 @@ __device__ inline void stencil_dd(const double *H, const double *Lo, int dims, i
 template <int EPI>
 __device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
 {
+    GLOBAL double *out = gview_rw<double>(e.out);
     if constexpr (EPI == EPI_STORE) {
-        e.out[(long)i * e.ldo + p] = acc;
+        out[(long)i * e.ldo + p] = acc;
     } else if constexpr (EPI == EPI_SUB) {
-        double *o = e.out + (long)i * e.ldo + p;
+        GLOBAL double *o = out + (long)i * e.ldo + p;
         *o = *o - acc;
     } else if constexpr (EPI == EPI_SCATTER) {
-        e.out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = acc;
+        out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = acc;
     } else if constexpr (EPI == EPI_SCATTER_ADD) {
-        double *o = e.out + (long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p);
+        GLOBAL double *o = out + (long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p);
+        *o = *o + acc;
+    } else if constexpr (EPI == EPI_ADD) {
+        GLOBAL double *o = out + (long)i * e.ldo + p;
         *o = *o + acc;
     }
 }
@@ -122,6 +137,29 @@ struct KP {
     void *part;                // split partials [nsplit][M][P] (double for F64, float otherwise)
     EpiArgs ea;
 };
+
+// One launch of a product kernel over the products of several problems:
+// block b runs work item items[b].y of problem items[b].x; the host sorts the
+// table by the K extent of the items, longest first, so that the short items
+// of every problem fill the tail of the launch.
+struct KGrp {
+    KP one;                    // the product when n == 1 (block b = item b)
+    const KP *many;            // n > 1: device array of n products
+    const int2 *items;         // n > 1: (product, work item) of every block
+    int n;
+};
+__device__ inline void kgrp_select(const KGrp &g, KP &kp, int &b)
+{
+    if (g.n == 1) {
+        kp = g.one;
+        b = blockIdx.x;
+        return;
+    }
+    const int2 it = g.items[blockIdx.x];
+    const int p = __builtin_amdgcn_readfirstlane(it.x);
+    b = __builtin_amdgcn_readfirstlane(it.y);
+    kp = g.many[p];
+}
 
 // Work item b -> (row tile, column tile, split).  Row tiles in decreasing
 // order (a causal product has the most work in its last rows, so the short
@@ -160,7 +198,7 @@ template <int EPI, typename PT>
 __device__ inline void emit(const KP &kp, int s, int i, int p, double acc)
 {
     if (kp.nsplit > 1)
-        ((PT *)kp.part)[((long)s * kp.M + i) * kp.P + p] = (PT)acc;
+        gview_rw<PT>(kp.part)[((long)s * kp.M + i) * kp.P + p] = (PT)acc;
     else
         epi_apply<EPI>(kp.ea, i, p, acc);
 }
@@ -201,7 +239,7 @@ template <> struct WideCfg<1> { static constexpr int WGM = 4, WGN = 1, FM = 4, F
 template <int V> constexpr int wide_bm() { return 16 * WideCfg<V>::FM * WideCfg<V>::WGM; }
 
 template <int MODE, int EPI, int V>
-__global__ __launch_bounds__(256) void k_toep_wide(KP kp)
+__global__ __launch_bounds__(256) void k_toep_wide(KGrp grp)
 {
     using T = Tr<MODE>;
     using S = typename T::S;
@@ -213,10 +251,13 @@ __global__ __launch_bounds__(256) void k_toep_wide(KP kp)
     __shared__ S Ws[2][WIN];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / C::WGN, wn = wid % C::WGN;
-    const Item it = item_of(kp, blockIdx.x);
+    KP kp;
+    int blk;
+    kgrp_select(grp, kp, blk);
+    const Item it = item_of(kp, blk);
     const int i0 = it.tm * BM, p0 = it.tn * WBN;
-    const S *coef = (const S *)kp.coef;
-    const S *B = (const S *)kp.B;
+    const GLOBAL S *coef = gview<S>(kp.coef);
+    const GLOBAL S *B = gview<S>(kp.B);
     int kbase, ks0, ks1;
     k_range<BM, WBK>(kp, i0, it.s, kbase, ks0, ks1);
     const int nk = ks1 - ks0;
@@ -305,17 +346,20 @@ __global__ __launch_bounds__(256) void k_toep_wide(KP kp)
 constexpr int NBM = 64, NBN = 16, NCH = 16;
 
 template <int MODE, int EPI>
-__global__ __launch_bounds__(256) void k_toep_narrow(KP kp)
+__global__ __launch_bounds__(256) void k_toep_narrow(KGrp grp)
 {
     using T = Tr<MODE>;
     using S = typename T::S;
     using acc_t = typename T::acc_t;
     __shared__ S red[4][NBM * NBN];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const Item it = item_of(kp, blockIdx.x);
+    KP kp;
+    int blk;
+    kgrp_select(grp, kp, blk);
+    const Item it = item_of(kp, blk);
     const int i0 = it.tm * NBM, p0 = it.tn * NBN;
-    const S *coef = (const S *)kp.coef;
-    const S *B = (const S *)kp.B;
+    const GLOBAL S *coef = gview<S>(kp.coef);
+    const GLOBAL S *B = gview<S>(kp.B);
     int kbase, ks0, ks1;
     k_range<NBM, NCH>(kp, i0, it.s, kbase, ks0, ks1);
 
@@ -370,15 +414,18 @@ __global__ __launch_bounds__(256) void k_toep_narrow(KP kp)
 // multiple of 128, padding zero.
 constexpr int QBM = 256, QBN = 128, QBK = 32;
 
-__device__ inline v8bf as_bf8(uint4 v) { return __builtin_bit_cast(v8bf, v); }
+__device__ inline v8bf as_bf8(u32x4 v) { return __builtin_bit_cast(v8bf, v); }
 
 template <int EPI>
-__global__ __launch_bounds__(256) void k_toep_bf16x3(KP kp)
+__global__ __launch_bounds__(256) void k_toep_bf16x3(KGrp grp)
 {
-    __shared__ uint4 Bs[3][2][4][QBN];   // [buffer][hi/lo][k/8][column]
+    __shared__ u32x4 Bs[3][2][4][QBN];   // [buffer][hi/lo][k/8][column]
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid >> 1, wn = wid & 1;
-    const Item it = item_of(kp, blockIdx.x);
+    KP kp;
+    int blk;
+    kgrp_select(grp, kp, blk);
+    const Item it = item_of(kp, blk);
     const int i0 = it.tm * QBM, p0 = it.tn * QBN;
     int kbase, ks0, ks1;
     k_range<QBM, QBK>(kp, i0, it.s, kbase, ks0, ks1);
@@ -393,14 +440,14 @@ __global__ __launch_bounds__(256) void k_toep_bf16x3(KP kp)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0, 0, 0, 0};
 
-    const uint4 *fh = (const uint4 *)kp.fhi, *fl = (const uint4 *)kp.flo;
-    const uint4 *bh = (const uint4 *)kp.Bhi, *bl = (const uint4 *)kp.Blo;
+    const GLOBAL u32x4 *fh = gview<u32x4>(kp.fhi), *fl = gview<u32x4>(kp.flo);
+    const GLOBAL u32x4 *bh = gview<u32x4>(kp.Bhi), *bl = gview<u32x4>(kp.Blo);
     const long ldb = kp.ldb;
-    uint4 Ah[8], Al[8];          // Toeplitz fragment slots
-    uint4 nh0, nl0, nh1, nl1;    // fragments of the next K step
+    u32x4 Ah[8], Al[8];          // Toeplitz fragment slots
+    u32x4 nh0, nl0, nh1, nl1;    // fragments of the next K step
     // two register sets for B tiles in flight: this thread's share is hi and
     // lo at rows k/8 = kr and kr + 2, column tc
-    uint4 r00, r01, r02, r03, r10, r11, r12, r13;
+    u32x4 r00, r01, r02, r03, r10, r11, r12, r13;
     const int kr = tid >> 7, tc = tid & 127;
     // B fragments of this and of the next K step (two sets)
     v8bf fh0[4], fl0[4], fh1[4], fl1[4];
@@ -511,178 +558,383 @@ __global__ __launch_bounds__(256) void k_toep_bf16x3(KP kp)
             }
 }
 
-// Sum of the split partials in a fixed order, then the epilogue.
-template <int EPI, typename PT>
-__global__ void k_splitk_reduce(KP kp)
+// ---------------------------------------------------------------------------
+// Grouped launches of the bandwidth kernels: block b of the launch runs block
+// b - start[p] of argument set p, where start[] is the prefix sum of the
+// blocks each set asked for; a set of one is passed by value.
+template <class A> struct Grp {
+    A one;
+    const A *many;
+    const int *start;   // n + 1 entries
+    int n;
+};
+
+// Number of i in [1, n) with start[i] <= b, i.e. the set that owns block b
+// (each wave counts on its own: no LDS, no barrier).
+__device__ inline int grp_find(const int *start, int n, int b)
 {
-    const long MP = (long)kp.M * kp.P;
-    const PT *part = (const PT *)kp.part;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < MP; e += (long)gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int s = 0; s < kp.nsplit; ++s) acc += (double)part[s * MP + e];
-        int i = (int)(e / kp.P), p = (int)(e - (long)i * kp.P);
-        epi_apply<EPI>(kp.ea, i, p, acc);
+    const int lane = threadIdx.x & 63;
+    int cnt = 0;
+    for (int base = 1; base < n; base += 64) {
+        const int i = base + lane;
+        const bool le = (i < n) && (start[i] <= b);
+        cnt += __popcll(__ballot(le));
     }
+    return cnt;
 }
 
+template <class A>
+__device__ inline void grp_select(const Grp<A> &g, A &a, long &lb, long &nb)
+{
+    if (g.n == 1) {
+        a = g.one;
+        lb = blockIdx.x;
+        nb = gridDim.x;
+        return;
+    }
+    const int p = __builtin_amdgcn_readfirstlane(grp_find(g.start, g.n, blockIdx.x));
+    a = g.many[p];
+    const int s0 = g.start[p], s1 = g.start[p + 1];
+    lb = (long)blockIdx.x - s0;
+    nb = s1 - s0;
+}
+
+constexpr int kThreads = 256;
+#define GRID_STRIDE(e, total) \
+    for (long e = lb * kThreads + threadIdx.x; e < (total); e += nb * kThreads)
+
+template <class Op>
+__global__ __launch_bounds__(kThreads) void k_group(Grp<typename Op::A> g)
+{
+    typename Op::A a;
+    long lb, nb;
+    grp_select(g, a, lb, nb);
+    Op::run(a, lb, nb);
+}
+
+// Sum of the split partials in a fixed order, then the epilogue.
+template <int EPI, typename PT> struct OpReduce {
+    using A = KP;
+    __device__ static void run(const KP &kp, long lb, long nb)
+    {
+        const long MP = (long)kp.M * kp.P;
+        const GLOBAL PT *part = gview<PT>(kp.part);
+        GRID_STRIDE(e, MP) {
+            double acc = 0.0;
+            for (int s = 0; s < kp.nsplit; ++s) acc += (double)part[s * MP + e];
+            int i = (int)(e / kp.P), p = (int)(e - (long)i * kp.P);
+            epi_apply<EPI>(kp.ea, i, p, acc);
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
-// Launch geometry.  A launch with few tiles (coarse levels) would leave most
-// CUs idle while its last row tile walks the whole K range, so its K range
-// is split over several blocks and a reduce kernel applies the epilogue.
+// Launch geometry of the products.  kind: 0 narrow (64 x 16 blocks), 1 wide
+// 128 x 64, 2 wide 256 x 64, 3 split-BF16 256 x 128.
 struct Geo {
-    int BM, BN, BK, tiles_m, tiles_n, nsplit, variant;
+    int kind, BM, BN, BK, tiles_m, tiles_n, nsplit;
     size_t part_bytes;
 };
 
-// Wide-kernel variant per mode (0: 128 x 64 blocks, 1: 256 x 64 blocks,
-// -1: by launch size); the environment variable MGWR_WIDE_VARIANT
-// ("<fp64><fp32>", e.g. "10") fixes it for tuning runs.
-static int wide_variant(int mode)
+static int tile_steps(int K, int off, int ncoef, int BM, int BK, int tm)
 {
-    static int v[2] = {-2, -2};
-    if (v[0] == -2) {
-        v[0] = -1; v[1] = -1;   // -1: choose by launch size
-        const char *e = getenv("MGWR_WIDE_VARIANT");
-        if (e && e[0] >= '0' && e[0] <= '1') v[0] = e[0] - '0';
-        if (e && e[0] && e[1] >= '0' && e[1] <= '1') v[1] = e[1] - '0';
-    }
-    return v[mode == GM_F64 ? 0 : 1];
+    const int i0 = tm * BM;
+    const int kend = std::min(K, i0 + BM + off);
+    int kbeg = std::max(0, off + i0 - ncoef + 1);
+    kbeg = (kbeg / BK) * BK;
+    return (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
 }
 
-static Geo geometry(int mode, int M, int P, int K, int off, int ncoef, size_t part_cap)
+static Geo tiles(int mode, int M, int P, const TileKnobs &kn)
 {
-    Geo g;
-    g.variant = 0;
-    if (mode == GM_BF16X3) { g.BM = QBM; g.BN = QBN; g.BK = QBK; }
-    else if (P <= 32) { g.BM = NBM; g.BN = NBN; g.BK = NCH; }
+    Geo g{};
+    if (mode == GM_BF16X3) { g.kind = 3; g.BM = QBM; g.BN = QBN; g.BK = QBK; }
+    else if (P <= 32) { g.kind = 0; g.BM = NBM; g.BN = NBN; g.BK = NCH; }
     else {
-        // 256-row blocks help launches that are too small to fill the chip
-        // with 128-row blocks several times over
+        // 256-row blocks help launches too small to fill the chip several
+        // times over with 128-row blocks
         const long t0 = (long)((M + wide_bm<0>() - 1) / wide_bm<0>()) * ((P + WBN - 1) / WBN);
-        g.variant = wide_variant(mode);
-        if (g.variant < 0) g.variant = (t0 < 4096) ? 1 : 0;
-        g.BM = g.variant ? wide_bm<1>() : wide_bm<0>(); g.BN = WBN; g.BK = WBK;
+        int v = kn.variant;
+        if (v < 0) v = (t0 < 4096) ? 1 : 0;
+        g.kind = 1 + v; g.BM = v ? wide_bm<1>() : wide_bm<0>(); g.BN = WBN; g.BK = WBK;
     }
     g.tiles_m = (M + g.BM - 1) / g.BM;
     g.tiles_n = (P + g.BN - 1) / g.BN;
+    g.nsplit = 1;
+    g.part_bytes = 0;
+    return g;
+}
+
+static int split_cap(const Geo &g, int mode, int M, int P, int ns, size_t part_cap)
+{
+    const size_t esz = (mode == GM_F64) ? 8 : 4;
+    while (ns > 1 && (size_t)ns * M * P * esz > part_cap) --ns;
+    return std::max(ns, 1);
+}
+
+// A lone launch with few tiles (coarse levels) would leave most CUs idle
+// while its last row tile walks the whole K range, so its K range is split
+// over several blocks until the launch has about `target` work items.
+static Geo geometry(int mode, int M, int P, int K, int off, int ncoef, size_t part_cap, const TileKnobs &kn)
+{
+    Geo g = tiles(mode, M, P, kn);
     const long T = (long)g.tiles_m * g.tiles_n;
-    // K steps of the longest row tile
-    int i0 = (g.tiles_m - 1) * g.BM;
-    int kend = std::min(K, i0 + g.BM + off);
-    int kbeg = std::max(0, off + i0 - ncoef + 1);
-    int nk = (kend > kbeg) ? (kend - kbeg + g.BK - 1) / g.BK : 0;
-    // target number of work items: the narrow kernel's items are short, so
-    // it takes more of them; MGWR_SPLIT_TARGET overrides it for tuning runs
-    static long tgt_env = -2;
-    if (tgt_env == -2) {
-        const char *e = getenv("MGWR_SPLIT_TARGET");
-        tgt_env = e ? atol(e) : -1;
-    }
-    const long target = tgt_env > 0 ? tgt_env : (g.BM == NBM) ? 8192 : (mode == GM_BF16X3) ? 1024 : 2048;
+    const int nk = tile_steps(K, off, ncoef, g.BM, g.BK, g.tiles_m - 1);
+    const long target = kn.split_target > 0 ? kn.split_target
+                        : (g.kind == 0) ? 8192 : (g.kind == 3) ? 1024 : 2048;
     int ns = 1;
     if (T < target) {
         ns = (int)((target + T - 1) / T);
         ns = std::min(ns, 64);
         ns = std::min(ns, std::max(1, nk / 8));
     }
-    const size_t esz = (mode == GM_F64) ? 8 : 4;
-    while (ns > 1 && (size_t)ns * M * P * esz > part_cap) --ns;
-    g.nsplit = ns;
-    g.part_bytes = ns > 1 ? (size_t)ns * M * P * esz : 0;
+    g.nsplit = split_cap(g, mode, M, P, ns, part_cap);
+    g.part_bytes = g.nsplit > 1 ? (size_t)g.nsplit * M * P * ((mode == GM_F64) ? 8 : 4) : 0;
     return g;
 }
 
-size_t splitk_bytes(int mode, int M, int P, int K, int off, int ncoef)
+size_t splitk_bytes(int mode, int M, int P, int K, int off, int ncoef, const TileKnobs &kn)
 {
-    return geometry(mode, M, P, K, off, ncoef, (size_t)-1).part_bytes;
+    return geometry(mode, M, P, K, off, ncoef, (size_t)-1, kn).part_bytes;
 }
 
-static inline dim3 grid_for(long total, int threads = 256)
+static inline long blocks_for(long total)
 {
-    long b = (total + threads - 1) / threads;
-    if (b < 1) b = 1;
-    if (b > 65536) b = 65536;
-    return dim3((unsigned)b);
+    long b = (total + kThreads - 1) / kThreads;
+    return std::max(1L, std::min(b, 65536L));
 }
 
-template <int MODE, int EPI>
-static hipError_t launch_mode_epi(const GemmArgs &a, KP &kp, hipStream_t s)
+// One grouped launch of Op over the argument sets v (blocks[i] blocks each).
+template <class Op>
+static hipError_t launch_group(const std::vector<typename Op::A> &v, const std::vector<long> &blocks,
+                               Staging *st, hipStream_t s)
 {
-    Geo g = geometry(MODE, a.M, a.P, a.K, a.off, a.coef->n, a.part ? a.part_cap : 0);
-    kp.tiles_m = g.tiles_m;
-    kp.tiles_n = g.tiles_n;
-    kp.nsplit = g.nsplit;
-    kp.part = a.part;
-    const unsigned blocks = (unsigned)((long)g.tiles_m * g.tiles_n * g.nsplit);
-    if constexpr (MODE == GM_BF16X3) {
-        hipLaunchKernelGGL((k_toep_bf16x3<EPI>), dim3(blocks), dim3(256), 0, s, kp);
-    } else if (a.P <= 32) {
-        hipLaunchKernelGGL((k_toep_narrow<MODE, EPI>), dim3(blocks), dim3(256), 0, s, kp);
-    } else if (g.variant == 1) {
-        hipLaunchKernelGGL((k_toep_wide<MODE, EPI, 1>), dim3(blocks), dim3(256), 0, s, kp);
+    using A = typename Op::A;
+    if (v.empty()) return hipSuccess;
+    if (v.size() > 1 && !st) {   // no staging area: one launch per set
+        for (size_t i = 0; i < v.size(); ++i) {
+            hipError_t e = launch_group<Op>({v[i]}, {blocks[i]}, nullptr, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    Grp<A> g{};
+    long total = 0;
+    if (v.size() == 1) {
+        if (st && st->record) return hipSuccess;
+        g.one = v[0];
+        g.n = 1;
+        total = blocks[0];
     } else {
-        hipLaunchKernelGGL((k_toep_wide<MODE, EPI, 0>), dim3(blocks), dim3(256), 0, s, kp);
+        if (!st) return hipErrorInvalidValue;
+        std::vector<int> start(v.size() + 1, 0);
+        for (size_t i = 0; i < v.size(); ++i) start[i + 1] = start[i] + (int)blocks[i];
+        const void *dm = st->put(v.data(), sizeof(A) * v.size());
+        const void *ds = st->put(start.data(), sizeof(int) * start.size());
+        if (st->record) return hipSuccess;
+        g.one = v[0];
+        g.many = (const A *)dm;
+        g.start = (const int *)ds;
+        g.n = (int)v.size();
+        total = start.back();
     }
-    if (g.nsplit > 1) {
-        using PT = typename std::conditional<MODE == GM_F64, double, float>::type;
-        hipLaunchKernelGGL((k_splitk_reduce<EPI, PT>), grid_for((long)a.M * a.P), dim3(256), 0, s, kp);
-    }
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_group<Op>, dim3((unsigned)total), dim3(kThreads), 0, s, g);
     return hipGetLastError();
 }
 
-template <int MODE>
-static hipError_t launch_mode(const GemmArgs &a, KP &kp, hipStream_t s)
+template <int MODE, int EPI>
+static void launch_product_kernel(int kind, const KGrp &g, unsigned blocks, hipStream_t s)
 {
-    switch (a.epi) {
-    case EPI_STORE: return launch_mode_epi<MODE, EPI_STORE>(a, kp, s);
-    case EPI_SCATTER: return launch_mode_epi<MODE, EPI_SCATTER>(a, kp, s);
-    case EPI_SCATTER_ADD: return launch_mode_epi<MODE, EPI_SCATTER_ADD>(a, kp, s);
-    case EPI_SUB: return launch_mode_epi<MODE, EPI_SUB>(a, kp, s);
+    if constexpr (MODE == GM_BF16X3) {
+        hipLaunchKernelGGL((k_toep_bf16x3<EPI>), dim3(blocks), dim3(256), 0, s, g);
+    } else {
+        if (kind == 0) hipLaunchKernelGGL((k_toep_narrow<MODE, EPI>), dim3(blocks), dim3(256), 0, s, g);
+        else if (kind == 2) hipLaunchKernelGGL((k_toep_wide<MODE, EPI, 1>), dim3(blocks), dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((k_toep_wide<MODE, EPI, 0>), dim3(blocks), dim3(256), 0, s, g);
+    }
+}
+
+// Products of one (mode, epilogue, kernel) class: one launch, plus one
+// grouped reduce launch for the products whose K range is split.
+template <int MODE, int EPI>
+static hipError_t launch_class(std::vector<KP> &kps, const std::vector<Geo> &geos, Staging *st, hipStream_t s)
+{
+    using PT = typename std::conditional<MODE == GM_F64, double, float>::type;
+    if (kps.size() > 1 && !st) {   // no staging area: one launch per product
+        for (size_t i = 0; i < kps.size(); ++i) {
+            std::vector<KP> one{kps[i]};
+            hipError_t e = launch_class<MODE, EPI>(one, {geos[i]}, nullptr, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const int kind = geos[0].kind;
+    KGrp g{};
+    long total = 0;
+    if (kps.size() == 1) {
+        if (st && st->record) return hipSuccess;
+        g.one = kps[0];
+        g.n = 1;
+        total = (long)kps[0].tiles_m * kps[0].tiles_n * kps[0].nsplit;
+    } else {
+        if (!st) return hipErrorInvalidValue;
+        // work items of every product with their K extent, longest first
+        struct It { int steps, p, b; };
+        std::vector<It> items;
+        for (size_t p = 0; p < kps.size(); ++p) {
+            const KP &kp = kps[p];
+            const Geo &ge = geos[p];
+            const long nitems = (long)kp.tiles_m * kp.tiles_n * kp.nsplit;
+            for (long b = 0; b < nitems; ++b) {
+                const long t = b / kp.nsplit;
+                const int sidx = (int)(b - t * kp.nsplit);
+                const int tm = kp.tiles_m - 1 - (int)(t / kp.tiles_n);
+                const int nk = tile_steps(kp.K, kp.off, kp.ncoef, ge.BM, ge.BK, tm);
+                const int st0 = (int)((long)nk * sidx / kp.nsplit), st1 = (int)((long)nk * (sidx + 1) / kp.nsplit);
+                items.push_back({st1 - st0, (int)p, (int)b});
+            }
+        }
+        std::stable_sort(items.begin(), items.end(), [](const It &x, const It &y) { return x.steps > y.steps; });
+        std::vector<int2> tab(items.size());
+        for (size_t i = 0; i < items.size(); ++i) tab[i] = make_int2(items[i].p, items[i].b);
+        const void *dk = st->put(kps.data(), sizeof(KP) * kps.size());
+        const void *di = st->put(tab.data(), sizeof(int2) * tab.size());
+        total = (long)tab.size();
+        if (!st->record) {
+            g.one = kps[0];
+            g.many = (const KP *)dk;
+            g.items = (const int2 *)di;
+            g.n = (int)kps.size();
+        }
+    }
+    std::vector<KP> red;
+    std::vector<long> rblocks;
+    for (const KP &kp : kps)
+        if (kp.nsplit > 1) {
+            red.push_back(kp);
+            rblocks.push_back(blocks_for((long)kp.M * kp.P));
+        }
+    if (!(st && st->record) && total > 0) launch_product_kernel<MODE, EPI>(kind, g, (unsigned)total, s);
+    if (!red.empty()) {
+        hipError_t e = launch_group<OpReduce<EPI, PT>>(red, rblocks, st, s);
+        if (e != hipSuccess) return e;
+    }
+    return (st && st->record) ? hipSuccess : hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_mode(int epi, std::vector<KP> &kps, const std::vector<Geo> &geos, Staging *st,
+                              hipStream_t s)
+{
+    switch (epi) {
+    case EPI_STORE: return launch_class<MODE, EPI_STORE>(kps, geos, st, s);
+    case EPI_SUB: return launch_class<MODE, EPI_SUB>(kps, geos, st, s);
+    }
+    if constexpr (MODE == GM_F64) {
+        if (epi == EPI_SCATTER) return launch_class<MODE, EPI_SCATTER>(kps, geos, st, s);
+    } else {
+        if (epi == EPI_SCATTER_ADD) return launch_class<MODE, EPI_SCATTER_ADD>(kps, geos, st, s);
+        if (epi == EPI_ADD) return launch_class<MODE, EPI_ADD>(kps, geos, st, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_toep_gemm(const GemmArgs &a, hipStream_t s)
+hipError_t launch_toep_gemm(const std::vector<GemmArgs> &as, Staging *st, hipStream_t s)
 {
-    if (a.M <= 0 || a.P <= 0) return hipSuccess;
-    KP kp{};
-    kp.M = a.M; kp.P = a.P; kp.K = a.K; kp.off = a.off; kp.ncoef = a.coef->n;
-    kp.B = a.B; kp.Bhi = (const uint16_t *)a.Bhi; kp.Blo = (const uint16_t *)a.Blo; kp.ldb = a.ldb;
-    kp.ea = a.ea;
-    switch (a.mode) {
-    case GM_F64: kp.coef = a.coef->d64; return launch_mode<GM_F64>(a, kp, s);
-    case GM_F32: kp.coef = a.coef->d32; return launch_mode<GM_F32>(a, kp, s);
-    case GM_BF16X3:
-        kp.fhi = a.coef->fhi; kp.flo = a.coef->flo;
-        return launch_mode<GM_BF16X3>(a, kp, s);
+    // classes of (mode, epilogue, kernel); one launch each
+    std::map<int, std::vector<size_t>> cls;
+    std::vector<Geo> geo(as.size());
+    for (size_t i = 0; i < as.size(); ++i) {
+        const GemmArgs &a = as[i];
+        if (a.M <= 0 || a.P <= 0) continue;
+        geo[i] = geometry(a.mode, a.M, a.P, a.K, a.off, a.coef->n, a.part ? a.part_cap : 0, a.knobs);
+        cls[(a.mode << 8) | (a.epi << 4) | geo[i].kind].push_back(i);
     }
-    return hipErrorInvalidValue;
+    for (auto &kv : cls) {
+        const std::vector<size_t> &idx = kv.second;
+        std::vector<KP> kps;
+        std::vector<Geo> geos;
+        if (idx.size() > 1) {
+            // a group: the launch is as long as its total work over the
+            // concurrent blocks or its longest item, whichever is larger, so
+            // split only the products whose longest tile exceeds that share
+            const Geo &g0 = geo[idx[0]];
+            const double slots = (g0.kind == 0) ? 1024.0 : (g0.kind == 3) ? 256.0 : 512.0;
+            double work = 0;
+            std::vector<int> longest(idx.size());
+            for (size_t j = 0; j < idx.size(); ++j) {
+                const GemmArgs &a = as[idx[j]];
+                Geo g = tiles(a.mode, a.M, a.P, a.knobs);
+                for (int tm = 0; tm < g.tiles_m; ++tm)
+                    work += (double)tile_steps(a.K, a.off, a.coef->n, g.BM, g.BK, tm) * g.tiles_n;
+                longest[j] = tile_steps(a.K, a.off, a.coef->n, g.BM, g.BK, g.tiles_m - 1);
+            }
+            const double share = std::max(1.0, work / slots);
+            for (size_t j = 0; j < idx.size(); ++j) {
+                const GemmArgs &a = as[idx[j]];
+                Geo g = tiles(a.mode, a.M, a.P, a.knobs);
+                int ns = (int)std::ceil(longest[j] / share);
+                ns = std::min(ns, std::min(64, std::max(1, longest[j] / 8)));
+                g.nsplit = split_cap(g, a.mode, a.M, a.P, ns, a.part ? a.part_cap : 0);
+                geo[idx[j]] = g;
+            }
+        }
+        for (size_t i : idx) {
+            const GemmArgs &a = as[i];
+            const Geo &g = geo[i];
+            KP kp{};
+            kp.M = a.M; kp.P = a.P; kp.K = a.K; kp.off = a.off; kp.ncoef = a.coef->n;
+            kp.tiles_m = g.tiles_m; kp.tiles_n = g.tiles_n; kp.nsplit = g.nsplit;
+            kp.coef = (a.mode == GM_F64) ? (const void *)a.coef->d64 : (const void *)a.coef->d32;
+            kp.fhi = a.coef->fhi; kp.flo = a.coef->flo;
+            kp.B = a.B; kp.Bhi = (const uint16_t *)a.Bhi; kp.Blo = (const uint16_t *)a.Blo; kp.ldb = a.ldb;
+            kp.part = a.part;
+            kp.ea = a.ea;
+            kps.push_back(kp);
+            geos.push_back(g);
+        }
+        const int mode = kv.first >> 8, epi = (kv.first >> 4) & 15;
+        hipError_t e = hipErrorInvalidValue;
+        if (mode == GM_F64) e = launch_mode<GM_F64>(epi, kps, geos, st, s);
+        else if (mode == GM_F32) e = launch_mode<GM_F32>(epi, kps, geos, st, s);
+        else if (mode == GM_BF16X3) e = launch_mode<GM_BF16X3>(epi, kps, geos, st, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int product_kernel_kind(int mode, int M, int P, const TileKnobs &kn)
+{
+    return tiles(mode, M, P, kn).kind;
 }
 
 // ---------------------------------------------------------------------------
 // Colour right-hand side of the smoother (Section 3, eq. red-black; Section 6,
 // eq. red-black_2d): b = f + c d g + (neighbour sum) / h^2 at the points of
 // one colour, gathered into a dense panel (the B operand of the product).
-template <typename S>
-__global__ void k_rhs_panel(int dims, int n, int colour, int M, int Pc, const double *F, double *U,
-                            const double *cd, const double *g, double ih2, double lam0, S *panel,
-                            long ldp)
-{
-    long P = (dims == 1) ? n : (long)n * n;
-    long total = (long)M * Pc;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        int k = (int)(e / Pc), j = (int)(e - (long)k * Pc);
-        int pt = colour_point(dims, n, colour, j);
-        double *Uk = U + (long)k * P;
-        double b = F[(long)k * P + pt] + nbr_sum(Uk, dims, n, pt) * ih2;
-        if (g) b += cd[k] * g[pt];
-        panel[(long)k * ldp + j] = (S)b;
-        if (lam0 != 0.0) Uk[pt] = lam0 * b;
+template <typename S> struct OpRhsPanel {
+    using A = RhsArgs;
+    __device__ static void run(const RhsArgs &a, long lb, long nb)
+    {
+        const int Pc = colour_count(a.dims, a.n, a.colour);
+        const long P = (a.dims == 1) ? a.n : (long)a.n * a.n;
+        GLOBAL S *panel = gview_rw<S>(a.panel);
+        const GLOBAL double *F = gview<double>(a.F), *cd = gview<double>(a.cd), *g = gview<double>(a.g);
+        GLOBAL double *U = gview_rw<double>(a.U);
+        GRID_STRIDE(e, (long)a.M * Pc) {
+            int k = (int)(e / Pc), j = (int)(e - (long)k * Pc);
+            int pt = colour_point(a.dims, a.n, a.colour, j);
+            GLOBAL double *Uk = U + (long)k * P;
+            double b = F[(long)k * P + pt] + nbr_sum(Uk, a.dims, a.n, pt) * a.ih2;
+            if (a.g) b += cd[k] * g[pt];
+            panel[(long)k * a.ldp + j] = (S)b;
+            if (a.lam0 != 0.0) Uk[pt] = a.lam0 * b;
+        }
     }
-}
+};
 
-__device__ inline void store_split8(const float *b, uint16_t *hi, uint16_t *lo, long e)
+__device__ inline void store_split8(const float *b, void *hi, void *lo, long e)
 {
     uint16_t h8[8], l8[8];
 #pragma unroll
@@ -691,269 +943,297 @@ __device__ inline void store_split8(const float *b, uint16_t *hi, uint16_t *lo, 
         h8[q] = hb;
         l8[q] = f2bf(b[q] - bf2f(hb));
     }
-    uint4 vh, vl;
+    u32x4 vh, vl;
     vh.x = h8[0] | ((uint32_t)h8[1] << 16); vh.y = h8[2] | ((uint32_t)h8[3] << 16);
     vh.z = h8[4] | ((uint32_t)h8[5] << 16); vh.w = h8[6] | ((uint32_t)h8[7] << 16);
     vl.x = l8[0] | ((uint32_t)l8[1] << 16); vl.y = l8[2] | ((uint32_t)l8[3] << 16);
     vl.z = l8[4] | ((uint32_t)l8[5] << 16); vl.w = l8[6] | ((uint32_t)l8[7] << 16);
-    ((uint4 *)hi)[e] = vh;
-    ((uint4 *)lo)[e] = vl;
+    gview_rw<u32x4>(hi)[e] = vh;
+    gview_rw<u32x4>(lo)[e] = vl;
 }
 
 // Same right-hand side as split BF16 hi/lo in the k8-packed layout
 // [Mpad/8][ldp][8] (zero outside k < M, j < Pc).  One thread builds the 8
 // time rows of one column.
-__global__ void k_rhs_panel_packed(int dims, int n, int colour, int M, int Mpad, int Pc,
-                                   const double *F, double *U, const double *cd, const double *g,
-                                   double ih2, double lam0, uint16_t *hi, uint16_t *lo, long ldp)
-{
-    long P = (dims == 1) ? n : (long)n * n;
-    long total = (long)(Mpad / 8) * ldp;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        int kg = (int)(e / ldp), j = (int)(e - (long)kg * ldp);
-        float b8[8];
-        int pt = (j < Pc) ? colour_point(dims, n, colour, j) : 0;
+struct OpRhsPacked {
+    using A = RhsArgs;
+    __device__ static void run(const RhsArgs &a, long lb, long nb)
+    {
+        const int Pc = colour_count(a.dims, a.n, a.colour);
+        const long P = (a.dims == 1) ? a.n : (long)a.n * a.n;
+        const GLOBAL double *F = gview<double>(a.F), *cd = gview<double>(a.cd), *g = gview<double>(a.g);
+        GLOBAL double *U = gview_rw<double>(a.U);
+        GRID_STRIDE(e, (long)(a.Mpad / 8) * a.ldp) {
+            int kg = (int)(e / a.ldp), j = (int)(e - (long)kg * a.ldp);
+            float b8[8];
+            int pt = (j < Pc) ? colour_point(a.dims, a.n, a.colour, j) : 0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            int k = kg * 8 + q;
-            double b = 0.0;
-            if (k < M && j < Pc) {
-                double *Uk = U + (long)k * P;
-                b = F[(long)k * P + pt] + nbr_sum(Uk, dims, n, pt) * ih2;
-                if (g) b += cd[k] * g[pt];
-                if (lam0 != 0.0) Uk[pt] = lam0 * b;
+            for (int q = 0; q < 8; ++q) {
+                int k = kg * 8 + q;
+                double b = 0.0;
+                if (k < a.M && j < Pc) {
+                    GLOBAL double *Uk = U + (long)k * P;
+                    b = F[(long)k * P + pt] + nbr_sum(Uk, a.dims, a.n, pt) * a.ih2;
+                    if (a.g) b += cd[k] * g[pt];
+                    if (a.lam0 != 0.0) Uk[pt] = a.lam0 * b;
+                }
+                b8[q] = (float)b;
             }
-            b8[q] = (float)b;
+            store_split8(b8, a.panel, a.panel_lo, e);
         }
-        store_split8(b8, hi, lo, e);
     }
-}
+};
 
 // Residual (Section 2, eq. discrete_model_IVP_1; Section 6) from the Toeplitz
 // product already stored in out: out = (f + c d g - diag u - A_h u) - out.
 // With lo != nullptr the iterate is the double-double hi + lo and A_h is
 // applied with error-free transformations.
-__global__ void k_resid_post(int dims, int n, int M, const double *F, const double *U, const double *lo,
-                             const double *cd, const double *g, double ih2, double diag, double *out)
-{
-    long P = (dims == 1) ? n : (long)n * n;
-    long total = (long)M * P;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        int k = (int)(e / P), p = (int)(e - (long)k * P);
-        const double *Uk = U + (long)k * P;
-        double rhs = F[e];
-        if (g) rhs += cd[k] * g[p];
-        if (diag != 0.0) rhs -= diag * Uk[p];
-        double r;
-        if (lo) {
-            double shi, slo;
-            stencil_dd(Uk, lo + (long)k * P, dims, n, p, shi, slo);
-            r = (rhs - shi * ih2) - slo * ih2;
-        } else {
-            double st = (dims == 1 ? 2.0 : 4.0) * Uk[p] - nbr_sum(Uk, dims, n, p);
-            r = rhs - st * ih2;
+struct OpPost {
+    using A = PostArgs;
+    __device__ static void run(const PostArgs &a, long lb, long nb)
+    {
+        const long P = (a.dims == 1) ? a.n : (long)a.n * a.n;
+        const GLOBAL double *F = gview<double>(a.F), *U = gview<double>(a.U), *lo = gview<double>(a.lo);
+        const GLOBAL double *cd = gview<double>(a.cd), *g = gview<double>(a.g);
+        GLOBAL double *out = gview_rw<double>(a.out);
+        GRID_STRIDE(e, (long)a.M * P) {
+            int k = (int)(e / P), p = (int)(e - (long)k * P);
+            const GLOBAL double *Uk = U + (long)k * P;
+            double rhs = F[e];
+            if (a.g) rhs += cd[k] * g[p];
+            if (a.diag != 0.0) rhs -= a.diag * Uk[p];
+            double r;
+            if (a.lo) {
+                double shi, slo;
+                stencil_dd(Uk, lo + (long)k * P, a.dims, a.n, p, shi, slo);
+                r = (rhs - shi * a.ih2) - slo * a.ih2;
+            } else {
+                double st = (a.dims == 1 ? 2.0 : 4.0) * Uk[p] - nbr_sum(Uk, a.dims, a.n, p);
+                r = rhs - st * a.ih2;
+            }
+            out[e] = r - out[e];
         }
-        out[e] = r - out[e];
     }
-}
+};
 
-__global__ void k_split_bf16(int M, int Mpad, int P, const double *X, uint16_t *hi, uint16_t *lo,
-                             long ldp)
-{
-    long total = (long)(Mpad / 8) * ldp;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        int kg = (int)(e / ldp), j = (int)(e - (long)kg * ldp);
-        float b8[8];
+// Low-precision operands of the products (and the D&C diagonal part).
+struct OpOperandF32 {
+    using A = OperandArgs;
+    __device__ static void run(const OperandArgs &a, long lb, long nb)
+    {
+        GLOBAL float *out = gview_rw<float>(a.out);
+        const GLOBAL double *X = gview<double>(a.X);
+        GLOBAL double *X2 = gview_rw<double>(a.X2);
+        GRID_STRIDE(e, (long)a.M * a.P) {
+            int k = (int)(e / a.P), j = (int)(e - (long)k * a.P);
+            double x = X[(long)k * a.ldx + j];
+            out[(long)k * a.ldp + j] = (float)x;
+            if (a.X2) X2[(long)k * a.ldx + j] = a.s2 * x;
+        }
+    }
+};
+struct OpOperandBf16 {
+    using A = OperandArgs;
+    __device__ static void run(const OperandArgs &a, long lb, long nb)
+    {
+        const GLOBAL double *X = gview<double>(a.X);
+        GLOBAL double *X2 = gview_rw<double>(a.X2);
+        GRID_STRIDE(e, (long)(a.Mpad / 8) * a.ldp) {
+            int kg = (int)(e / a.ldp), j = (int)(e - (long)kg * a.ldp);
+            float b8[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            int k = kg * 8 + q;
-            b8[q] = (k < M && j < P) ? (float)X[(long)k * P + j] : 0.0f;
+            for (int q = 0; q < 8; ++q) {
+                int k = kg * 8 + q;
+                double x = 0.0;
+                if (k < a.M && j < a.P) {
+                    x = X[(long)k * a.ldx + j];
+                    if (a.X2) X2[(long)k * a.ldx + j] = a.s2 * x;
+                }
+                b8[q] = (float)x;
+            }
+            store_split8(b8, a.out, a.out_lo, e);
         }
-        store_split8(b8, hi, lo, e);
     }
-}
-
-__global__ void k_narrow_f32(long n, const double *x, float *y)
-{
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        y[i] = (float)x[i];
-}
-
-__global__ void k_widen(long n, const float *x, double *y)
-{
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        y[i] = (double)x[i];
-}
+};
 
 // Full weighting (Section 3; Section 6): coarse node J on fine node 2J,
-// weights [1 2 1]/4 (1D) and their tensor product /16 (2D).
-__global__ void k_restrict(int dims, int nf, int M, const double *rf, double *rc)
-{
-    int nc = (nf - 1) / 2;
-    long Pc = (dims == 1) ? nc : (long)nc * nc;
-    long Pf = (dims == 1) ? nf : (long)nf * nf;
-    long total = (long)M * Pc;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        int k = (int)(e / Pc);
-        long q = e - (long)k * Pc;
-        const double *r = rf + (long)k * Pf;
-        double v;
-        if (dims == 1) {
-            int x = 2 * (int)q + 1;
-            v = 0.25 * (r[x - 1] + 2.0 * r[x] + r[x + 1]);
-        } else {
-            int I = (int)(q % nc), J = (int)(q / nc);
-            int x = 2 * I + 1, y = 2 * J + 1;
-            const double *r0 = r + (long)(y - 1) * nf, *r1 = r + (long)y * nf, *r2 = r + (long)(y + 1) * nf;
-            v = (r0[x - 1] + 2.0 * r0[x] + r0[x + 1] + 2.0 * (r1[x - 1] + 2.0 * r1[x] + r1[x + 1])
-                 + r2[x - 1] + 2.0 * r2[x] + r2[x + 1]) * (1.0 / 16.0);
-        }
-        rc[e] = v;
-    }
-}
-
-// Linear / bilinear interpolation of the coarse correction, added to the fine
-// iterate (Section 3; Section 6); coarse values on the boundary are zero.
-__device__ inline double coarse_at(const double *e, int nc, int X)  // X: 1-based coarse index
+// weights [1 2 1]/4 (1D) and their tensor product /16 (2D).  Linear /
+// bilinear interpolation of the coarse correction, added to the fine iterate;
+// coarse values on the boundary are zero.
+__device__ inline double coarse_at(const GLOBAL double *e, int nc, int X)  // X: 1-based coarse index
 {
     return (X >= 1 && X <= nc) ? e[X - 1] : 0.0;
 }
 
-__global__ void k_prolong_add(int dims, int nc, int M, const double *ec, double *uf)
-{
-    int nf = 2 * nc + 1;
-    long Pc = (dims == 1) ? nc : (long)nc * nc;
-    long Pf = (dims == 1) ? nf : (long)nf * nf;
-    long total = (long)M * Pf;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        int k = (int)(e / Pf);
-        long p = e - (long)k * Pf;
-        const double *c = ec + (long)k * Pc;
-        double v;
-        if (dims == 1) {
-            int nn = (int)p + 1;   // paper numbering
-            v = 0.5 * (coarse_at(c, nc, nn / 2) + coarse_at(c, nc, (nn + 1) / 2));
-        } else {
-            int nn = (int)(p % nf) + 1, ll = (int)(p / nf) + 1;
-            int xa = nn / 2, xb = (nn + 1) / 2, ya = ll / 2, yb = (ll + 1) / 2;
-            auto at = [&](int X, int Y) -> double {
-                return (X >= 1 && X <= nc && Y >= 1 && Y <= nc) ? c[(long)(Y - 1) * nc + (X - 1)] : 0.0;
-            };
-            v = 0.25 * (at(xa, ya) + at(xb, ya) + at(xa, yb) + at(xb, yb));
+struct OpXfer {
+    using A = XferArgs;
+    __device__ static void restrict_fw(const XferArgs &a, long lb, long nb)
+    {
+        const int nf = a.n, nc = (nf - 1) / 2;
+        const long Pc = (a.dims == 1) ? nc : (long)nc * nc;
+        const long Pf = (a.dims == 1) ? nf : (long)nf * nf;
+        GRID_STRIDE(e, (long)a.M * Pc) {
+            int k = (int)(e / Pc);
+            long q = e - (long)k * Pc;
+            const GLOBAL double *r = gview<double>(a.src) + (long)k * Pf;
+            double v;
+            if (a.dims == 1) {
+                int x = 2 * (int)q + 1;
+                v = 0.25 * (r[x - 1] + 2.0 * r[x] + r[x + 1]);
+            } else {
+                int I = (int)(q % nc), J = (int)(q / nc);
+                int x = 2 * I + 1, y = 2 * J + 1;
+                const GLOBAL double *r0 = r + (long)(y - 1) * nf, *r1 = r + (long)y * nf, *r2 = r + (long)(y + 1) * nf;
+                v = (r0[x - 1] + 2.0 * r0[x] + r0[x + 1] + 2.0 * (r1[x - 1] + 2.0 * r1[x] + r1[x + 1])
+                     + r2[x - 1] + 2.0 * r2[x] + r2[x + 1]) * (1.0 / 16.0);
+            }
+            gview_rw<double>(a.dst)[e] = v;
         }
-        uf[e] += v;
     }
-}
-
-__global__ void k_scaled_fill(long M, long P, const double *cd, const double *g, double *u)
-{
-    long total = M * P;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        u[e] = g ? cd[e / P] * g[e % P] : 0.0;
+    __device__ static void prolong_add(const XferArgs &a, long lb, long nb)
+    {
+        const int nc = a.n, nf = 2 * nc + 1;
+        const long Pc = (a.dims == 1) ? nc : (long)nc * nc;
+        const long Pf = (a.dims == 1) ? nf : (long)nf * nf;
+        GRID_STRIDE(e, (long)a.M * Pf) {
+            int k = (int)(e / Pf);
+            long p = e - (long)k * Pf;
+            const GLOBAL double *c = gview<double>(a.src) + (long)k * Pc;
+            double v;
+            if (a.dims == 1) {
+                int nn = (int)p + 1;   // paper numbering
+                v = 0.5 * (coarse_at(c, nc, nn / 2) + coarse_at(c, nc, (nn + 1) / 2));
+            } else {
+                int nn = (int)(p % nf) + 1, ll = (int)(p / nf) + 1;
+                int xa = nn / 2, xb = (nn + 1) / 2, ya = ll / 2, yb = (ll + 1) / 2;
+                auto at = [&](int X, int Y) -> double {
+                    return (X >= 1 && X <= nc && Y >= 1 && Y <= nc) ? c[(long)(Y - 1) * nc + (X - 1)] : 0.0;
+                };
+                v = 0.25 * (at(xa, ya) + at(xb, ya) + at(xa, yb) + at(xb, yb));
+            }
+            gview_rw<double>(a.dst)[e] += v;
+        }
     }
-}
-
-__global__ void k_fill(long M, long P, const double *g, double *u)
-{
-    long total = M * P;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-         e += (long)gridDim.x * blockDim.x) {
-        u[e] = g ? g[e % P] : 0.0;
+    __device__ static void run(const XferArgs &a, long lb, long nb)
+    {
+        if (a.dir == 0) restrict_fw(a, lb, nb);
+        else prolong_add(a, lb, nb);
     }
-}
+};
 
-// Deterministic norm partials: each block reduces a fixed contiguous share.
-constexpr int kNormThreads = 256;
-int norm_partial_blocks(long n)
-{
-    long b = (n + 8L * kNormThreads - 1) / (8L * kNormThreads);
-    if (b < 1) b = 1;
-    if (b > 2048) b = 2048;
-    return (int)b;
-}
-
-__global__ __launch_bounds__(kNormThreads) void k_norm_partials(long n, const double *x, double *partials)
-{
-    __shared__ double smax[kNormThreads], ssum[kNormThreads];
-    long per = (n + gridDim.x - 1) / gridDim.x;
-    long beg = (long)blockIdx.x * per, end = min(n, beg + per);
-    double mx = 0.0, sq = 0.0;
-    for (long e = beg + threadIdx.x; e < end; e += kNormThreads) {
-        double v = x[e];
-        double a = fabs(v);
-        mx = (a > mx || a != a) ? a : mx;   // keeps a NaN once seen
-        sq += v * v;
+struct OpFill {
+    using A = FillArgs;
+    __device__ static void run(const FillArgs &a, long lb, long nb)
+    {
+        const GLOBAL double *cd = gview<double>(a.cd), *g = gview<double>(a.g);
+        GLOBAL double *u = gview_rw<double>(a.u);
+        GRID_STRIDE(e, a.M * a.P) {
+            double v = 0.0;
+            if (a.g) v = a.scaled ? cd[e / a.P] * g[e % a.P] : g[e % a.P];
+            u[e] = v;
+        }
     }
+};
+
+// Deterministic norms: block b of a set reduces a fixed contiguous share
+// into partials[b]; one block per set reduces the partials in a fixed order.
+// A NaN, once seen, is kept by the max.
+__device__ inline double nan_max(double a, double m) { return (a > m || a != a) ? a : m; }
+
+__device__ inline void block_reduce(double &mx, double &sq)
+{
+    __shared__ double smax[kThreads], ssum[kThreads];
     smax[threadIdx.x] = mx;
     ssum[threadIdx.x] = sq;
     __syncthreads();
-    for (int w = kNormThreads / 2; w > 0; w >>= 1) {
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
-            double a = smax[threadIdx.x + w];
-            double m = smax[threadIdx.x];
-            smax[threadIdx.x] = (a > m || a != a) ? a : m;
+            smax[threadIdx.x] = nan_max(smax[threadIdx.x + w], smax[threadIdx.x]);
             ssum[threadIdx.x] += ssum[threadIdx.x + w];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = smax[0];
-        partials[2 * blockIdx.x + 1] = ssum[0];
-    }
+    mx = smax[0];
+    sq = ssum[0];
 }
 
-__global__ __launch_bounds__(kNormThreads) void k_norm_final(int nblk, const double *partials, double *out2)
-{
-    __shared__ double smax[kNormThreads], ssum[kNormThreads];
-    double mx = 0.0, sq = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kNormThreads) {
-        double a = partials[2 * b];
-        mx = (a > mx || a != a) ? a : mx;
-        sq += partials[2 * b + 1];
-    }
-    smax[threadIdx.x] = mx;
-    ssum[threadIdx.x] = sq;
-    __syncthreads();
-    for (int w = kNormThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            double a = smax[threadIdx.x + w];
-            double m = smax[threadIdx.x];
-            smax[threadIdx.x] = (a > m || a != a) ? a : m;
-            ssum[threadIdx.x] += ssum[threadIdx.x + w];
+struct OpNormPartial {
+    using A = NormArgs;
+    __device__ static void run(const NormArgs &a, long lb, long nb)
+    {
+        const long per = (a.n + nb - 1) / nb;
+        const long beg = lb * per, end = min(a.n, beg + per);
+        double mx = 0.0, sq = 0.0;
+        const GLOBAL double *x = gview<double>(a.x);
+        for (long e = beg + threadIdx.x; e < end; e += kThreads) {
+            double v = x[e];
+            mx = nan_max(fabs(v), mx);
+            sq += v * v;
         }
-        __syncthreads();
+        block_reduce(mx, sq);
+        if (threadIdx.x == 0) {
+            gview_rw<double>(a.partials)[2 * lb] = mx;
+            gview_rw<double>(a.partials)[2 * lb + 1] = sq;
+        }
     }
-    if (threadIdx.x == 0) {
-        out2[0] = smax[0];
-        out2[1] = sqrt(ssum[0]);
+};
+
+struct OpNormFinal {
+    using A = NormArgs;
+    __device__ static void run(const NormArgs &a, long, long)
+    {
+        double mx = 0.0, sq = 0.0;
+        const GLOBAL double *part = gview<double>(a.partials);
+        for (int b = threadIdx.x; b < a.nblk; b += kThreads) {
+            mx = nan_max(part[2 * b], mx);
+            sq += part[2 * b + 1];
+        }
+        block_reduce(mx, sq);
+        if (threadIdx.x == 0) {
+            gview_rw<double>(a.out2)[0] = mx;
+            gview_rw<double>(a.out2)[1] = sqrt(sq);
+        }
     }
-}
+};
 
 // (hi, lo) <- (hi, lo) + e as a renormalised double-double (TwoSum, then
 // fast renormalisation); with lo == nullptr a plain FP64 add.
-__global__ void k_dd_update(long n, const double *e, double *hi, double *lo)
-{
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        double d = e[i];
-        if (!lo) {
-            hi[i] += d;
-            continue;
+struct OpDD {
+    using A = DDArgs;
+    __device__ static void run(const DDArgs &a, long lb, long nb)
+    {
+        const GLOBAL double *ev = gview<double>(a.e);
+        GLOBAL double *hi = gview_rw<double>(a.hi), *lo = gview_rw<double>(a.lo);
+        GRID_STRIDE(i, a.n) {
+            double d = ev[i];
+            if (!a.lo) {
+                hi[i] += d;
+                continue;
+            }
+            double s, err;
+            two_sum(hi[i], d, s, err);
+            double l = lo[i] + err;
+            double h2 = s + l;
+            lo[i] = l - (h2 - s);
+            hi[i] = h2;
         }
-        double s, err;
-        two_sum(hi[i], d, s, err);
-        double l = lo[i] + err;
-        double h2 = s + l;
-        lo[i] = l - (h2 - s);
-        hi[i] = h2;
     }
-}
+};
+
+// The D&C solution panel back into the colour's points of the iterate.
+struct OpScatter {
+    using A = ScatterArgs;
+    __device__ static void run(const ScatterArgs &a, long lb, long nb)
+    {
+        const long P = (a.dims == 1) ? a.n : (long)a.n * a.n;
+        const GLOBAL double *X = gview<double>(a.X);
+        GLOBAL double *U = gview_rw<double>(a.U);
+        GRID_STRIDE(e, (long)a.M * a.Pc) {
+            int k = (int)(e / a.Pc), j = (int)(e - (long)k * a.Pc);
+            U[(long)k * P + colour_point(a.dims, a.n, a.colour, j)] = X[e];
+        }
+    }
+};
 
 // FP32 copy and BF16 fragment table of a coefficient vector.
 __global__ void k_build_coef(int n, const double *d64, float *d32, int nq, uint16_t *fhi, uint16_t *flo)
@@ -975,107 +1255,105 @@ __global__ void k_build_coef(int n, const double *d64, float *d32, int nq, uint1
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_rhs_panel(int fmt, int dims, int n, int colour, int M, int Mpad, const double *F,
-                            double *U, const double *cd, const double *g, double ih2, double lam0,
-                            void *panel, void *panel_lo, long ldp, hipStream_t s)
+// Launchers: one launch per argument-set type (the right-hand side and the
+// operands split by format).
+template <class Op, class Pred, class Count>
+static hipError_t launch_subset(const std::vector<typename Op::A> &v, Pred pred, Count count, Staging *st,
+                                hipStream_t s)
 {
-    int Pc = colour_count(dims, n, colour);
-    if (fmt == 2) {
-        long total = (long)(Mpad / 8) * ldp;
-        hipLaunchKernelGGL(k_rhs_panel_packed, grid_for(total), dim3(256), 0, s, dims, n, colour, M, Mpad,
-                           Pc, F, U, cd, g, ih2, lam0, (uint16_t *)panel, (uint16_t *)panel_lo, ldp);
-    } else if (fmt == 0) {
-        hipLaunchKernelGGL(k_rhs_panel<double>, grid_for((long)M * Pc), dim3(256), 0, s, dims, n, colour,
-                           M, Pc, F, U, cd, g, ih2, lam0, (double *)panel, ldp);
-    } else {
-        hipLaunchKernelGGL(k_rhs_panel<float>, grid_for((long)M * Pc), dim3(256), 0, s, dims, n, colour,
-                           M, Pc, F, U, cd, g, ih2, lam0, (float *)panel, ldp);
-    }
-    return hipGetLastError();
+    std::vector<typename Op::A> sub;
+    std::vector<long> blocks;
+    for (const auto &a : v)
+        if (pred(a)) {
+            sub.push_back(a);
+            blocks.push_back(count(a));
+        }
+    return launch_group<Op>(sub, blocks, st, s);
 }
 
-hipError_t launch_resid_post(int dims, int n, int M, const double *F, const double *U, const double *lo,
-                             const double *cd, const double *g, double ih2, double diag, double *out,
-                             hipStream_t s)
+#define RET_IF(e)                          \
+    do {                                   \
+        hipError_t e_ = (e);               \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)
+
+hipError_t launch_rhs(const std::vector<RhsArgs> &v, Staging *st, hipStream_t s)
 {
-    long total = (long)M * ((dims == 1) ? n : (long)n * n);
-    hipLaunchKernelGGL(k_resid_post, grid_for(total), dim3(256), 0, s, dims, n, M, F, U, lo, cd, g, ih2, diag,
-                       out);
-    return hipGetLastError();
+    auto elems = [](const RhsArgs &a) { return blocks_for((long)a.M * colour_count(a.dims, a.n, a.colour)); };
+    RET_IF(launch_subset<OpRhsPanel<double>>(v, [](const RhsArgs &a) { return a.fmt == 0; }, elems, st, s));
+    RET_IF(launch_subset<OpRhsPanel<float>>(v, [](const RhsArgs &a) { return a.fmt == 1; }, elems, st, s));
+    return launch_subset<OpRhsPacked>(
+        v, [](const RhsArgs &a) { return a.fmt == 2; },
+        [](const RhsArgs &a) { return blocks_for((long)(a.Mpad / 8) * a.ldp); }, st, s);
 }
 
-hipError_t launch_operand(int fmt, int M, int Mpad, int P, const double *X, void *out, void *out_lo,
-                          long ldp, hipStream_t s)
+hipError_t launch_post(const std::vector<PostArgs> &v, Staging *st, hipStream_t s)
 {
-    if (fmt == 2) {
-        long total = (long)(Mpad / 8) * ldp;
-        hipLaunchKernelGGL(k_split_bf16, grid_for(total), dim3(256), 0, s, M, Mpad, P, X, (uint16_t *)out,
-                           (uint16_t *)out_lo, ldp);
-    } else {
-        long n = (long)M * P;
-        hipLaunchKernelGGL(k_narrow_f32, grid_for(n), dim3(256), 0, s, n, X, (float *)out);
-    }
-    return hipGetLastError();
+    return launch_subset<OpPost>(
+        v, [](const PostArgs &) { return true; },
+        [](const PostArgs &a) { return blocks_for((long)a.M * ((a.dims == 1) ? a.n : (long)a.n * a.n)); }, st,
+        s);
 }
 
-hipError_t launch_widen(long n, const float *x, double *y, hipStream_t s)
+hipError_t launch_operand(const std::vector<OperandArgs> &v, Staging *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_widen, grid_for(n), dim3(256), 0, s, n, x, y);
-    return hipGetLastError();
+    RET_IF(launch_subset<OpOperandF32>(
+        v, [](const OperandArgs &a) { return a.fmt == 1; },
+        [](const OperandArgs &a) { return blocks_for((long)a.M * a.P); }, st, s));
+    return launch_subset<OpOperandBf16>(
+        v, [](const OperandArgs &a) { return a.fmt == 2; },
+        [](const OperandArgs &a) { return blocks_for((long)(a.Mpad / 8) * a.ldp); }, st, s);
 }
 
-hipError_t launch_restrict(int dims, int nf, int M, const double *rf, double *rc, hipStream_t s)
+hipError_t launch_xfer(const std::vector<XferArgs> &v, Staging *st, hipStream_t s)
 {
-    int nc = (nf - 1) / 2;
-    long total = (long)M * ((dims == 1) ? nc : (long)nc * nc);
-    hipLaunchKernelGGL(k_restrict, grid_for(total), dim3(256), 0, s, dims, nf, M, rf, rc);
-    return hipGetLastError();
+    return launch_subset<OpXfer>(
+        v, [](const XferArgs &) { return true; },
+        [](const XferArgs &a) {
+            long np = (a.dir == 0) ? (a.n - 1) / 2 : 2 * a.n + 1;
+            return blocks_for((long)a.M * ((a.dims == 1) ? np : np * np));
+        },
+        st, s);
 }
 
-hipError_t launch_prolong_add(int dims, int nc, int M, const double *ec, double *uf, hipStream_t s)
+hipError_t launch_fill(const std::vector<FillArgs> &v, Staging *st, hipStream_t s)
 {
-    int nf = 2 * nc + 1;
-    long total = (long)M * ((dims == 1) ? nf : (long)nf * nf);
-    hipLaunchKernelGGL(k_prolong_add, grid_for(total), dim3(256), 0, s, dims, nc, M, ec, uf);
-    return hipGetLastError();
+    return launch_subset<OpFill>(
+        v, [](const FillArgs &) { return true; }, [](const FillArgs &a) { return blocks_for(a.M * a.P); }, st, s);
 }
 
-hipError_t launch_scaled_fill(long M, long P, const double *cd, const double *g, double *u, hipStream_t s)
+int norm_partial_blocks(long n)
 {
-    hipLaunchKernelGGL(k_scaled_fill, grid_for(M * P), dim3(256), 0, s, M, P, cd, g, u);
-    return hipGetLastError();
+    long b = (n + 8L * kThreads - 1) / (8L * kThreads);
+    return (int)std::max(1L, std::min(b, 2048L));
 }
 
-hipError_t launch_fill(long M, long P, const double *g, double *u, hipStream_t s)
+hipError_t launch_norms(const std::vector<NormArgs> &v, Staging *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill, grid_for(M * P), dim3(256), 0, s, M, P, g, u);
-    return hipGetLastError();
+    RET_IF(launch_subset<OpNormPartial>(
+        v, [](const NormArgs &) { return true; }, [](const NormArgs &a) { return (long)a.nblk; }, st, s));
+    return launch_subset<OpNormFinal>(
+        v, [](const NormArgs &) { return true; }, [](const NormArgs &) { return 1L; }, st, s);
 }
 
-hipError_t launch_norm_partials(long n, const double *x, double *partials, int *nblk, hipStream_t s)
+hipError_t launch_dd_update(const std::vector<DDArgs> &v, Staging *st, hipStream_t s)
 {
-    int b = norm_partial_blocks(n);
-    *nblk = b;
-    hipLaunchKernelGGL(k_norm_partials, dim3(b), dim3(kNormThreads), 0, s, n, x, partials);
-    return hipGetLastError();
+    return launch_subset<OpDD>(
+        v, [](const DDArgs &) { return true; }, [](const DDArgs &a) { return blocks_for(a.n); }, st, s);
 }
 
-hipError_t launch_norm_final(int nblk, const double *partials, double *out2, hipStream_t s)
+hipError_t launch_scatter(const std::vector<ScatterArgs> &v, Staging *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kNormThreads), 0, s, nblk, partials, out2);
-    return hipGetLastError();
-}
-
-hipError_t launch_dd_update(long n, const double *e, double *hi, double *lo, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_dd_update, grid_for(n), dim3(256), 0, s, n, e, hi, lo);
-    return hipGetLastError();
+    return launch_subset<OpScatter>(
+        v, [](const ScatterArgs &) { return true; },
+        [](const ScatterArgs &a) { return blocks_for((long)a.M * a.Pc); }, st, s);
 }
 
 hipError_t launch_build_coef(ToepCoef &c, hipStream_t s)
 {
     long tot = (long)c.nq * 512 + c.n;
-    hipLaunchKernelGGL(k_build_coef, grid_for(tot), dim3(256), 0, s, c.n, c.d64, c.d32, c.nq, c.fhi, c.flo);
+    hipLaunchKernelGGL(k_build_coef, dim3((unsigned)blocks_for(tot)), dim3(kThreads), 0, s, c.n, c.d64, c.d32,
+                       c.nq, c.fhi, c.flo);
     return hipGetLastError();
 }
 

@@ -1,0 +1,258 @@
+"""GPU parity of the divide-and-conquer line solve, the batched solver, the
+graph replays and the autotuner, all through the C ABI against the oracle.
+
+Reference values come from ``oracle`` only.  Tolerances as in
+test_gpu_parity.py: FP64 steps 1e-12 of the term size (same sums, other
+order), FP64 solves 1e-10 and mixed-precision solves 1e-8 relative (max
+norm) against the exact discrete solution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_05400_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_05400_amd import binding
+    binding.load()
+    return binding
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relmax(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+def _rand(dims, N, M, seed):
+    rng = np.random.default_rng(seed)
+    shape = (M, N) if dims == 1 else (M, N, N)
+    return rng.standard_normal(shape), rng.standard_normal(shape), rng.standard_normal(shape[1:])
+
+
+# ---------------------------------------------------------------------------
+# D&C blocked forward substitution (Section 5.2): base blocks of Mb rows, the
+# last one ragged when Mb does not divide M
+
+DC_CASES = [(1, 63, 300, 0.5, 128), (1, 127, 1024, 0.3, 128), (1, 255, 640, 0.8, 256),
+            (2, 15, 384, 0.4, 128), (1, 31, 129, 0.6, 128)]
+
+
+@pytest.mark.parametrize("dims,N,M,alpha,Mb", DC_CASES)
+@pytest.mark.parametrize("first", [0, 1])
+def test_dc_sweep_matches_oracle(B, dims, N, M, alpha, Mb, first):
+    f, u, g = _rand(dims, N, M, 21)
+    ref = oracle.half_sweep(dims, N, M, alpha, first, f, u, g=g)
+    ref = oracle.half_sweep(dims, N, M, alpha, 1 - first, f, ref, g=g)
+    with B.Solver(N, M, alpha, dims=dims, first_colour=first, smoother="dc", dc_block=Mb) as s:
+        U = dev(u)
+        s.smooth(dev(f), U, g=dev(g), sweeps=1)
+        U = host(U)
+    assert relmax(U, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,N,M,alpha,Mb", DC_CASES[:3])
+def test_dc_cycle_matches_oracle(B, dims, N, M, alpha, Mb):
+    f, u, g = _rand(dims, N, M, 22)
+    ref = oracle.vcycle(dims, N, M, alpha, f, u, g=g)
+    with B.Solver(N, M, alpha, dims=dims, smoother="dc", dc_block=Mb) as s:
+        U = dev(u)
+        s.vcycle(dev(f), U, g=dev(g))
+        U = host(U)
+    assert relmax(U, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp64r", 1e-10), ("fp32", 1e-8), ("bf16x3", 1e-8)])
+@pytest.mark.parametrize("dims,N,M,alpha,Mb", [(1, 255, 1000, 0.4, 128), (2, 31, 512, 0.6, 256)])
+def test_dc_solve_matches_direct_solve(B, prec, tol, dims, N, M, alpha, Mb):
+    rng = np.random.default_rng(23)
+    K = 4
+    kx = rng.integers(1, 7, size=K).astype(np.int32)
+    ky = (rng.integers(1, 7, size=K) if dims == 2 else np.zeros(K, int)).astype(np.int32)
+    t = np.arange(1, M + 1) / M
+    s_ = rng.standard_normal((K, 1)) * t[None, :] ** 1.5
+    w = W.Workload(dims, N, M, alpha, 1.0, 1.0, kx, ky, s_)
+    f = w.forcing()
+    ref = oracle.direct_solve(dims, N, M, alpha, f)
+    with B.Solver(N, M, alpha, dims=dims, precision=prec, smoother="dc", dc_block=Mb) as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(dev(f), U, tol=1e-12)
+        U = host(U)
+    assert info["rc"] in (0, 2), info
+    assert relmax(U, ref) <= tol, (info, relmax(U, ref))
+
+
+def test_dc_block_covering_all_rows_is_inverse_solve(B):
+    dims, N, M, alpha = 1, 63, 200, 0.5
+    f, u, g = _rand(dims, N, M, 24)
+    outs = []
+    for opts in ({}, {"smoother": "dc", "dc_block": 256}):
+        with B.Solver(N, M, alpha, **opts) as s:
+            U = dev(u)
+            s.smooth(dev(f), U, g=dev(g))
+            outs.append(host(U))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_dc_block_must_be_multiple_of_128(B):
+    with pytest.raises(B.MgwrError):
+        B.Solver(15, 512, 0.5, smoother="dc", dc_block=100)
+
+
+# ---------------------------------------------------------------------------
+# batches: every stage one launch over all problems still iterating
+
+SMALL_BATCH = [(63, 64, 0.5), (127, 300, 0.2), (1, 40, 0.7), (255, 128, 0.9), (31, 1, 0.4),
+               (511, 520, 0.35), (15, 1000, 0.6)]
+
+
+def _modes_problem(N, M, alpha, seed):
+    w = W.random_modes_1d(N, M, alpha, seed=seed)
+    return w, w.forcing()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x3", 1e-8), ("fp32", 1e-8)])
+@pytest.mark.parametrize("graph", [1, 0])
+def test_batch_matches_direct_solves(B, prec, tol, graph):
+    ws = [_modes_problem(N, M, a, 100 + i) for i, (N, M, a) in enumerate(SMALL_BATCH)]
+    refs = [oracle.direct_solve(1, w.N, w.M, w.alpha, f) for w, f in ws]
+    b = B.Batch([w.N for w, _ in ws], [w.M for w, _ in ws], [w.alpha for w, _ in ws], precision=prec,
+                graph=graph)
+    us = [torch.zeros((w.M, w.N), dtype=torch.float64, device="cuda") for w, _ in ws]
+    rc, infos = b.solve([dev(f) for _, f in ws], us, tol=1e-12)
+    b.close()
+    for i, (u, ref, inf) in enumerate(zip(us, refs, infos)):
+        assert inf["status"] in ("ok", "stagnated"), (i, inf)
+        assert relmax(host(u), ref) <= tol, (i, inf, relmax(host(u), ref))
+
+
+def test_batch_iterations_match_single_solves(B):
+    """Each problem of a batch stops by its own test after the cycles it
+    takes alone (FP64, same algorithm; the products differ only in the
+    order of their sums)."""
+    ws = [_modes_problem(N, M, a, 200 + i) for i, (N, M, a) in enumerate(SMALL_BATCH)]
+    single = []
+    for w, f in ws:
+        with B.Solver(w.N, w.M, w.alpha) as s:
+            U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+            single.append(s.solve(dev(f), U, tol=1e-9)["iters"])
+    b = B.Batch([w.N for w, _ in ws], [w.M for w, _ in ws], [w.alpha for w, _ in ws])
+    us = [torch.zeros((w.M, w.N), dtype=torch.float64, device="cuda") for w, _ in ws]
+    _, infos = b.solve([dev(f) for _, f in ws], us, tol=1e-9)
+    b.close()
+    assert [i["iters"] for i in infos] == single
+
+
+def test_batch_with_initial_conditions_and_dc(B):
+    ws = [_modes_problem(N, M, a, 300 + i) for i, (N, M, a) in enumerate([(63, 300, 0.4), (127, 700, 0.7)])]
+    gs = [np.sin(np.pi * w.nodes()) for w, _ in ws]
+    refs = [oracle.direct_solve(1, w.N, w.M, w.alpha, f, g=g) for (w, f), g in zip(ws, gs)]
+    b = B.Batch([w.N for w, _ in ws], [w.M for w, _ in ws], [w.alpha for w, _ in ws], precision="bf16x3",
+                smoother="dc", dc_block=128)
+    us = [torch.zeros((w.M, w.N), dtype=torch.float64, device="cuda") for w, _ in ws]
+    rc, infos = b.solve([dev(f) for _, f in ws], us, gs=[dev(g) for g in gs], tol=1e-12)
+    b.close()
+    for u, ref, inf in zip(us, refs, infos):
+        assert relmax(host(u), ref) <= 1e-8, inf
+
+
+def test_batch_reports_failing_problem(B):
+    ws = [_modes_problem(31, 32, 0.5, 400), _modes_problem(63, 40, 0.5, 401)]
+    fs = [dev(f) for _, f in ws]
+    fs[1][5, 7] = float("nan")
+    b = B.Batch([31, 63], [32, 40], [0.5, 0.5])
+    us = [torch.zeros((w.M, w.N), dtype=torch.float64, device="cuda") for w, _ in ws]
+    rc, infos = b.solve(fs, us, tol=1e-10, raise_on_error=False)
+    b.close()
+    assert rc == B.MGWR_ENONFINITE
+    assert infos[0]["status"] in ("ok", "stagnated")
+    assert infos[1]["status"] == "enonfinite"
+
+
+# ---------------------------------------------------------------------------
+# graph replays against eager launches: the same kernels with the same
+# arguments, so the results are identical
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_graph_replay_equals_eager(B, prec):
+    w, f = _modes_problem(255, 500, 0.45, 500)
+    outs = []
+    for graph in (0, 1, 1):   # the second graph solve replays the cached graphs
+        with B.Solver(w.N, w.M, w.alpha, precision=prec, graph=graph) as s:
+            F = dev(f)
+            U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+            info = s.solve(F, U, tol=1e-11)
+            if graph:
+                U2 = torch.zeros_like(U)
+                s.solve(F, U2, tol=1e-11)
+                assert torch.equal(U, U2)
+            outs.append((host(U), info["iters"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+# ---------------------------------------------------------------------------
+# autotuner: chooses among correct configurations, so the solve stays exact
+
+@pytest.mark.parametrize("prec,smoother", [("bf16x3", "auto"), ("fp64", "inverse")])
+def test_autotuned_solve_matches_direct_solve(B, prec, smoother):
+    w, f = _modes_problem(255, 1024, 0.6, 600)
+    ref = oracle.direct_solve(1, w.N, w.M, w.alpha, f)
+    with B.Solver(w.N, w.M, w.alpha, precision=prec, smoother=smoother) as s:
+        t = s.autotune()
+        assert t["tuned"] and t["ms_tuned"] > 0 and t["ms_tuned"] <= t["ms_default"] * 1.05, t
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(dev(f), U, tol=1e-12)
+        U = host(U)
+    assert relmax(U, ref) <= (1e-8 if prec == "bf16x3" else 1e-10), (t, info)
+
+
+# ---------------------------------------------------------------------------
+# the 256-problem batch at full size (N in {127..2047}, M in {256..8192},
+# alpha in (0.1, 0.9)), in the launch configuration the benchmark times:
+# every problem must reach the tolerance; sampled problems are compared with
+# the exact discrete solution from the oracle's modal solve
+
+def _sampled_error(w, U, npts=1500, seed=3):
+    rng = np.random.default_rng(seed)
+    v = oracle.modal_solve(1, w.N, w.M, w.alpha, w.kx, w.s, ky=w.ky)
+    m = rng.integers(1, w.M + 1, size=npts)
+    m[:20] = w.M
+    n = rng.integers(1, w.N + 1, size=npts)
+    ref = oracle.modal_eval(1, w.N, w.M, w.kx, v, np.stack([m, n, np.ones_like(n)], 1), ky=w.ky)
+    got = U.reshape(-1)[torch.from_numpy((m - 1) * w.N + (n - 1)).cuda()].cpu().numpy()
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+def test_config4_batch_full_size(B):
+    ws = W.batch_1d()
+    print(f"config4: {len(ws)} problems, {sum(w.unknowns for w in ws)} unknowns", flush=True)
+    b = B.Batch([w.N for w in ws], [w.M for w in ws], [w.alpha for w in ws], precision="bf16x3")
+    fs = [w.forcing_torch("cuda").contiguous() for w in ws]
+    us = [torch.zeros((w.M, w.N), dtype=torch.float64, device="cuda") for w in ws]
+    rc, infos = b.solve(fs, us, tol=1e-10)
+    torch.cuda.synchronize()
+    bad = [(i, inf["status"], inf["relres"]) for i, inf in enumerate(infos)
+           if inf["status"] != "ok" or inf["relres"] > 1e-10]
+    assert not bad, bad[:5]
+    order = sorted(range(len(ws)), key=lambda i: -ws[i].N * ws[i].M)
+    check = order[:3] + order[-3:] + list(range(0, len(ws), 37))
+    for i in check:
+        err = _sampled_error(ws[i], us[i])
+        assert err <= 1e-8, (i, ws[i].N, ws[i].M, ws[i].alpha, err)
+    b.close()
