@@ -202,6 +202,22 @@ def summ(v):
     return {"min": min(v), "max": max(v), "mean": sum(v) / len(v)}
 
 
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of a kernel from the committed counter runs
+    (profiles/traffic.json), or None when the kernel source has changed since
+    the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        rec = json.load(open(os.path.join(here, "profiles", "traffic.json"))).get(kernel_name)
+        src = open(os.path.join(here, "paper_1608_05400_amd", "csrc", "mgwr_kernels.hip"), "rb").read()
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernels_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec
+
+
 def roofline_of(records, steps):
     """Dominant Toeplitz-product kernel (largest total time) and its achieved
     algorithmic FLOP rate from the per-launch HIP events."""
@@ -235,6 +251,14 @@ def roofline_of(records, steps):
     }
     if mode == 2:
         out["issued_frac"] = round(3 * achieved / peak, 4)   # three BF16 passes per product
+    tr = measured_traffic(out["kernel"])
+    if tr:
+        out["traffic"] = tr["bytes_per_launch"]
+        out["traffic_unit"] = "bytes/launch (FETCH_SIZE x %g + WRITE_SIZE x %g)" % (tr["fetch_factor"],
+                                                                                   tr["write_factor"])
+        # operand read once and product written once, FP64 (8 bytes each)
+        rs = [r for r in records if r["kernel"] == kid]
+        out["algorithmic_bytes"] = sum(16.0 * r["M"] * r["P"] for r in rs) / len(rs)
     return out
 
 
@@ -276,6 +300,19 @@ def cpu_baseline(w, seconds):
                        f"took {ts:.2f} s; full-solve time scaled by (M/Ms)^2 = {t_full:.1f} s")}
 
 
+def calibrate_copy(mib=512, reps=3):
+    """A plain device-to-device copy of known size (for scaling the HBM
+    byte counters of a profiler run: each copy reads and writes mib MiB)."""
+    import torch
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +322,8 @@ def main():
     ap.add_argument("--smoother", default="inverse", choices=["inverse", "dc", "auto"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 512 MiB device copy three times (profiler counter calibration)")
     ap.add_argument("--modes", default="bf16x3,fp64,fp32,fp64r")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -299,6 +338,9 @@ def main():
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     from paper_1608_05400_amd import binding as B
     B.load()
     wls, wname = make_workloads(args.workload)

@@ -1181,7 +1181,8 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
     const int tprec = (prec == MGWR_FP64) ? MGWR_FP64_REFINED : prec;
     for (mgwr_ctx *h : hs) {
         CHK(alloc_inner(h, tprec, uses_dc(h)));
-        for (auto &L : h->lv) L.dc_tuned = 0;
+        // start from the choice an untuned handle makes
+        for (auto &L : h->lv) L.dc_tuned = (h->opt.smoother == MGWR_SMOOTH_DC) ? kDcDefault : 0;
         for (int m = 0; m < 3; ++m) h->tune.kn[m] = TileKnobs{};
         // the finest right-hand side of the error equation: zeros
         std::vector<FillArgs> z{FillArgs{h->M, h->lv.back().P, nullptr, nullptr, h->res64, 0}};

@@ -193,6 +193,24 @@ __device__ inline void k_range(const KP &kp, int i0, int s, int &kbase, int &ks0
     ks1 = (int)((long)nk * (s + 1) / kp.nsplit);
 }
 
+// Pieces of the epilogues for the product kernels: the output column of
+// product column p, whether the epilogue reads the old value, and the new value.
+template <int EPI> __device__ constexpr bool epi_reads()
+{
+    return EPI == EPI_SCATTER_ADD || EPI == EPI_SUB || EPI == EPI_ADD;
+}
+template <int EPI> __device__ inline long epi_col(const EpiArgs &e, int p)
+{
+    if constexpr (EPI == EPI_SCATTER || EPI == EPI_SCATTER_ADD) return colour_point(e.dims, e.n, e.colour, p);
+    else return p;
+}
+template <int EPI> __device__ inline double epi_combine(double prev, double acc)
+{
+    if constexpr (EPI == EPI_SUB) return prev - acc;
+    else if constexpr (EPI == EPI_SCATTER_ADD || EPI == EPI_ADD) return prev + acc;
+    else return acc;
+}
+
 // Result of element (i, p): the epilogue, or a partial sum when K is split.
 template <int EPI, typename PT>
 __device__ inline void emit(const KP &kp, int s, int i, int p, double acc)
@@ -323,19 +341,52 @@ __global__ __launch_bounds__(256) void k_toep_wide(KGrp grp)
         if (kt + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
     }
+    const int pl = p0 + wn * 16 * C::FN + (lane & 15);
+    if (kp.nsplit > 1) {
 #pragma unroll
-    for (int x = 0; x < C::FM; ++x)
+        for (int x = 0; x < C::FM; ++x)
 #pragma unroll
-        for (int y = 0; y < C::FN; ++y) {
+            for (int y = 0; y < C::FN; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int i = i0 + wm * 16 * C::FM + 16 * x + T::crow(lane, v);
+                    int p = pl + 16 * y;
+                    if (i < kp.M && p < kp.P) emit<EPI, S>(kp, it.s, i, p, (double)acc[x][y][v]);
+                }
+        return;
+    }
+    // one row block at a time: all old values of the block are loaded before
+    // any store (a load cannot move above a store to the same array, so an
+    // interleaved read-modify-write would wait for every load in turn)
+    GLOBAL double *out = gview_rw<double>(kp.ea.out);
+    long col[C::FN];
+    bool cok[C::FN];
+#pragma unroll
+    for (int y = 0; y < C::FN; ++y) {
+        cok[y] = pl + 16 * y < kp.P;
+        col[y] = cok[y] ? epi_col<EPI>(kp.ea, pl + 16 * y) : 0;
+    }
+#pragma unroll
+    for (int x = 0; x < C::FM; ++x) {
+        double prev[C::FN][4];
+#pragma unroll
+        for (int y = 0; y < C::FN; ++y)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int i = i0 + wm * 16 * C::FM + 16 * x + T::crow(lane, v);
-                int p = p0 + wn * 16 * C::FN + 16 * y + (lane & 15);
-                if (i < kp.M && p < kp.P) emit<EPI, S>(kp, it.s, i, p, (double)acc[x][y][v]);
+                const int i = i0 + wm * 16 * C::FM + 16 * x + T::crow(lane, v);
+                prev[y][v] = 0.0;
+                if constexpr (epi_reads<EPI>())
+                    if (cok[y] && i < kp.M) prev[y][v] = out[(long)i * kp.ea.ldo + col[y]];
             }
-            // keep the read-modify-write epilogues from holding every load at once
-            __builtin_amdgcn_sched_barrier(0);
-        }
+#pragma unroll
+        for (int y = 0; y < C::FN; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + wm * 16 * C::FM + 16 * x + T::crow(lane, v);
+                if (cok[y] && i < kp.M)
+                    out[(long)i * kp.ea.ldo + col[y]] = epi_combine<EPI>(prev[y][v], (double)acc[x][y][v]);
+            }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -546,16 +597,50 @@ __global__ __launch_bounds__(256) void k_toep_bf16x3(KGrp grp)
 #undef BF_FREAD
 #undef BF_LSTORE
 #undef BF_GLOAD
+    const int pl = p0 + wn * 64 + (lane & 15);
+    if (kp.nsplit > 1) {
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int i = iw + 16 * a + 4 * (lane >> 4) + v;
+                    int p = pl + 16 * b;
+                    if (i < kp.M && p < kp.P) emit<EPI, float>(kp, it.s, i, p, (double)acc[a][b][v]);
+                }
+        return;
+    }
+    // one row block at a time, loads before stores (see k_toep_wide)
+    GLOBAL double *out = gview_rw<double>(kp.ea.out);
+    long col[4];
+    bool cok[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        cok[b] = pl + 16 * b < kp.P;
+        col[b] = cok[b] ? epi_col<EPI>(kp.ea, pl + 16 * b) : 0;
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        double prev[4][4];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int i = iw + 16 * a + 4 * (lane >> 4) + v;
-                int p = p0 + wn * 64 + 16 * b + (lane & 15);
-                if (i < kp.M && p < kp.P) emit<EPI, float>(kp, it.s, i, p, (double)acc[a][b][v]);
+                const int i = iw + 16 * a + 4 * (lane >> 4) + v;
+                prev[b][v] = 0.0;
+                if constexpr (epi_reads<EPI>())
+                    if (cok[b] && i < kp.M) prev[b][v] = out[(long)i * kp.ea.ldo + col[b]];
             }
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = iw + 16 * a + 4 * (lane >> 4) + v;
+                if (cok[b] && i < kp.M)
+                    out[(long)i * kp.ea.ldo + col[b]] = epi_combine<EPI>(prev[b][v], (double)acc[a][b][v]);
+            }
+    }
 }
 
 // ---------------------------------------------------------------------------
