@@ -218,9 +218,32 @@ def measured_traffic(kernel_name):
     return rec
 
 
+HBM_PEAK_GBS = 8000.0
+
+
+def fft_pass_bytes(r):
+    """Bytes the FFT route of one product must move: its first forward pass
+    reads the K x P input once and writes the L x ceil(P/2) complex work
+    array; each other pass reads and writes that array; the last inverse pass
+    reads it and writes the M x P FP64 product (and reads it first when the
+    epilogue accumulates).  n = ceil(log2(L) / 5) passes per direction."""
+    M, P, K, kid = r["M"], r["P"], r["K"], r["kernel"]
+    mode, epi = (kid >> 4) & 15, kid & 15
+    L = 64
+    while L < 2 * M:
+        L *= 2
+    n = (L.bit_length() - 1 + 4) // 5
+    c = 16 if mode == 0 else 8                        # complex FP64 / FP32
+    insz = 8 if (mode == 0 or epi == 0) else 4        # FP32 smoother reads an FP32 panel
+    Q = (P + 1) // 2
+    epi_bytes = 8.0 * M * P * (2 if epi in (2, 3, 4) else 1)
+    return K * P * insz + (4 * n - 2) * L * Q * c + epi_bytes
+
+
 def roofline_of(records, steps):
     """Dominant Toeplitz-product kernel (largest total time) and its achieved
-    algorithmic FLOP rate from the per-launch HIP events."""
+    rate from the per-launch HIP events: algorithmic FLOP/s against the matrix
+    cores for the dense kernels, bytes/s against HBM for the FFT route."""
     if not records:
         return None
     from paper_1608_05400_amd import binding as B
@@ -233,6 +256,31 @@ def roofline_of(records, steps):
     kid = max(by, key=lambda k: by[k]["ms"])
     d = by[kid]
     mode = (kid >> 4) & 15
+    if (kid >> 8) == 4:
+        rs = [r for r in records if r["kernel"] == kid]
+        nbytes = sum(fft_pass_bytes(r) for r in rs)
+        achieved = nbytes / (d["ms"] * 1e-3) / 1e9
+        out = {
+            "bound": "hbm",
+            "kernel": B.kernel_name(kid),
+            "dtype": "f64" if mode == 0 else "f32",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "algorithmic_bytes": nbytes / len(rs),
+            "launches_per_step": d["n"] // max(1, steps),
+            "avg_launch_ms": round(d["ms"] / d["n"], 4),
+            "dense_equivalent_tflops": round(d["flops"] / (d["ms"] * 1e-3) / 1e12, 1),
+            "share_of_product_time": round(d["ms"] / sum(v["ms"] for v in by.values()), 3),
+        }
+        tr = measured_traffic(out["kernel"])
+        if tr:
+            out["traffic"] = tr["bytes_per_launch"]
+            out["traffic_unit"] = "bytes/launch (FETCH_SIZE x %g + WRITE_SIZE x %g)" % (tr["fetch_factor"],
+                                                                                       tr["write_factor"])
+        return out
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[mode]
     out = {

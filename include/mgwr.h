@@ -97,6 +97,11 @@ typedef struct {
     int graph;          /* 1 = record each outer iteration of mgwr_solve /
                            mgwr_batch_solve once per set of arguments and replay it as a
                            HIP graph; 0 = issue every launch each time (default 1)          */
+    int fft;            /* FP64 Toeplitz products (the FP64 residual, FP64 smoother and
+                           FP64 cycles) as circulant products by FFT (Section 5.1) instead of
+                           dense matrix-core products: 0 = never, 1 = per level as the
+                           autotuner chose (before tuning: when M >= 1024), 2 = always
+                           (M >= 32).  The two routes agree to rounding (default 1)       */
 } mgwr_options;
 
 typedef struct {
@@ -176,7 +181,8 @@ int mgwr_levels(mgwr_t h);
 /* ---- autotuner ----
  * Times one cycle of the error equation of the handle (its own buffers only:
  * no caller array is read or written) under candidate tile shapes of the
- * Toeplitz-product kernels and, when options.smoother is MGWR_SMOOTH_DC with
+ * Toeplitz-product kernels, the FFT or dense route of the FP64 products per
+ * level (options.fft = 1), and, when options.smoother is MGWR_SMOOTH_DC with
  * dc_block = 0 or MGWR_SMOOTH_AUTO, candidate D&C base blocks per level, and
  * keeps the fastest.  Handles of the same shape and options created later in
  * the process reuse the result.  Synchronous; the choice is reported by
@@ -189,6 +195,7 @@ typedef struct {
     int levels;
     int dc_block[32];     /* per level (0 = coarsest): 0 = inverse-column solve, else the
                              D&C base block in rows                                       */
+    int fft[32];          /* per level: 1 = FP64 products by FFT, 0 = dense               */
     double ms_default;    /* cycle time with the default choices (ms)                    */
     double ms_tuned;      /* cycle time with the chosen ones (ms)                        */
 } mgwr_tuning;
@@ -222,7 +229,7 @@ int mgwr_batch_destroy(mgwr_batch_t b);
  * its launches one by one instead of replaying graphs.  kernel identifies
  * the kernel instantiation: (kind << 8) | (mode << 4) | epilogue, with kind
  * 0 = narrow (64x16 tiles), 1 = wide 128x64, 2 = wide 256x64, 3 = split-BF16
- * 256x128; mode 0 = FP64, 1 = FP32, 2 = split-BF16; epilogue 0 = store
+ * 256x128, 4 = FFT route (all passes of one product); mode 0 = FP64, 1 = FP32, 2 = split-BF16; epilogue 0 = store
  * (residual product, D&C base block in FP64), 1 = colour scatter (smoother,
  * whole line solve), 2 = colour scatter-add (smoother, history part),
  * 3 = subtract (D&C history update), 4 = add (D&C base block, history part).

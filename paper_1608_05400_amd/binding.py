@@ -47,19 +47,21 @@ class Options(ctypes.Structure):
                 ("maxit", ctypes.c_int), ("norm", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("precision", ctypes.c_int), ("first_colour", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("dc_block", ctypes.c_int),
-                ("L", ctypes.c_double), ("stall", ctypes.c_double), ("graph", ctypes.c_int)]
+                ("L", ctypes.c_double), ("stall", ctypes.c_double), ("graph", ctypes.c_int),
+                ("fft", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tuned", ctypes.c_int), ("variant", ctypes.c_int * 2),
                 ("split_target", ctypes.c_int * 3), ("levels", ctypes.c_int),
-                ("dc_block", ctypes.c_int * 32), ("ms_default", ctypes.c_double),
-                ("ms_tuned", ctypes.c_double)]
+                ("dc_block", ctypes.c_int * 32), ("fft", ctypes.c_int * 32),
+                ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double)]
 
     def as_dict(self):
         return {"tuned": bool(self.tuned), "variant": list(self.variant),
                 "split_target": list(self.split_target),
                 "dc_block": list(self.dc_block[:self.levels]),
+                "fft": list(self.fft[:self.levels]),
                 "ms_default": self.ms_default, "ms_tuned": self.ms_tuned}
 
 

@@ -31,6 +31,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -85,6 +86,18 @@ int fail(int code, const char *fmt, ...)
 constexpr int kBf16MinCols = 128;
 // Base block of MGWR_SMOOTH_DC when neither the options nor the tuner set one.
 constexpr int kDcDefault = 1024;
+// FP64 products take the FFT route from this many time levels on unless the
+// autotuner has chosen per level (dense: 2M flops per element on the matrix
+// cores; FFT: about 32 bytes per element per pass, 4 passes up to M = 512,
+// 6 from M = 1024).
+constexpr int kFftMinM = 1024;
+// The same for the FP32 history products of the mixed cycles, against the
+// split-BF16 matrix-core products (about 5x faster per flop than FP64).
+constexpr int kFftMinMLow = 4096;
+constexpr int kFftMinCols = 64;
+// Bytes of each of the two work arrays of the FFT route (columns beyond what
+// fits are transformed in chunks).
+constexpr size_t kFftBufCap = (size_t)1 << 30;
 
 // ---------------------------------------------------------------------------
 // L1 weights (Section 2, L1 scheme; Section 5, r_i).  d_k for k >= 2 as
@@ -156,6 +169,32 @@ void inverse_column(const std::vector<double> &r, double sigma, std::vector<doub
     }
 }
 
+// DFT of a zero-padded real vector, X[k] = sum_t v[t] exp(-2 pi i t k / L),
+// by an iterative radix-2 FFT in long double (L a power of two); the
+// coefficient spectra of the FFT route.
+std::vector<std::complex<long double>> host_dft(const std::vector<double> &v, int L)
+{
+    using C = std::complex<long double>;
+    std::vector<C> a(L, C(0, 0)), w(L / 2);
+    for (size_t t = 0; t < v.size() && (int)t < L; ++t) a[t] = C(v[t], 0);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < L / 2; ++k) w[k] = C(cosl(2 * pi * k / L), -sinl(2 * pi * k / L));
+    for (int i = 1, j = 0; i < L; ++i) {
+        int bit = L >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (int len = 2; len <= L; len <<= 1)
+        for (int i = 0; i < L; i += len)
+            for (int k = 0; k < len / 2; ++k) {
+                const C x = a[i + k], y = a[i + k + len / 2] * w[k * (L / len)];
+                a[i + k] = x + y;
+                a[i + k + len / 2] = x - y;
+            }
+    return a;
+}
+
 // ---------------------------------------------------------------------------
 struct Level {
     int n = 0;
@@ -168,6 +207,9 @@ struct Level {
     double *u64 = nullptr, *f64 = nullptr;  // FP64 hierarchy (levels below the finest)
     double *e = nullptr, *fe = nullptr;     // inner hierarchy of the refinement (all levels)
     int dc_tuned = 0;                       // base block chosen by the tuner (0: inverse column)
+    int fft_tuned = -1;                     // products by FFT (1) or dense (0); -1: size rule
+    void *spec_inv = nullptr;               // DFT of the zero-padded inverse column (FFT route)
+    void *spec32_inv_h = nullptr;           // FP32 DFT of its history part (mixed cycles)
 };
 
 // Tile knobs per product arithmetic (FP64, FP32, split-BF16).
@@ -213,8 +255,8 @@ struct Profiler {
     }
     void release()
     {
-        for (auto &p : pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
-        for (auto e : pool) hipEventDestroy(e);
+        for (auto &p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+        for (auto e : pool) (void)hipEventDestroy(e);
         pending.clear();
         pool.clear();
     }
@@ -243,9 +285,9 @@ struct Runner {
 
 void drop_program(Program &p)
 {
-    if (p.exec) hipGraphExecDestroy(p.exec);
-    if (p.graph) hipGraphDestroy(p.graph);
-    if (p.arena) hipFree(p.arena);
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    if (p.arena) (void)hipFree(p.arena);
     p = Program{};
 }
 
@@ -312,6 +354,12 @@ struct mgwr_ctx {
     double *partials = nullptr;
     void *part = nullptr;            // split-K partials of the Toeplitz products
     size_t part_cap = 0;
+    // FFT route of the FP64 products: transform length, twiddles, spectra, work arrays
+    int fft_L = 0;
+    void *fft_tw = nullptr, *spec_tm = nullptr;
+    void *fft_tw32 = nullptr, *spec32_tm_h = nullptr;
+    void *fft_buf0 = nullptr, *fft_buf1 = nullptr;
+    size_t fft_buf_cap = 0;
     Tuning tune;
     Runner run;
     int inner_prec = -1;             // precision the inner buffers exist for
@@ -372,7 +420,8 @@ double product_flops(const GemmArgs &a)
 // narrow, 1 = wide 128 x 64, 2 = wide 256 x 64, 3 = split-BF16.
 int kernel_id(const GemmArgs &a)
 {
-    return (product_kernel_kind(a.mode, a.M, a.P, a.knobs) << 8) | (a.mode << 4) | a.epi;
+    const int kind = a.fft_spec ? 4 : product_kernel_kind(a.mode, a.M, a.P, a.knobs);
+    return (kind << 8) | (a.mode << 4) | a.epi;
 }
 
 GemmArgs gemm_base(mgwr_ctx *h, int mode)
@@ -437,7 +486,104 @@ int check_opts(const mgwr_options *o)
     if (!(o->L > 0) || !std::isfinite(o->L)) return fail(MGWR_EINVAL, "L must be positive");
     if (!(o->stall >= 0) || o->stall >= 1.0) return fail(MGWR_EINVAL, "stall must be in [0, 1)");
     if (o->graph != 0 && o->graph != 1) return fail(MGWR_EINVAL, "graph must be 0 or 1");
+    if (o->fft < 0 || o->fft > 2) return fail(MGWR_EINVAL, "fft must be 0, 1 or 2");
     return MGWR_OK;
+}
+
+// FFT route of the FP64 products: twiddles, the spectra of T_M's column and
+// of every level's inverse column, and two work arrays.
+int alloc_fft(mgwr_t h)
+{
+    if (h->fft_tw || h->opt.fft == 0 || h->M < 32) return MGWR_OK;
+    int L = 64;
+    while (L < 2 * h->M) L <<= 1;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double> tw(2 * (size_t)L);
+    for (int k = 0; k < L; ++k) {
+        tw[2 * k] = (double)cosl(2 * pi * k / L);
+        tw[2 * k + 1] = (double)-sinl(2 * pi * k / L);
+    }
+    CHK(dmalloc(h->alloc, &h->fft_tw, sizeof(double) * tw.size()));
+    HIPCHK(hipMemcpy(h->fft_tw, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice));
+    std::vector<float> tw32(tw.begin(), tw.end());
+    CHK(dmalloc(h->alloc, &h->fft_tw32, sizeof(float) * tw32.size()));
+    HIPCHK(hipMemcpy(h->fft_tw32, tw32.data(), sizeof(float) * tw32.size(), hipMemcpyHostToDevice));
+    // columns: T_M's, then every level's inverse; the FP32 spectra are of
+    // the history parts (first entry zero)
+    const int nl = (int)h->lv.size();
+    std::vector<std::vector<double>> cols(nl + 1), specs(nl + 1), specs_h(nl + 1);
+    cols[nl] = h->r_host;
+    for (int l = 0; l < nl; ++l) {
+        cols[l].resize(h->M);
+        HIPCHK(hipMemcpy(cols[l].data(), h->lv[l].inv.d64, sizeof(double) * h->M, hipMemcpyDeviceToHost));
+    }
+    std::vector<std::thread> th;
+    for (int l = 0; l <= nl; ++l)
+        th.emplace_back([&, l]() {
+            auto X = host_dft(cols[l], L);
+            std::vector<double> hist = cols[l];
+            hist[0] = 0.0;
+            auto Xh = host_dft(hist, L);
+            specs[l].resize(2 * (size_t)L);
+            specs_h[l].resize(2 * (size_t)L);
+            for (int k = 0; k < L; ++k) {
+                specs[l][2 * k] = (double)X[k].real();
+                specs[l][2 * k + 1] = (double)X[k].imag();
+                specs_h[l][2 * k] = (double)Xh[k].real();
+                specs_h[l][2 * k + 1] = (double)Xh[k].imag();
+            }
+        });
+    for (auto &t : th) t.join();
+    for (int l = 0; l <= nl; ++l) {
+        void **dst = (l == nl) ? &h->spec_tm : &h->lv[l].spec_inv;
+        CHK(dmalloc(h->alloc, dst, sizeof(double) * specs[l].size()));
+        HIPCHK(hipMemcpy(*dst, specs[l].data(), sizeof(double) * specs[l].size(), hipMemcpyHostToDevice));
+        std::vector<float> f32(specs_h[l].begin(), specs_h[l].end());
+        void **dst32 = (l == nl) ? &h->spec32_tm_h : &h->lv[l].spec32_inv_h;
+        CHK(dmalloc(h->alloc, dst32, sizeof(float) * f32.size()));
+        HIPCHK(hipMemcpy(*dst32, f32.data(), sizeof(float) * f32.size(), hipMemcpyHostToDevice));
+    }
+    const size_t need = (size_t)16 * L * ((h->lv.back().P + 1) / 2);
+    h->fft_buf_cap = std::min(need, kFftBufCap);
+    CHK(dmalloc(h->alloc, &h->fft_buf0, h->fft_buf_cap));
+    CHK(dmalloc(h->alloc, &h->fft_buf1, h->fft_buf_cap));
+    h->fft_L = L;
+    return MGWR_OK;
+}
+
+// Whether the products of level lev in arithmetic `mode` take the FFT route.
+bool fft_for(const mgwr_ctx *h, int lev, int mode = GM_F64)
+{
+    if (!h->fft_tw || h->opt.fft == 0) return false;
+    if (h->opt.fft == 2) return true;
+    // the tuner times the cycle's own products: in the mixed modes those are
+    // the FP32 / split-BF16 ones, so the FP64 residual keeps the size rule
+    const bool cycle_f64 = h->opt.precision == MGWR_FP64 || h->opt.precision == MGWR_FP64_REFINED;
+    if (h->lv[lev].fft_tuned >= 0 && (mode != GM_F64 || cycle_f64)) return h->lv[lev].fft_tuned == 1;
+    // a transform is several launches over the whole length: not for the
+    // few-column products of the coarse levels
+    return h->M >= (mode == GM_F64 ? kFftMinM : kFftMinMLow) && h->lv[lev].P >= kFftMinCols;
+}
+
+// FFT route of an FP64 product (spec: FP64 spectrum of the full column).
+void set_fft(const mgwr_ctx *h, GemmArgs &a, const void *spec)
+{
+    a.fft_spec = spec;
+    a.fft_tw = h->fft_tw;
+    a.fft_L = a.fft_Ltw = h->fft_L;
+    a.fft_buf0 = h->fft_buf0;
+    a.fft_buf1 = h->fft_buf1;
+    a.fft_buf_cap = h->fft_buf_cap;
+}
+
+// FFT route in FP32 of a history product of the mixed cycles (spec32: FP32
+// spectrum of the history column; b64: B is FP64, else FP32).
+void set_fft32(const mgwr_ctx *h, GemmArgs &a, const void *spec32, bool b64)
+{
+    set_fft(h, a, spec32);
+    a.mode = GM_F32;
+    a.fft_tw = h->fft_tw32;
+    a.fft_b64 = b64;
 }
 
 // Base block of the line solve on level lev (0: one product with the inverse
@@ -654,10 +800,12 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
             rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
                                   L.ih2, 0.0, h->panel64, nullptr, Pc});
             a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
-        } else if (mode == GM_F32) {
+            if (fft_for(h, t.lev)) set_fft(h, a, L.spec_inv);
+        } else if (mode == GM_F32 || fft_for(h, t.lev, mode)) {
             rhs.push_back(RhsArgs{1, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
                                   L.ih2, L.lam0, h->panel32, nullptr, Pc});
             a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.B = h->panel32; a.ldb = Pc;
+            if (fft_for(h, t.lev, mode)) set_fft32(h, a, L.spec32_inv_h, false);
         } else {
             const long ldp = packed_ld(Pc);
             rhs.push_back(RhsArgs{2, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
@@ -701,6 +849,11 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
         a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
         if (mode == GM_F64) {
             a.coef = &h->tm; a.B = t.H->u[t.lev]; a.ldb = L.P;
+            if (fft_for(h, t.lev)) set_fft(h, a, h->spec_tm);
+        } else if (fft_for(h, t.lev, mode)) {
+            // the FFT's first pass reads the FP64 iterate itself
+            a.coef = &h->tm_h; a.B = t.H->u[t.lev]; a.ldb = L.P;
+            set_fft32(h, a, h->spec32_tm_h, true);
         } else if (mode == GM_F32) {
             ops.push_back(OperandArgs{1, h->M, h->M, (int)L.P, t.H->u[t.lev], L.P, h->op32, nullptr, L.P, nullptr, 0.0});
             a.coef = &h->tm_h; a.B = h->op32; a.ldb = L.P;
@@ -822,6 +975,7 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
             a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm; a.epi = EPI_STORE;
             a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
             a.B = r.u; a.ldb = L.P;
+            if (fft_for(h, level)) set_fft(h, a, h->spec_tm);
             prods.push_back(a);
         }
         posts.push_back(PostArgs{h->dims, L.n, h->M, r.f, r.u, r.lo, h->cd, r.g, L.ih2, 0.0, out});
@@ -1108,7 +1262,7 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
 // the same shape and options (process-wide cache).
 struct TuneResult {
     TileKnobs kn[3];
-    std::vector<int> dc;   // per level
+    std::vector<int> dc, fft;   // per level
     double ms_default, ms_tuned;
 };
 std::mutex g_tune_mu;
@@ -1117,8 +1271,8 @@ std::map<std::string, TuneResult> g_tune_cache;
 std::string tune_key(const mgwr_ctx *h)
 {
     char buf[256];
-    snprintf(buf, sizeof buf, "d%d N%d M%d p%d s%d b%d", h->dims, h->N, h->M, h->opt.precision, h->opt.smoother,
-             h->opt.dc_block);
+    snprintf(buf, sizeof buf, "d%d N%d M%d p%d s%d b%d f%d", h->dims, h->N, h->M, h->opt.precision,
+             h->opt.smoother, h->opt.dc_block, h->opt.fft);
     return buf;
 }
 
@@ -1169,7 +1323,10 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end() && hs.size() == 1) {
             for (int m = 0; m < 3; ++m) h0->tune.kn[m] = it->second.kn[m];
-            for (size_t l = 0; l < h0->lv.size(); ++l) h0->lv[l].dc_tuned = it->second.dc[l];
+            for (size_t l = 0; l < h0->lv.size(); ++l) {
+                h0->lv[l].dc_tuned = it->second.dc[l];
+                h0->lv[l].fft_tuned = it->second.fft[l];
+            }
             h0->tune.ms_default = it->second.ms_default;
             h0->tune.ms_tuned = it->second.ms_tuned;
             h0->tune.tuned = true;
@@ -1182,7 +1339,10 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
     for (mgwr_ctx *h : hs) {
         CHK(alloc_inner(h, tprec, uses_dc(h)));
         // start from the choice an untuned handle makes
-        for (auto &L : h->lv) L.dc_tuned = (h->opt.smoother == MGWR_SMOOTH_DC) ? kDcDefault : 0;
+        for (auto &L : h->lv) {
+            L.dc_tuned = (h->opt.smoother == MGWR_SMOOTH_DC) ? kDcDefault : 0;
+            L.fft_tuned = -1;
+        }
         for (int m = 0; m < 3; ++m) h->tune.kn[m] = TileKnobs{};
         // the finest right-hand side of the error equation: zeros
         std::vector<FillArgs> z{FillArgs{h->M, h->lv.back().P, nullptr, nullptr, h->res64, 0}};
@@ -1223,11 +1383,37 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
         }
         set_kn(mode, k);
     }
+    int depth = 0;
+    for (mgwr_ctx *h : hs) depth = std::max(depth, (int)h->lv.size());
+    // FFT or dense route of the products, level by level from the finest
+    if (h0->opt.fft == 1 && h0->fft_tw) {
+        for (int d = 0; d < depth; ++d) {
+            auto set_fft_choice = [&](int c) {
+                for (mgwr_ctx *h : hs) {
+                    int l = (int)h->lv.size() - 1 - d;
+                    if (l >= 0) h->lv[l].fft_tuned = c;
+                }
+            };
+            // the default of the deepest-reaching problem decides where to start
+            mgwr_ctx *hp = h0;
+            for (mgwr_ctx *h : hs)
+                if (h->lv.size() > hp->lv.size()) hp = h;
+            const int l0 = (int)hp->lv.size() - 1 - d;
+            Hier probe = inner_hier(hp, tprec);
+            set_fft_choice(-1);
+            const int def = fft_for(hp, l0, level_mode(probe, hp->lv[l0].P)) ? 1 : 0;
+            set_fft_choice(def);
+            CHK(time_cycle(R, hs, tprec, 2, best));
+            set_fft_choice(1 - def);
+            double t;
+            CHK(time_cycle(R, hs, tprec, 2, t));
+            if (t < best * 0.995) best = t;
+            else set_fft_choice(def);
+        }
+    }
     // D&C base blocks, level by level from the finest (the same choice for
     // every problem at the same depth)
     if (h0->opt.smoother != MGWR_SMOOTH_INVERSE && h0->opt.dc_block == 0) {
-        int depth = 0;
-        for (mgwr_ctx *h : hs) depth = std::max(depth, (int)h->lv.size());
         std::vector<int> cands;
         if (h0->opt.smoother == MGWR_SMOOTH_AUTO) cands.push_back(0);
         for (int b : {4096, 2048, 1024, 512, 256}) cands.push_back(b);
@@ -1261,7 +1447,10 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
     if (hs.size() == 1) {
         TuneResult tr;
         for (int m = 0; m < 3; ++m) tr.kn[m] = h0->tune.kn[m];
-        for (auto &L : h0->lv) tr.dc.push_back(L.dc_tuned);
+        for (auto &L : h0->lv) {
+            tr.dc.push_back(L.dc_tuned);
+            tr.fft.push_back(L.fft_tuned);
+        }
         tr.ms_default = ms_default;
         tr.ms_tuned = best;
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1278,7 +1467,12 @@ void tuning_out(const mgwr_ctx *h, mgwr_tuning *t)
     t->variant[1] = h->tune.kn[GM_F32].variant;
     for (int m = 0; m < 3; ++m) t->split_target[m] = h->tune.kn[m].split_target;
     t->levels = (int)h->lv.size();
-    for (int l = 0; l < t->levels && l < 32; ++l) t->dc_block[l] = dc_block_of(h, l);
+    Hier probe;
+    probe.prec = h->opt.precision;
+    for (int l = 0; l < t->levels && l < 32; ++l) {
+        t->dc_block[l] = dc_block_of(h, l);
+        t->fft[l] = fft_for(h, l, level_mode(probe, h->lv[l].P)) ? 1 : 0;
+    }
     t->ms_default = h->tune.ms_default;
     t->ms_tuned = h->tune.ms_tuned;
 }
@@ -1297,6 +1491,7 @@ int mgwr_default_options(mgwr_options *o)
     o->nu1 = 1; o->nu2 = 1; o->gamma = 1; o->maxit = 100; o->norm = MGWR_NORM_MAX;
     o->warm_start = 0; o->precision = MGWR_FP64; o->first_colour = 0;
     o->smoother = MGWR_SMOOTH_INVERSE; o->dc_block = 0; o->L = 1.0; o->stall = 0.5; o->graph = 1;
+    o->fft = 1;
     return MGWR_OK;
 }
 
@@ -1423,6 +1618,7 @@ int mgwr_create_ex(int N, int M, double alpha, double T, int dims, const mgwr_op
             h->part_cap = part;
         }
         CHK(init_runner(h->run, 1));
+        CHK(alloc_fft(h));
         CHK(alloc_inner(h, o.precision, uses_dc(h)));
         HIPCHK(hipDeviceSynchronize());
         return MGWR_OK;
@@ -1452,9 +1648,15 @@ int mgwr_set_options(mgwr_t h, const mgwr_options *opts)
         return rc;
     }
     h->run.graphs = opts->graph != 0;
-    if (old.precision != opts->precision || old.smoother != opts->smoother || old.dc_block != opts->dc_block) {
+    rc = alloc_fft(h);
+    if (rc < 0) {
+        h->opt = old;
+        return rc;
+    }
+    if (old.precision != opts->precision || old.smoother != opts->smoother || old.dc_block != opts->dc_block ||
+        old.fft != opts->fft) {
         h->tune = Tuning{};
-        for (auto &L : h->lv) L.dc_tuned = 0;
+        for (auto &L : h->lv) { L.dc_tuned = 0; L.fft_tuned = -1; }
     }
     return MGWR_OK;
 }
@@ -1582,6 +1784,8 @@ int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int
     Exec ex{h->stream, nullptr, &h->run.prof};
     if (mode == GM_F64) {
         a.B = B; a.ldb = ldb;
+        if (fft_for(h, which < 0 ? (int)h->lv.size() - 1 : which))
+            set_fft(h, a, which < 0 ? h->spec_tm : h->lv[which].spec_inv);
         return run_gemms(ex, {a}, which);
     }
     // FP32 / split-BF16 operands are built in temporaries (test path)
@@ -1646,6 +1850,7 @@ const char *mgwr_kernel_name(int kernel)
     case 0: name = "k_toep_narrow<" + m + ", " + e + ">"; break;
     case 1: name = "k_toep_wide<" + m + ", " + e + ", 0>"; break;
     case 2: name = "k_toep_wide<" + m + ", " + e + ", 1>"; break;
+    case 4: name = std::string(mode == 0 ? "k_fft_pass<double> (FFT route, epilogue " : "k_fft_pass<float> (FFT route, epilogue ") + e + ")"; break;
     default: name = "k_toep_bf16x3<" + e + ">"; break;
     }
     return name.c_str();

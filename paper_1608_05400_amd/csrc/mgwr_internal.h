@@ -78,6 +78,17 @@ struct GemmArgs {
     void *part = nullptr;      // scratch for split-K partials
     size_t part_cap = 0;       // its size in bytes (0: never split)
     TileKnobs knobs;
+    // FFT route (off = 0, K <= M): the causal product is the first M outputs
+    // of a circular convolution of length fft_L >= 2M.  When fft_spec is set
+    // the product runs as batched FFTs along time instead of the dense
+    // kernels, in FP64 (mode GM_F64) or FP32 (other modes; spectra and
+    // twiddles then FP32 complex, B FP64 if fft_b64 else FP32).
+    const void *fft_spec = nullptr;  // complex [fft_L]: DFT of the coefficients, zero padded
+    const void *fft_tw = nullptr;    // complex [fft_Ltw]: exp(-2 pi i k / fft_Ltw)
+    int fft_L = 0, fft_Ltw = 0;      // powers of two, 64 <= fft_L <= fft_Ltw
+    bool fft_b64 = true;
+    void *fft_buf0 = nullptr, *fft_buf1 = nullptr;  // work arrays, fft_buf_cap bytes each:
+    size_t fft_buf_cap = 0;          // columns are transformed in chunks of 2 fft_buf_cap / (16 fft_L)
 };
 
 // Flat point index of the j-th point of a colour (0: n even / n + l even).

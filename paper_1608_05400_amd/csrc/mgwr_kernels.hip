@@ -925,6 +925,8 @@ static hipError_t launch_mode(int epi, std::vector<KP> &kps, const std::vector<G
     return hipErrorInvalidValue;
 }
 
+static hipError_t launch_toep_fft(const GemmArgs &a, hipStream_t s);
+
 hipError_t launch_toep_gemm(const std::vector<GemmArgs> &as, Staging *st, hipStream_t s)
 {
     // classes of (mode, epilogue, kernel); one launch each
@@ -933,6 +935,13 @@ hipError_t launch_toep_gemm(const std::vector<GemmArgs> &as, Staging *st, hipStr
     for (size_t i = 0; i < as.size(); ++i) {
         const GemmArgs &a = as[i];
         if (a.M <= 0 || a.P <= 0) continue;
+        if (a.fft_spec) {   // FFT route: launched on its own (arguments by value)
+            if (!(st && st->record)) {
+                hipError_t e = launch_toep_fft(a, s);
+                if (e != hipSuccess) return e;
+            }
+            continue;
+        }
         geo[i] = geometry(a.mode, a.M, a.P, a.K, a.off, a.coef->n, a.part ? a.part_cap : 0, a.knobs);
         cls[(a.mode << 8) | (a.epi << 4) | geo[i].kind].push_back(i);
     }
@@ -992,6 +1001,229 @@ hipError_t launch_toep_gemm(const std::vector<GemmArgs> &as, Staging *st, hipStr
 int product_kernel_kind(int mode, int M, int P, const TileKnobs &kn)
 {
     return tiles(mode, M, P, kn).kind;
+}
+
+// ---------------------------------------------------------------------------
+// FFT route of the causal Toeplitz product (Section 5.1: a Toeplitz product
+// is the leading block of a circulant product of twice the size, applied
+// with FFTs).  Two real columns 2q, 2q+1 of B form one complex sequence of
+// length L >= 2M (zero padded); its DFT times the DFT of the zero-padded
+// coefficients, transformed back, holds the two causal products in its real
+// and imaginary parts (first M entries).  Each transform is a sequence of
+// Stockham autosort passes of radix R along time: a thread does one R-point
+// DFT in registers for one column pair, so the 64 lanes of a wave read and
+// write 64 consecutive column pairs per access.  The product with the
+// coefficient spectrum is fused into the first inverse pass and the product
+// epilogue into the last one.  Arithmetic in FP64 (the FP64 products) or in
+// FP32 (the history products of the mixed-precision cycles); the input may
+// be FP64 or FP32.
+template <typename T> struct Cx;
+template <> struct Cx<double> { typedef double v __attribute__((ext_vector_type(2))); };
+template <> struct Cx<float> { typedef float v __attribute__((ext_vector_type(2))); };
+
+template <typename C> __device__ inline C cmul(C a, C b)
+{
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+struct FftPass {
+    int L, Q, Ns;          // length, column pairs of this chunk, length of the sub-transforms done
+    int M, K, P, c0;       // output rows, input rows, columns, first column of this chunk
+    const void *src;       // complex [L][Q]
+    void *dst;             // complex [L][Q]
+    const void *B;         // real input [K][ldb] (FP64 or FP32)
+    long ldb;
+    const void *spec;      // complex [L]
+    const void *tw;        // complex [Ltw], exp(-2 pi i k / Ltw)
+    int Ltw;
+    double scale;          // 1 / L (last inverse pass)
+    EpiArgs ea;
+};
+enum FftSrc { FS_REAL = 0, FS_CPLX = 1, FS_SPEC = 2 };
+enum FftDst { FD_CPLX = 0, FD_EPI = 1 };
+
+// R-point DFT (R a power of two <= 32) of v in natural order, in registers:
+// bit-reversal permutation (register renaming once unrolled), then radix-2
+// butterflies; SIGN -1 forward, +1 inverse (unnormalised).
+template <typename T, int R, int SIGN>
+__device__ inline void dft_reg(typename Cx<T>::v (&v)[R], const GLOBAL typename Cx<T>::v *tw, int Ltw)
+{
+    using C = typename Cx<T>::v;
+    constexpr int LG = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : (R == 16) ? 4 : 5;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        int j = 0;
+#pragma unroll
+        for (int b = 0; b < LG; ++b) j |= ((i >> b) & 1) << (LG - 1 - b);
+        if (j > i) {
+            C t = v[i];
+            v[i] = v[j];
+            v[j] = t;
+        }
+    }
+#pragma unroll
+    for (int m = 2; m <= R; m <<= 1) {
+#pragma unroll
+        for (int t = 0; t < m / 2; ++t) {
+            C w = tw[(long)t * (Ltw / m)];
+            if (SIGN > 0) w.y = -w.y;
+#pragma unroll
+            for (int k = 0; k < R; k += m) {
+                const C a = v[k + t], b = cmul(v[k + t + m / 2], w);
+                v[k + t] = a + b;
+                v[k + t + m / 2] = a - b;
+            }
+        }
+    }
+}
+
+template <typename T, typename TIN, int R, int SIGN, int SRC, int DST, int EPI>
+__global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
+{
+    using C = typename Cx<T>::v;
+    const long g = (long)blockIdx.x * 256 + threadIdx.x;
+    const int nj = a.L / R;
+    if (g >= (long)a.Q * nj) return;
+    const int q = (int)(g % a.Q), j = (int)(g / a.Q);
+    const GLOBAL C *tw = gview<C>(a.tw);
+    C v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int tau = j + r * nj;
+        if constexpr (SRC == FS_REAL) {
+            T re = 0, im = 0;
+            if (tau < a.K) {
+                const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb + a.c0;
+                if (a.c0 + 2 * q < a.P) re = (T)row[2 * q];
+                if (a.c0 + 2 * q + 1 < a.P) im = (T)row[2 * q + 1];
+            }
+            v[r] = C{re, im};
+        } else {
+            v[r] = gview<C>(a.src)[(long)tau * a.Q + q];
+            if constexpr (SRC == FS_SPEC) v[r] = cmul(v[r], gview<C>(a.spec)[tau]);
+        }
+    }
+    const int jm = j % a.Ns;
+    if (a.Ns > 1) {
+        // exp(SIGN 2 pi i jm r / (Ns R)) = tw[jm r (Ltw / (Ns R))] (conjugated for SIGN > 0)
+        const long step = (long)jm * (a.Ltw / (a.Ns * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            C w = tw[step * r];
+            if (SIGN > 0) w.y = -w.y;
+            v[r] = cmul(v[r], w);
+        }
+    }
+    dft_reg<T, R, SIGN>(v, tw, a.Ltw);
+    const int base = (j / a.Ns) * a.Ns * R + jm;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int tau = base + r * a.Ns;
+        if constexpr (DST == FD_CPLX) {
+            gview_rw<C>(a.dst)[(long)tau * a.Q + q] = v[r];
+        } else {
+            if (tau < a.M) {
+                const int c = a.c0 + 2 * q;
+                if (c < a.P) epi_apply<EPI>(a.ea, tau, c, (double)v[r].x * a.scale);
+                if (c + 1 < a.P) epi_apply<EPI>(a.ea, tau, c + 1, (double)v[r].y * a.scale);
+            }
+        }
+    }
+}
+
+// Radices of the passes for a transform of length L = 2^s (L >= 64): the
+// remainder (2^(s mod 5)) first, then radix 32, so that the last inverse
+// pass (the one with the epilogue) is always radix 32.
+static std::vector<int> fft_plan(int L)
+{
+    int lg = 0;
+    while ((1 << lg) < L) ++lg;
+    std::vector<int> r;
+    if (lg % 5) r.push_back(1 << (lg % 5));
+    for (int i = 0; i < lg / 5; ++i) r.push_back(32);
+    return r;
+}
+
+template <typename T, typename TIN, int SIGN, int SRC, int DST, int EPI>
+static void launch_fft_pass(int R, const FftPass &p, hipStream_t s)
+{
+    const long threads = (long)p.Q * (p.L / R);
+    const dim3 grid((unsigned)((threads + 255) / 256));
+    switch (R) {
+    case 2: hipLaunchKernelGGL((k_fft_pass<T, TIN, 2, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
+    case 4: hipLaunchKernelGGL((k_fft_pass<T, TIN, 4, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
+    case 8: hipLaunchKernelGGL((k_fft_pass<T, TIN, 8, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
+    case 16: hipLaunchKernelGGL((k_fft_pass<T, TIN, 16, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
+    default: hipLaunchKernelGGL((k_fft_pass<T, TIN, 32, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
+    }
+}
+
+template <typename T, int EPI>
+static void launch_fft_last(const FftPass &p, hipStream_t s)
+{
+    const dim3 grid((unsigned)(((long)p.Q * (p.L / 32) + 255) / 256));
+    hipLaunchKernelGGL((k_fft_pass<T, T, 32, 1, FS_CPLX, FD_EPI, EPI>), grid, dim3(256), 0, s, p);
+}
+
+template <typename T, typename TIN>
+static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
+{
+    const std::vector<int> plan = fft_plan(a.fft_L);
+    if (plan.size() < 2) return hipErrorInvalidValue;
+    const long qcap = (long)(a.fft_buf_cap / (2 * sizeof(T) * (size_t)a.fft_L));
+    if (qcap < 1) return hipErrorInvalidValue;
+    for (long c0 = 0; c0 < a.P; c0 += 2 * qcap) {
+        FftPass p{};
+        p.L = a.fft_L;
+        p.Q = (int)std::min(qcap, (long)(a.P - c0 + 1) / 2);
+        p.M = a.M; p.K = a.K; p.P = a.P; p.c0 = (int)c0;
+        p.B = a.B; p.ldb = a.ldb;
+        p.spec = a.fft_spec; p.tw = a.fft_tw; p.Ltw = a.fft_Ltw;
+        p.scale = 1.0 / a.fft_L;
+        p.ea = a.ea;
+        void *bufs[2] = {a.fft_buf0, a.fft_buf1};
+        int cur = 0;   // buffer the next pass writes
+        // forward transform
+        p.Ns = 1;
+        for (size_t i = 0; i < plan.size(); ++i) {
+            p.dst = bufs[cur];
+            if (i == 0) launch_fft_pass<T, TIN, -1, FS_REAL, FD_CPLX, 0>(plan[i], p, s);
+            else launch_fft_pass<T, T, -1, FS_CPLX, FD_CPLX, 0>(plan[i], p, s);
+            p.src = bufs[cur];
+            cur ^= 1;
+            p.Ns *= plan[i];
+        }
+        // times the coefficient spectrum, inverse transform, epilogue
+        p.Ns = 1;
+        for (size_t i = 0; i < plan.size(); ++i) {
+            if (i + 1 < plan.size()) {
+                p.dst = bufs[cur];
+                if (i == 0) launch_fft_pass<T, T, 1, FS_SPEC, FD_CPLX, 0>(plan[i], p, s);
+                else launch_fft_pass<T, T, 1, FS_CPLX, FD_CPLX, 0>(plan[i], p, s);
+                p.src = bufs[cur];
+                cur ^= 1;
+            } else {
+                switch (a.epi) {
+                case EPI_STORE: launch_fft_last<T, EPI_STORE>(p, s); break;
+                case EPI_SCATTER: launch_fft_last<T, EPI_SCATTER>(p, s); break;
+                case EPI_SCATTER_ADD: launch_fft_last<T, EPI_SCATTER_ADD>(p, s); break;
+                default: return hipErrorInvalidValue;
+                }
+            }
+            p.Ns *= plan[i];
+        }
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_toep_fft(const GemmArgs &a, hipStream_t s)
+{
+    if (a.off != 0 || a.K > a.M || a.fft_L < 2 * a.M || a.fft_L < 64 || a.fft_L > a.fft_Ltw)
+        return hipErrorInvalidValue;
+    if (a.mode == GM_F64) return fft_product<double, double>(a, s);
+    // FP32 arithmetic (the history products of the mixed cycles) on FP64 or FP32 input
+    if (a.fft_b64) return fft_product<float, double>(a, s);
+    return fft_product<float, float>(a, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,140 @@
+"""GPU parity of the FFT route of the FP64 Toeplitz products (the causal
+product as the leading block of a circulant product of length L >= 2M,
+Section 5.1), through the C ABI, against the oracle.
+
+Tolerances: an FFT convolution is accurate normwise, to a small multiple of
+eps log2(L) times ||t||_1 max|x| per entry, so the products are compared
+with 1e-12 of the term size sum_k |t_k| |x|; solves use the same bars as the
+dense route (1e-10 FP64, 1e-8 mixed against the exact discrete solution).
+"""
+import numpy as np
+import pytest
+from scipy import linalg
+
+import oracle
+from paper_1608_05400_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_05400_amd import binding
+    binding.load()
+    return binding
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relmax(a, b, scale=None):
+    s = np.abs(b).max() if scale is None else scale
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+def toeplitz_lower(col):
+    return linalg.toeplitz(col, np.zeros_like(col))
+
+
+@pytest.mark.parametrize("M", [32, 33, 100, 1000, 4096])
+@pytest.mark.parametrize("P", [1, 2, 7, 130])
+def test_fft_product_matches_oracle_coefficients(B, M, P):
+    alpha = 0.41
+    rng = np.random.default_rng(M * 7 + P)
+    X = rng.standard_normal((M, P))
+    c, d, r = oracle.l1_coeffs(M, alpha)
+    Tm = toeplitz_lower(r)
+    ref = Tm @ X
+    scale = (np.abs(Tm) @ np.abs(X)).max()
+    with B.Solver(7, M, alpha, fft=2) as s:
+        C = host(s.toeplitz_apply(dev(X), which=-1, precision="fp64"))
+    assert relmax(C, ref, scale) <= 1e-12
+
+
+@pytest.mark.parametrize("M,P", [(64, 31), (600, 200), (2048, 1023)])
+def test_fft_inverse_column_product_is_line_solve(B, M, P):
+    alpha = 0.6
+    rng = np.random.default_rng(P)
+    X = rng.standard_normal((M, P))
+    c, d, r = oracle.l1_coeffs(M, alpha)
+    with B.Solver(63, M, alpha, fft=2) as s:
+        nl = s.levels()
+        for lev in (0, nl // 2, nl - 1):
+            n = 2 ** (lev + 1) - 1
+            sigma = 2.0 * (n + 1) ** 2
+            ref = linalg.solve_triangular(toeplitz_lower(r) + sigma * np.eye(M), X, lower=True)
+            C = host(s.toeplitz_apply(dev(X), which=lev, precision="fp64"))
+            assert relmax(C, ref) <= 1e-12, lev
+
+
+@pytest.mark.parametrize("dims,N,M,alpha", [(1, 127, 200, 0.3), (2, 31, 64, 0.7), (1, 63, 33, 0.5)])
+def test_fft_residual_and_sweep_match_oracle(B, dims, N, M, alpha):
+    rng = np.random.default_rng(5)
+    shape = (M, N) if dims == 1 else (M, N, N)
+    f, u, g = rng.standard_normal(shape), rng.standard_normal(shape), rng.standard_normal(shape[1:])
+    ref_r = oracle.residual(dims, N, M, alpha, f, u, g=g)
+    ref_s = oracle.half_sweep(dims, N, M, alpha, 0, f, u, g=g)
+    ref_s = oracle.half_sweep(dims, N, M, alpha, 1, f, ref_s, g=g)
+    with B.Solver(N, M, alpha, dims=dims, fft=2) as s:
+        R = host(s.residual(dev(f), dev(u), g=dev(g)))
+        U = dev(u)
+        s.smooth(dev(f), U, g=dev(g))
+        U = host(U)
+    scale = np.abs(f).max() + (2 * dims * (N + 1) ** 2 + 2 * oracle.l1_coeffs(M, alpha)[0]) * np.abs(u).max()
+    assert relmax(R, ref_r, scale) <= 1e-12
+    assert relmax(U, ref_s) <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp64r", 1e-10), ("fp32", 1e-8), ("bf16x3", 1e-8)])
+def test_fft_solve_matches_direct_solve(B, prec, tol):
+    w = W.random_modes_1d(255, 1500, 0.45, seed=77)
+    f = w.forcing()
+    ref = oracle.direct_solve(1, w.N, w.M, w.alpha, f)
+    with B.Solver(w.N, w.M, w.alpha, precision=prec, fft=2) as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(dev(f), U, tol=1e-12)
+        U = host(U)
+    assert info["rc"] in (0, 2), info
+    assert relmax(U, ref) <= tol, (info, relmax(U, ref))
+
+
+def test_fft_and_dense_routes_agree(B):
+    """Same cycles, products by the two routes: the iterates agree to
+    rounding and the iteration counts are the same."""
+    w = W.random_modes_1d(511, 1024, 0.3, seed=78)
+    f = w.forcing()
+    outs = []
+    for fft in (0, 2):
+        with B.Solver(w.N, w.M, w.alpha, fft=fft) as s:
+            U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+            info = s.solve(dev(f), U, tol=1e-9)
+            outs.append((host(U), info["iters"]))
+    assert outs[0][1] == outs[1][1]
+    assert relmax(outs[1][0], outs[0][0]) <= 1e-11
+
+
+def test_fft_batch_with_uneven_problems(B):
+    ws = [W.random_modes_1d(N, M, a, seed=90 + i) for i, (N, M, a) in
+          enumerate([(63, 64, 0.5), (127, 1100, 0.2), (255, 40, 0.8), (31, 2048, 0.6)])]
+    refs = [oracle.direct_solve(1, w.N, w.M, w.alpha, w.forcing()) for w in ws]
+    b = B.Batch([w.N for w in ws], [w.M for w in ws], [w.alpha for w in ws], fft=2)
+    us = [torch.zeros((w.M, w.N), dtype=torch.float64, device="cuda") for w in ws]
+    rc, infos = b.solve([dev(w.forcing()) for w in ws], us, tol=1e-12)
+    b.close()
+    for u, ref, inf in zip(us, refs, infos):
+        assert relmax(host(u), ref) <= 1e-10, inf
+
+
+def test_fft_option_validated(B):
+    with pytest.raises(B.MgwrError):
+        B.Solver(15, 64, 0.5, fft=3)
