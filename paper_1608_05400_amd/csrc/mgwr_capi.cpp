@@ -95,6 +95,13 @@ constexpr int kFftMinM = 1024;
 // split-BF16 matrix-core products (about 5x faster per flop than FP64).
 constexpr int kFftMinMLow = 4096;
 constexpr int kFftMinCols = 64;
+// The FP32 FFT route of a smoother product only where its history part is
+// small against the diagonal (c / sigma <= this): an FFT's rounding error is
+// spread evenly over all time levels, and on the coarse levels, where the
+// history carries the whole line solve, FP32 error of that kind slows the
+// refinement (1D workload, alpha = 0.7: cycle factor 0.06 -> 0.09).  Those
+// levels take the FFT route in FP64.
+constexpr double kFft32MaxHist = 0.1;
 // Bytes of each of the two work arrays of the FFT route (columns beyond what
 // fits are transformed in chunks).
 constexpr size_t kFftBufCap = (size_t)1 << 30;
@@ -210,6 +217,7 @@ struct Level {
     int fft_tuned = -1;                     // products by FFT (1) or dense (0); -1: size rule
     void *spec_inv = nullptr;               // DFT of the zero-padded inverse column (FFT route)
     void *spec32_inv_h = nullptr;           // FP32 DFT of its history part (mixed cycles)
+    void *spec32_inv = nullptr;             // FP32 DFT of the whole column (mgwr_toeplitz_apply)
 };
 
 // Tile knobs per product arithmetic (FP64, FP32, split-BF16).
@@ -357,7 +365,7 @@ struct mgwr_ctx {
     // FFT route of the FP64 products: transform length, twiddles, spectra, work arrays
     int fft_L = 0;
     void *fft_tw = nullptr, *spec_tm = nullptr;
-    void *fft_tw32 = nullptr, *spec32_tm_h = nullptr;
+    void *fft_tw32 = nullptr, *spec32_tm_h = nullptr, *spec32_tm = nullptr;
     void *fft_buf0 = nullptr, *fft_buf1 = nullptr;
     size_t fft_buf_cap = 0;
     Tuning tune;
@@ -542,6 +550,10 @@ int alloc_fft(mgwr_t h)
         void **dst32 = (l == nl) ? &h->spec32_tm_h : &h->lv[l].spec32_inv_h;
         CHK(dmalloc(h->alloc, dst32, sizeof(float) * f32.size()));
         HIPCHK(hipMemcpy(*dst32, f32.data(), sizeof(float) * f32.size(), hipMemcpyHostToDevice));
+        std::vector<float> g32(specs[l].begin(), specs[l].end());
+        void **dstf = (l == nl) ? &h->spec32_tm : &h->lv[l].spec32_inv;
+        CHK(dmalloc(h->alloc, dstf, sizeof(float) * g32.size()));
+        HIPCHK(hipMemcpy(*dstf, g32.data(), sizeof(float) * g32.size(), hipMemcpyHostToDevice));
     }
     const size_t need = (size_t)16 * L * ((h->lv.back().P + 1) / 2);
     h->fft_buf_cap = std::min(need, kFftBufCap);
@@ -801,6 +813,11 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
                                   L.ih2, 0.0, h->panel64, nullptr, Pc});
             a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
             if (fft_for(h, t.lev)) set_fft(h, a, L.spec_inv);
+        } else if (fft_for(h, t.lev, mode) && h->c > kFft32MaxHist * L.sigma) {
+            rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
+                                  L.ih2, 0.0, h->panel64, nullptr, Pc});
+            a.mode = GM_F64; a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
+            set_fft(h, a, L.spec_inv);
         } else if (mode == GM_F32 || fft_for(h, t.lev, mode)) {
             rhs.push_back(RhsArgs{1, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
                                   L.ih2, L.lam0, h->panel32, nullptr, Pc});
@@ -865,7 +882,7 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
         }
         prods.push_back(a);
         posts.push_back(PostArgs{h->dims, L.n, h->M, t.H->f[t.lev], t.H->u[t.lev], nullptr, h->cd,
-                                 fine ? t.H->g : nullptr, L.ih2, (mode == GM_F64) ? 0.0 : h->c, out});
+                                 fine ? t.H->g : nullptr, L.ih2, (a.mode == GM_F64) ? 0.0 : h->c, out});
     }
     HIPCHK(launch_operand(ops, ex.st, ex.s));
     CHK(run_gemms(ex, prods, level));
@@ -1786,6 +1803,13 @@ int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int
         a.B = B; a.ldb = ldb;
         if (fft_for(h, which < 0 ? (int)h->lv.size() - 1 : which))
             set_fft(h, a, which < 0 ? h->spec_tm : h->lv[which].spec_inv);
+        return run_gemms(ex, {a}, which);
+    }
+    // the FFT route in FP32 reads the FP64 operand itself
+    const int lev = which < 0 ? (int)h->lv.size() - 1 : which;
+    if (fft_for(h, lev, mode)) {
+        a.B = B; a.ldb = ldb;
+        set_fft32(h, a, which < 0 ? h->spec32_tm : h->lv[which].spec32_inv, true);
         return run_gemms(ex, {a}, which);
     }
     // FP32 / split-BF16 operands are built in temporaries (test path)

@@ -138,3 +138,23 @@ def test_fft_batch_with_uneven_problems(B):
 def test_fft_option_validated(B):
     with pytest.raises(B.MgwrError):
         B.Solver(15, 64, 0.5, fft=3)
+
+
+@pytest.mark.parametrize("M", [64, 1000, 4096, 16384])
+@pytest.mark.parametrize("P", [2, 129])
+def test_fft32_product_matches_oracle_coefficients(B, M, P):
+    """The FP32 FFT route (history products of the mixed cycles) on its own:
+    FP32 arithmetic, so 1e-6 of the term size as for the dense FP32 kernel."""
+    alpha = 0.7
+    rng = np.random.default_rng(M + P)
+    t = np.arange(1, M + 1) / M
+    X = rng.standard_normal((M, P)) * t[:, None] ** 1.5
+    c, d, r = oracle.l1_coeffs(M, alpha)
+    Tm = toeplitz_lower(r)
+    ref = Tm @ X
+    scale = (np.abs(Tm) @ np.abs(X)).max()
+    with B.Solver(7, M, alpha, fft=2) as s:
+        C = host(s.toeplitz_apply(dev(X), which=-1, precision="fp32"))
+    err = relmax(C, ref, scale)
+    print(f"M {M} P {P}: max error / term size {err:.2e}")
+    assert err <= 1e-6
