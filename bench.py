@@ -226,17 +226,21 @@ def fft_pass_bytes(r):
     reads the K x P input once and writes the L x ceil(P/2) complex work
     array; each other pass reads and writes that array; the last inverse pass
     reads it and writes the M x P FP64 product (and reads it first when the
-    epilogue accumulates).  n = ceil(log2(L) / 5) passes per direction."""
+    epilogue accumulates).  n passes per direction: ceil(log2(L) / 8) from
+    L = 512 on (radix-256 passes), ceil(log2(L) / 5) below."""
     M, P, K, kid = r["M"], r["P"], r["K"], r["kernel"]
     mode, epi = (kid >> 4) & 15, kid & 15
     L = 64
     while L < 2 * M:
         L *= 2
-    n = (L.bit_length() - 1 + 4) // 5
+    lg = L.bit_length() - 1
+    n = (lg + 7) // 8 if L >= 512 else (lg + 4) // 5
     c = 16 if mode == 0 else 8                        # complex FP64 / FP32
-    insz = 8 if (mode == 0 or epi == 0) else 4        # FP32 smoother reads an FP32 panel
+    insz = 4 if epi == 2 else 8                       # an FP32 panel, else FP64 input
     Q = (P + 1) // 2
-    epi_bytes = 8.0 * M * P * (2 if epi in (2, 3, 4) else 1)
+    # the last pass writes the product; scatter-add reads the old values,
+    # scatter-diag reads the right-hand sides
+    epi_bytes = 8.0 * M * P * (2 if epi in (2, 3, 4, 5) else 1)
     return K * P * insz + (4 * n - 2) * L * Q * c + epi_bytes
 
 

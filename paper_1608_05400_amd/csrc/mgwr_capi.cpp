@@ -818,11 +818,19 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
                                   L.ih2, 0.0, h->panel64, nullptr, Pc});
             a.mode = GM_F64; a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
             set_fft(h, a, L.spec_inv);
-        } else if (mode == GM_F32 || fft_for(h, t.lev, mode)) {
+        } else if (fft_for(h, t.lev, mode)) {
+            // FP64 right-hand sides; the FFT's first pass rounds them to FP32
+            // and its last pass writes lambda_0 b + history into the colour's
+            // points of U (one store, the diagonal term in FP64)
+            rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
+                                  L.ih2, 0.0, h->panel64, nullptr, Pc});
+            a.coef = &L.inv_h; a.epi = EPI_SCATTER_DIAG; a.B = h->panel64; a.ldb = Pc;
+            a.ea.b = h->panel64; a.ea.ldb_diag = Pc; a.ea.diag = L.lam0;
+            set_fft32(h, a, L.spec32_inv_h, true);
+        } else if (mode == GM_F32) {
             rhs.push_back(RhsArgs{1, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
                                   L.ih2, L.lam0, h->panel32, nullptr, Pc});
             a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.B = h->panel32; a.ldb = Pc;
-            if (fft_for(h, t.lev, mode)) set_fft32(h, a, L.spec32_inv_h, false);
         } else {
             const long ldp = packed_ld(Pc);
             rhs.push_back(RhsArgs{2, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
@@ -1367,10 +1375,32 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
         h->tune.tuned = true;   // dc_block_of reads the tuned blocks from here on
     }
     auto set_kn = [&](int mode, const TileKnobs &k) { for (mgwr_ctx *h : hs) h->tune.kn[mode] = k; };
+    // the untuned choices, to fall back on
+    struct Snap { TileKnobs kn[3]; std::vector<int> dc, fft; };
+    auto snap = [&]() {
+        std::vector<Snap> v;
+        for (mgwr_ctx *h : hs) {
+            Snap x;
+            for (int m = 0; m < 3; ++m) x.kn[m] = h->tune.kn[m];
+            for (auto &L : h->lv) { x.dc.push_back(L.dc_tuned); x.fft.push_back(L.fft_tuned); }
+            v.push_back(x);
+        }
+        return v;
+    };
+    auto restore = [&](const std::vector<Snap> &v) {
+        for (size_t i = 0; i < hs.size(); ++i) {
+            for (int m = 0; m < 3; ++m) hs[i]->tune.kn[m] = v[i].kn[m];
+            for (size_t l = 0; l < hs[i]->lv.size(); ++l) {
+                hs[i]->lv[l].dc_tuned = v[i].dc[l];
+                hs[i]->lv[l].fft_tuned = v[i].fft[l];
+            }
+        }
+    };
+    const std::vector<Snap> untuned = snap();
     double best = 0;
     CHK(time_cycle(R, hs, tprec, 2, best));   // also warms up
     CHK(time_cycle(R, hs, tprec, 2, best));
-    const double ms_default = best;
+    double ms_default = best;
     std::vector<int> modes;
     if (tprec == MGWR_FP64_REFINED) modes = {GM_F64};
     else if (tprec == MGWR_MIXED_FP32) modes = {GM_F32};
@@ -1453,6 +1483,22 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
                 if (t < best * 0.995) { best = t; bestb = b; }
             }
             set_dc(bestb);
+        }
+    }
+    // the choices against the untuned ones, head to head (stage timings are
+    // noisy for short cycles); keep the faster
+    {
+        const std::vector<Snap> tuned = snap();
+        double t_tuned = 0, t_default = 0;
+        CHK(time_cycle(R, hs, tprec, 3, t_tuned));
+        restore(untuned);
+        CHK(time_cycle(R, hs, tprec, 3, t_default));
+        ms_default = t_default;
+        if (t_tuned < t_default) {
+            restore(tuned);
+            best = t_tuned;
+        } else {
+            best = t_default;
         }
     }
     for (mgwr_ctx *h : hs) {

@@ -47,13 +47,18 @@ enum EpiKind {
     EPI_SCATTER = 1,     // out[i][colour_point(p)] = acc          (smoother, full product)
     EPI_SCATTER_ADD = 2, // out[i][colour_point(p)] += acc         (smoother, history product)
     EPI_SUB = 3,         // out[i][p] -= acc                       (D&C history update)
-    EPI_ADD = 4          // out[i][p] += acc                       (D&C base block, history part)
+    EPI_ADD = 4,         // out[i][p] += acc                       (D&C base block, history part)
+    EPI_SCATTER_DIAG = 5 // out[i][colour_point(p)] = diag b[i][p] + acc  (smoother: the FP64
+                         //   diagonal term of the line solve plus its history product)
 };
 
 struct EpiArgs {
     double *out = nullptr;     // output (STORE/SUB/ADD) or the iterate U of the level (SCATTER*)
     long ldo = 0;
     int dims = 1, n = 1, colour = 0;   // grid of the level (points per dim) and colour
+    const double *b = nullptr; // EPI_SCATTER_DIAG: right-hand sides [M][ldb_diag]
+    long ldb_diag = 0;
+    double diag = 0.0;         // EPI_SCATTER_DIAG: first entry of the inverse column
 };
 
 // Tile choices of the product kernels (set by the autotuner).

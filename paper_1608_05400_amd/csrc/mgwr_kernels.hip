@@ -121,6 +121,9 @@ __device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
     } else if constexpr (EPI == EPI_ADD) {
         GLOBAL double *o = out + (long)i * e.ldo + p;
         *o = *o + acc;
+    } else if constexpr (EPI == EPI_SCATTER_DIAG) {
+        out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] =
+            e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + p] + acc;
     }
 }
 
@@ -1131,22 +1134,128 @@ __global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
     }
 }
 
-// Radices of the passes for a transform of length L = 2^s (L >= 64): the
-// remainder (2^(s mod 5)) first, then radix 32, so that the last inverse
-// pass (the one with the epilogue) is always radix 32.
+// A Stockham pass of radix R = 16 R2 (64, 128 or 256) by one block for C
+// column pairs: the R-point DFT as two stages (Cooley-Tukey, R = 16 x R2):
+// 16-point DFTs over elements R2 apart in registers, twiddles, an exchange
+// through LDS, then R2-point DFTs.  Rows of 16 column pairs (256 bytes in
+// FP64, 128 in FP32) are read and written whole; 16 pairs with one DFT per
+// thread measured faster than 8 (narrow rows) or 32 (two DFTs per thread).
+template <typename T> constexpr int fft_lds_cols() { return 16; }
+
+template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
+__global__ __launch_bounds__(256) void k_fft_lds(FftPass a)
+{
+    using C = typename Cx<T>::v;
+    constexpr int R1 = 16, R = R1 * R2, NC = fft_lds_cols<T>();
+    __shared__ C sh[R * NC];
+    const int nj = a.L / R;
+    const int qblocks = (a.Q + NC - 1) / NC;
+    const int qb = blockIdx.x % qblocks, j = blockIdx.x / qblocks;
+    const int q0 = qb * NC;
+    const GLOBAL C *tw = gview<C>(a.tw);
+    const int jm = j % a.Ns;
+    const long pstep = (long)jm * (a.Ltw / (a.Ns * R));   // twiddles of the pass
+    const int wstep = a.Ltw / R;                           // twiddles inside the R-point DFT
+    for (int job = threadIdx.x; job < R2 * NC; job += 256) {
+        const int c = job % NC, r2 = job / NC, q = q0 + c;
+        C v[R1];
+#pragma unroll
+        for (int r1 = 0; r1 < R1; ++r1) {
+            const int r = R2 * r1 + r2, tau = j + r * nj;
+            C x = C{0, 0};
+            if (q < a.Q) {
+                if constexpr (SRC == FS_REAL) {
+                    T re = 0, im = 0;
+                    if (tau < a.K) {
+                        const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb + a.c0;
+                        if (a.c0 + 2 * q < a.P) re = (T)row[2 * q];
+                        if (a.c0 + 2 * q + 1 < a.P) im = (T)row[2 * q + 1];
+                    }
+                    x = C{re, im};
+                } else {
+                    x = gview<C>(a.src)[(long)tau * a.Q + q];
+                    if constexpr (SRC == FS_SPEC) x = cmul(x, gview<C>(a.spec)[tau]);
+                }
+            }
+            if (a.Ns > 1 && r > 0) {
+                C w = tw[pstep * r];
+                if (SIGN > 0) w.y = -w.y;
+                x = cmul(x, w);
+            }
+            v[r1] = x;
+        }
+        dft_reg<T, R1, SIGN>(v, tw, a.Ltw);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            C w = tw[(long)(r2 * k1) * wstep];
+            if (SIGN > 0) w.y = -w.y;
+            sh[(k1 * R2 + r2) * NC + c] = cmul(v[k1], w);
+        }
+    }
+    __syncthreads();
+    const int base = (j / a.Ns) * a.Ns * R + jm;
+    for (int job = threadIdx.x; job < R1 * NC; job += 256) {
+        const int c = job % NC, k1 = job / NC, q = q0 + c;
+        C v[R2];
+#pragma unroll
+        for (int r2 = 0; r2 < R2; ++r2) v[r2] = sh[(k1 * R2 + r2) * NC + c];
+        dft_reg<T, R2, SIGN>(v, tw, a.Ltw);
+        if (q >= a.Q) continue;
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+            const int tau = base + (k1 + R1 * k2) * a.Ns;
+            if constexpr (DST == FD_CPLX) {
+                gview_rw<C>(a.dst)[(long)tau * a.Q + q] = v[k2];
+            } else {
+                if (tau < a.M) {
+                    const int cc = a.c0 + 2 * q;
+                    if (cc < a.P) epi_apply<EPI>(a.ea, tau, cc, (double)v[k2].x * a.scale);
+                    if (cc + 1 < a.P) epi_apply<EPI>(a.ea, tau, cc + 1, (double)v[k2].y * a.scale);
+                }
+            }
+        }
+    }
+}
+
+// Radices of the passes for a transform of length L = 2^s.  From L = 512 on:
+// the remainder (2^(s mod 8)) first, then radix 256 (two stages through
+// LDS), so a length-32768 transform takes two passes; the last inverse pass
+// (the one with the epilogue) is radix 256.  Shorter transforms: the
+// remainder 2^(s mod 5) first, then radix 32 in registers.
 static std::vector<int> fft_plan(int L)
 {
     int lg = 0;
     while ((1 << lg) < L) ++lg;
     std::vector<int> r;
+    if (L >= 512) {
+        if (lg % 8) r.push_back(1 << (lg % 8));
+        for (int i = 0; i < lg / 8; ++i) r.push_back(256);
+        return r;
+    }
     if (lg % 5) r.push_back(1 << (lg % 5));
     for (int i = 0; i < lg / 5; ++i) r.push_back(32);
     return r;
 }
 
+template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
+static void launch_fft_lds(const FftPass &p, hipStream_t s)
+{
+    constexpr int R = 16 * R2, NC = fft_lds_cols<T>();
+    const long blocks = (long)((p.Q + NC - 1) / NC) * (p.L / R);
+    hipLaunchKernelGGL((k_fft_lds<T, TIN, R2, SIGN, SRC, DST, EPI>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+}
+
 template <typename T, typename TIN, int SIGN, int SRC, int DST, int EPI>
 static void launch_fft_pass(int R, const FftPass &p, hipStream_t s)
 {
+    if (R >= 64) {
+        if constexpr (DST == FD_CPLX) {
+            if (R == 64) launch_fft_lds<T, TIN, 4, SIGN, SRC, DST, EPI>(p, s);
+            else if (R == 128) launch_fft_lds<T, TIN, 8, SIGN, SRC, DST, EPI>(p, s);
+            else launch_fft_lds<T, TIN, 16, SIGN, SRC, DST, EPI>(p, s);
+        }
+        return;
+    }
     const long threads = (long)p.Q * (p.L / R);
     const dim3 grid((unsigned)((threads + 255) / 256));
     switch (R) {
@@ -1159,8 +1268,12 @@ static void launch_fft_pass(int R, const FftPass &p, hipStream_t s)
 }
 
 template <typename T, int EPI>
-static void launch_fft_last(const FftPass &p, hipStream_t s)
+static void launch_fft_last(int R, const FftPass &p, hipStream_t s)
 {
+    if (R == 256) {
+        launch_fft_lds<T, T, 16, 1, FS_CPLX, FD_EPI, EPI>(p, s);
+        return;
+    }
     const dim3 grid((unsigned)(((long)p.Q * (p.L / 32) + 255) / 256));
     hipLaunchKernelGGL((k_fft_pass<T, T, 32, 1, FS_CPLX, FD_EPI, EPI>), grid, dim3(256), 0, s, p);
 }
@@ -1204,9 +1317,10 @@ static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
                 cur ^= 1;
             } else {
                 switch (a.epi) {
-                case EPI_STORE: launch_fft_last<T, EPI_STORE>(p, s); break;
-                case EPI_SCATTER: launch_fft_last<T, EPI_SCATTER>(p, s); break;
-                case EPI_SCATTER_ADD: launch_fft_last<T, EPI_SCATTER_ADD>(p, s); break;
+                case EPI_STORE: launch_fft_last<T, EPI_STORE>(plan[i], p, s); break;
+                case EPI_SCATTER: launch_fft_last<T, EPI_SCATTER>(plan[i], p, s); break;
+                case EPI_SCATTER_ADD: launch_fft_last<T, EPI_SCATTER_ADD>(plan[i], p, s); break;
+                case EPI_SCATTER_DIAG: launch_fft_last<T, EPI_SCATTER_DIAG>(plan[i], p, s); break;
                 default: return hipErrorInvalidValue;
                 }
             }
