@@ -226,7 +226,7 @@ def fft_pass_bytes(r):
     reads the K x P input once and writes the L x ceil(P/2) complex work
     array; each other pass reads and writes that array; the last inverse pass
     reads it and writes the M x P FP64 product (and reads it first when the
-    epilogue accumulates).  n passes per direction: ceil(log2(L) / 8) from
+    epilogue reads).  n passes per direction: ceil(log2(L) / 8) from
     L = 512 on (radix-256 passes), ceil(log2(L) / 5) below."""
     M, P, K, kid = r["M"], r["P"], r["K"], r["kernel"]
     mode, epi = (kid >> 4) & 15, kid & 15
@@ -239,8 +239,9 @@ def fft_pass_bytes(r):
     insz = 4 if epi == 2 else 8                       # an FP32 panel, else FP64 input
     Q = (P + 1) // 2
     # the last pass writes the product; scatter-add reads the old values,
-    # scatter-diag reads the right-hand sides
-    epi_bytes = 8.0 * M * P * (2 if epi in (2, 3, 4, 5) else 1)
+    # scatter-diag reads the right-hand sides, the residual epilogue reads
+    # the right-hand side and the iterate
+    epi_bytes = 8.0 * M * P * (3 if epi == 6 else 2 if epi in (2, 3, 4, 5) else 1)
     return K * P * insz + (4 * n - 2) * L * Q * c + epi_bytes
 
 

@@ -229,10 +229,13 @@ int mgwr_batch_destroy(mgwr_batch_t b);
  * its launches one by one instead of replaying graphs.  kernel identifies
  * the kernel instantiation: (kind << 8) | (mode << 4) | epilogue, with kind
  * 0 = narrow (64x16 tiles), 1 = wide 128x64, 2 = wide 256x64, 3 = split-BF16
- * 256x128, 4 = FFT route (all passes of one product); mode 0 = FP64, 1 = FP32, 2 = split-BF16; epilogue 0 = store
- * (residual product, D&C base block in FP64), 1 = colour scatter (smoother,
- * whole line solve), 2 = colour scatter-add (smoother, history part),
- * 3 = subtract (D&C history update), 4 = add (D&C base block, history part).
+ * 256x128, 4 = FFT route (all passes of one product); mode 0 = FP64, 1 = FP32,
+ * 2 = split-BF16; epilogue 0 = store (residual product, D&C base block in
+ * FP64), 1 = colour scatter (smoother, whole line solve), 2 = colour
+ * scatter-add (smoother, history part), 3 = subtract (D&C history update),
+ * 4 = add (D&C base block, history part), 5 = colour scatter of the diagonal
+ * term plus the history part (smoother, FFT route), 6 = residual (FFT route:
+ * the stencil part minus the product, written as the residual).
  * A record covers one launch, possibly over several problems: M and K are
  * those of the first, P the sum of the columns, flops the sum of the
  * multiply-adds that are not structurally zero, times 2.  ms covers the

@@ -888,9 +888,18 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
                                       nullptr, 0.0});
             a.coef = &h->tm_h; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
         }
+        const double diag = (a.mode == GM_F64) ? 0.0 : h->c;
+        if (a.fft_spec) {
+            // FFT route: its last pass applies the stencil part itself
+            a.epi = EPI_RESID;
+            a.ea.F = t.H->f[t.lev]; a.ea.U = t.H->u[t.lev]; a.ea.lo = nullptr; a.ea.cd = h->cd;
+            a.ea.g = fine ? t.H->g : nullptr; a.ea.ih2 = L.ih2; a.ea.diag = diag;
+            prods.push_back(a);
+            continue;
+        }
         prods.push_back(a);
         posts.push_back(PostArgs{h->dims, L.n, h->M, t.H->f[t.lev], t.H->u[t.lev], nullptr, h->cd,
-                                 fine ? t.H->g : nullptr, L.ih2, (a.mode == GM_F64) ? 0.0 : h->c, out});
+                                 fine ? t.H->g : nullptr, L.ih2, diag, out});
     }
     HIPCHK(launch_operand(ops, ex.st, ex.s));
     CHK(run_gemms(ex, prods, level));
@@ -993,6 +1002,7 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
         Level &L = h->lv.back();
         level = (int)h->lv.size() - 1;
         double *out = r.out ? r.out : h->res64;
+        bool fused = false;
         if (r.cold) {
             fills.push_back(FillArgs{h->M, L.P, h->cd, r.g, out, 1});
         } else {
@@ -1000,10 +1010,18 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
             a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm; a.epi = EPI_STORE;
             a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
             a.B = r.u; a.ldb = L.P;
-            if (fft_for(h, level)) set_fft(h, a, h->spec_tm);
+            if (fft_for(h, level)) {
+                set_fft(h, a, h->spec_tm);
+                // the FFT route's last pass applies the stencil part itself
+                a.epi = EPI_RESID;
+                a.ea.F = r.f; a.ea.U = r.u; a.ea.lo = r.lo; a.ea.cd = h->cd; a.ea.g = r.g;
+                a.ea.ih2 = L.ih2; a.ea.diag = 0.0;
+                fused = true;
+            }
             prods.push_back(a);
         }
-        posts.push_back(PostArgs{h->dims, L.n, h->M, r.f, r.u, r.lo, h->cd, r.g, L.ih2, 0.0, out});
+        if (!fused)
+            posts.push_back(PostArgs{h->dims, L.n, h->M, r.f, r.u, r.lo, h->cd, r.g, L.ih2, 0.0, out});
         if (r.norm2) {
             const long n = (long)h->M * L.P;
             norms.push_back(NormArgs{n, out, h->partials, norm_partial_blocks(n), r.norm2});

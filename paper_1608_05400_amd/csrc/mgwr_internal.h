@@ -48,8 +48,10 @@ enum EpiKind {
     EPI_SCATTER_ADD = 2, // out[i][colour_point(p)] += acc         (smoother, history product)
     EPI_SUB = 3,         // out[i][p] -= acc                       (D&C history update)
     EPI_ADD = 4,         // out[i][p] += acc                       (D&C base block, history part)
-    EPI_SCATTER_DIAG = 5 // out[i][colour_point(p)] = diag b[i][p] + acc  (smoother: the FP64
+    EPI_SCATTER_DIAG = 5,// out[i][colour_point(p)] = diag b[i][p] + acc  (smoother: the FP64
                          //   diagonal term of the line solve plus its history product)
+    EPI_RESID = 6        // out[i][p] = (F + cd g - diag U - A_h U) - acc at (i, p)  (the
+                         //   residual; FFT route only)
 };
 
 struct EpiArgs {
@@ -58,7 +60,13 @@ struct EpiArgs {
     int dims = 1, n = 1, colour = 0;   // grid of the level (points per dim) and colour
     const double *b = nullptr; // EPI_SCATTER_DIAG: right-hand sides [M][ldb_diag]
     long ldb_diag = 0;
-    double diag = 0.0;         // EPI_SCATTER_DIAG: first entry of the inverse column
+    double diag = 0.0;         // EPI_SCATTER_DIAG: first entry of the inverse column;
+                               // EPI_RESID: coefficient of U (r_1 when acc is the history part)
+    // EPI_RESID: the level's right-hand side F [M][P], iterate U (+ lo, its
+    // double-double low part, or nullptr), c d_m, the initial condition g
+    // (or nullptr) and 1/h^2; out has ldo = P
+    const double *F = nullptr, *U = nullptr, *lo = nullptr, *cd = nullptr, *g = nullptr;
+    double ih2 = 0.0;
 };
 
 // Tile choices of the product kernels (set by the autotuner).

@@ -124,6 +124,23 @@ __device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
     } else if constexpr (EPI == EPI_SCATTER_DIAG) {
         out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] =
             e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + p] + acc;
+    } else if constexpr (EPI == EPI_RESID) {
+        // the stencil part of the residual (as OpPost), fused
+        const long k = (long)i * e.ldo;
+        const GLOBAL double *Uk = gview<double>(e.U) + k;
+        double rhs = gview<double>(e.F)[k + p];
+        if (e.g) rhs += gview<double>(e.cd)[i] * gview<double>(e.g)[p];
+        if (e.diag != 0.0) rhs -= e.diag * Uk[p];
+        double r;
+        if (e.lo) {
+            double shi, slo;
+            stencil_dd(Uk, gview<double>(e.lo) + k, e.dims, e.n, p, shi, slo);
+            r = (rhs - shi * e.ih2) - slo * e.ih2;
+        } else {
+            double st = (e.dims == 1 ? 2.0 : 4.0) * Uk[p] - nbr_sum(Uk, e.dims, e.n, p);
+            r = rhs - st * e.ih2;
+        }
+        out[k + p] = r - acc;
     }
 }
 
@@ -1321,6 +1338,7 @@ static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
                 case EPI_SCATTER: launch_fft_last<T, EPI_SCATTER>(plan[i], p, s); break;
                 case EPI_SCATTER_ADD: launch_fft_last<T, EPI_SCATTER_ADD>(plan[i], p, s); break;
                 case EPI_SCATTER_DIAG: launch_fft_last<T, EPI_SCATTER_DIAG>(plan[i], p, s); break;
+                case EPI_RESID: launch_fft_last<T, EPI_RESID>(plan[i], p, s); break;
                 default: return hipErrorInvalidValue;
                 }
             }
