@@ -242,7 +242,10 @@ def fft_pass_bytes(r):
     # scatter-diag reads the right-hand sides, the residual epilogue reads
     # the right-hand side and the iterate
     epi_bytes = 8.0 * M * P * (3 if epi == 6 else 2 if epi in (2, 3, 4, 5) else 1)
-    return K * P * insz + (4 * n - 2) * L * Q * c + epi_bytes
+    # from L = 512 on, the last forward pass, the spectrum and the first
+    # inverse pass are one kernel: one read and one write of the array less
+    work = (4 * n - 4) if L >= 512 else (4 * n - 2)
+    return K * P * insz + work * L * Q * c + epi_bytes
 
 
 def roofline_of(records, steps):

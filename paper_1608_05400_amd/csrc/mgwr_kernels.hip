@@ -1234,6 +1234,124 @@ __global__ __launch_bounds__(256) void k_fft_lds(FftPass a)
     }
 }
 
+// The middle of a product by the FFT route in one kernel: the last forward
+// pass (radix 256 = 16 x 16; block j holds rows j + k nj, nj = L / 256),
+// the product with the coefficient spectrum, and the first inverse pass.
+// That pass's RI-point DFTs (RI = the plan's first radix, no twiddles as
+// nothing is combined yet) take rows j' + s L / RI; for j' = j + g nj those
+// are rows j + nj (g + G s) of this block, G = 256 / RI, so the block does G
+// of them from LDS and writes rows j' RI + t.  One read and one write of the
+// work array less per product than the two passes.
+template <typename T, int RI>
+__global__ __launch_bounds__(256) void k_fft_mid(FftPass a)
+{
+    using C = typename Cx<T>::v;
+    constexpr int R = 256, NC = fft_lds_cols<T>(), G = R / RI;
+    static_assert(16 * NC == 256, "one radix-256 job per thread");
+    __shared__ C sh[R * NC];
+    const int nj = a.L / R;
+    const int qblocks = (a.Q + NC - 1) / NC;
+    const int qb = blockIdx.x % qblocks, j = blockIdx.x / qblocks;
+    const int q0 = qb * NC;
+    const GLOBAL C *tw = gview<C>(a.tw);
+    const GLOBAL C *src = gview<C>(a.src), *spec = gview<C>(a.spec);
+    GLOBAL C *dst = gview_rw<C>(a.dst);
+    const int wstep = a.Ltw / R;
+    {   // forward, first stage: 16-point DFTs over r = 16 r1 + r2 after the
+        // pass twiddles exp(-2 pi i j r / L), then the inner twiddles
+        const int c = threadIdx.x % NC, r2 = threadIdx.x / NC, q = q0 + c;
+        const long pstep = (long)j * (a.Ltw / a.L);
+        C v[16];
+#pragma unroll
+        for (int r1 = 0; r1 < 16; ++r1) {
+            const int r = 16 * r1 + r2;
+            C x = C{0, 0};
+            if (q < a.Q) x = src[(long)(j + r * nj) * a.Q + q];
+            if (r > 0) x = cmul(x, tw[pstep * r]);
+            v[r1] = x;
+        }
+        dft_reg<T, 16, -1>(v, tw, a.Ltw);
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) sh[(k1 * 16 + r2) * NC + c] = cmul(v[k1], tw[(long)(r2 * k1) * wstep]);
+    }
+    __syncthreads();
+    {   // forward, second stage: Y[k], k = k1 + 16 k2 (row j + k nj), times the spectrum
+        const int c = threadIdx.x % NC, k1 = threadIdx.x / NC;
+        C v[16];
+#pragma unroll
+        for (int r2 = 0; r2 < 16; ++r2) v[r2] = sh[(k1 * 16 + r2) * NC + c];
+        dft_reg<T, 16, -1>(v, tw, a.Ltw);
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) v[k2] = cmul(v[k2], spec[j + (k1 + 16 * k2) * nj]);
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) sh[(k1 + 16 * k2) * NC + c] = v[k2];
+    }
+    __syncthreads();
+    // inverse: group g takes x[s] = Y[g + G s], s < RI, and writes its DFT
+    // X[t] to row (j + g nj) RI + t
+    if constexpr (RI <= 16) {
+        for (int job = threadIdx.x; job < G * NC; job += 256) {
+            const int c = job % NC, g = job / NC, q = q0 + c;
+            C v[RI];
+#pragma unroll
+            for (int s2 = 0; s2 < RI; ++s2) v[s2] = sh[(g + G * s2) * NC + c];
+            dft_reg<T, RI, 1>(v, tw, a.Ltw);
+            if (q >= a.Q) continue;
+            const long row = (long)(j + g * nj) * RI;
+#pragma unroll
+            for (int t = 0; t < RI; ++t) dst[(row + t) * a.Q + q] = v[t];
+        }
+    } else {
+        // RI = 16 x RI2: 16-point DFTs over s = RI2 s1 + s2 (in place), the
+        // inner twiddles, then RI2-point DFTs giving X[k1 + 16 k2]
+        constexpr int RI2 = RI / 16;
+        const int wi = a.Ltw / RI;
+        for (int job = threadIdx.x; job < G * RI2 * NC; job += 256) {
+            const int c = job % NC, s2 = (job / NC) % RI2, g = job / (NC * RI2);
+            C v[16];
+#pragma unroll
+            for (int s1 = 0; s1 < 16; ++s1) v[s1] = sh[(g + G * (RI2 * s1 + s2)) * NC + c];
+            dft_reg<T, 16, 1>(v, tw, a.Ltw);
+#pragma unroll
+            for (int k1 = 0; k1 < 16; ++k1) {
+                C w = tw[(long)(s2 * k1) * wi];
+                w.y = -w.y;
+                sh[(g + G * (RI2 * k1 + s2)) * NC + c] = cmul(v[k1], w);
+            }
+        }
+        __syncthreads();
+        for (int job = threadIdx.x; job < G * 16 * NC; job += 256) {
+            const int c = job % NC, k1 = (job / NC) % 16, g = job / (NC * 16), q = q0 + c;
+            C v[RI2];
+#pragma unroll
+            for (int s2 = 0; s2 < RI2; ++s2) v[s2] = sh[(g + G * (RI2 * k1 + s2)) * NC + c];
+            dft_reg<T, RI2, 1>(v, tw, a.Ltw);
+            if (q >= a.Q) continue;
+            const long row = (long)(j + g * nj) * RI;
+#pragma unroll
+            for (int k2 = 0; k2 < RI2; ++k2) dst[(row + k1 + 16 * k2) * a.Q + q] = v[k2];
+        }
+    }
+}
+
+template <typename T>
+static void launch_fft_mid(int RI, const FftPass &p, hipStream_t s)
+{
+    constexpr int NC = fft_lds_cols<T>();
+    const dim3 grid((unsigned)((long)((p.Q + NC - 1) / NC) * (p.L / 256)));
+    switch (RI) {
+    case 2: hipLaunchKernelGGL((k_fft_mid<T, 2>), grid, dim3(256), 0, s, p); break;
+    case 4: hipLaunchKernelGGL((k_fft_mid<T, 4>), grid, dim3(256), 0, s, p); break;
+    case 8: hipLaunchKernelGGL((k_fft_mid<T, 8>), grid, dim3(256), 0, s, p); break;
+    case 16: hipLaunchKernelGGL((k_fft_mid<T, 16>), grid, dim3(256), 0, s, p); break;
+    case 32: hipLaunchKernelGGL((k_fft_mid<T, 32>), grid, dim3(256), 0, s, p); break;
+    case 64: hipLaunchKernelGGL((k_fft_mid<T, 64>), grid, dim3(256), 0, s, p); break;
+    case 128: hipLaunchKernelGGL((k_fft_mid<T, 128>), grid, dim3(256), 0, s, p); break;
+    default: hipLaunchKernelGGL((k_fft_mid<T, 256>), grid, dim3(256), 0, s, p); break;
+    }
+}
+
 // Radices of the passes for a transform of length L = 2^s.  From L = 512 on:
 // the remainder (2^(s mod 8)) first, then radix 256 (two stages through
 // LDS), so a length-32768 transform takes two passes; the last inverse pass
@@ -1313,9 +1431,13 @@ static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
         p.ea = a.ea;
         void *bufs[2] = {a.fft_buf0, a.fft_buf1};
         int cur = 0;   // buffer the next pass writes
+        // a plan that ends in radix 256 (L >= 512) does its last forward
+        // pass, the spectrum and its first inverse pass in one kernel
+        const size_t n = plan.size();
+        const bool mid = plan.back() == 256;
         // forward transform
         p.Ns = 1;
-        for (size_t i = 0; i < plan.size(); ++i) {
+        for (size_t i = 0; i + (mid ? 1 : 0) < n; ++i) {
             p.dst = bufs[cur];
             if (i == 0) launch_fft_pass<T, TIN, -1, FS_REAL, FD_CPLX, 0>(plan[i], p, s);
             else launch_fft_pass<T, T, -1, FS_CPLX, FD_CPLX, 0>(plan[i], p, s);
@@ -1323,10 +1445,18 @@ static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
             cur ^= 1;
             p.Ns *= plan[i];
         }
-        // times the coefficient spectrum, inverse transform, epilogue
-        p.Ns = 1;
-        for (size_t i = 0; i < plan.size(); ++i) {
-            if (i + 1 < plan.size()) {
+        size_t i0 = 0;
+        if (mid) {
+            p.dst = bufs[cur];
+            launch_fft_mid<T>(plan[0], p, s);
+            p.src = bufs[cur];
+            cur ^= 1;
+            i0 = 1;
+        }
+        // times the coefficient spectrum (unless done), inverse transform, epilogue
+        p.Ns = mid ? plan[0] : 1;
+        for (size_t i = i0; i < n; ++i) {
+            if (i + 1 < n) {
                 p.dst = bufs[cur];
                 if (i == 0) launch_fft_pass<T, T, 1, FS_SPEC, FD_CPLX, 0>(plan[i], p, s);
                 else launch_fft_pass<T, T, 1, FS_CPLX, FD_CPLX, 0>(plan[i], p, s);

@@ -158,3 +158,24 @@ def test_fft32_product_matches_oracle_coefficients(B, M, P):
     err = relmax(C, ref, scale)
     print(f"M {M} P {P}: max error / term size {err:.2e}")
     assert err <= 1e-6
+
+
+# Transform lengths L = pow2 >= 2M from 512 to 65536: every first radix of
+# the plans (2 ... 256) that the fused middle kernel (last forward pass,
+# spectrum, first inverse pass) is built for, with one and two blocks of
+# column pairs.
+@pytest.mark.parametrize("M", [200, 300, 1000, 2048, 4096, 5000, 16384, 20000])
+@pytest.mark.parametrize("P", [3, 33])
+def test_fft_product_every_plan(B, M, P):
+    alpha = 0.55
+    rng = np.random.default_rng(3 * M + P)
+    X = rng.standard_normal((M, P))
+    c, d, r = oracle.l1_coeffs(M, alpha)
+    # causal Toeplitz product = the first M terms of the full convolution
+    ref = np.stack([np.convolve(r, X[:, p])[:M] for p in range(P)], axis=1)
+    scale = np.stack([np.convolve(np.abs(r), np.abs(X[:, p]))[:M] for p in range(P)], axis=1).max()
+    with B.Solver(7, M, alpha, fft=2) as s:
+        C = host(s.toeplitz_apply(dev(X), which=-1, precision="fp64"))
+        C32 = host(s.toeplitz_apply(dev(X), which=-1, precision="fp32"))
+    assert relmax(C, ref, scale) <= 1e-12
+    assert relmax(C32, ref, scale) <= 1e-6
