@@ -1013,7 +1013,7 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
             if (fft_for(h, level)) {
                 set_fft(h, a, h->spec_tm);
                 // the FFT route's last pass applies the stencil part itself
-                a.epi = EPI_RESID;
+                a.epi = r.lo ? EPI_RESID_DD : EPI_RESID;
                 a.ea.F = r.f; a.ea.U = r.u; a.ea.lo = r.lo; a.ea.cd = h->cd; a.ea.g = r.g;
                 a.ea.ih2 = L.ih2; a.ea.diag = 0.0;
                 fused = true;

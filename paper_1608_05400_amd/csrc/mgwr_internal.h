@@ -50,8 +50,9 @@ enum EpiKind {
     EPI_ADD = 4,         // out[i][p] += acc                       (D&C base block, history part)
     EPI_SCATTER_DIAG = 5,// out[i][colour_point(p)] = diag b[i][p] + acc  (smoother: the FP64
                          //   diagonal term of the line solve plus its history product)
-    EPI_RESID = 6        // out[i][p] = (F + cd g - diag U - A_h U) - acc at (i, p)  (the
+    EPI_RESID = 6,       // out[i][p] = (F + cd g - diag U - A_h U) - acc at (i, p)  (the
                          //   residual; FFT route only)
+    EPI_RESID_DD = 7     // the same with the iterate U + lo (double-double)
 };
 
 struct EpiArgs {

@@ -55,22 +55,30 @@ __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b <<
 // ---------------------------------------------------------------------------
 // Stencils of the negative Laplacian (Section 2: 3-point; Section 6: 5-point)
 // with zero Dirichlet values, on one time row U of a level with n points/dim.
+// The neighbours are loaded at clamped indices and the ones outside the grid
+// replaced by zero, so that no load sits behind a branch.
+template <typename Ptr>
+__device__ inline void nbr_vals(Ptr U, int dims, int n, int p, double (&v)[4])
+{
+    // a 1D row is an n x 1 grid: its y-neighbours are outside
+    const int ny = dims == 1 ? 1 : n;
+    const int y = dims == 1 ? 0 : p / n, x = p - y * n;
+    v[0] = (double)U[x > 0 ? p - 1 : p];
+    v[1] = (double)U[x < n - 1 ? p + 1 : p];
+    v[2] = (double)U[y > 0 ? p - n : p];
+    v[3] = (double)U[y < ny - 1 ? p + n : p];
+    if (x == 0) v[0] = 0.0;
+    if (x == n - 1) v[1] = 0.0;
+    if (y == 0) v[2] = 0.0;
+    if (y == ny - 1) v[3] = 0.0;
+}
+
 template <typename Ptr>
 __device__ inline double nbr_sum(Ptr U, int dims, int n, int p)
 {
-    if (dims == 1) {
-        double s = 0.0;
-        if (p > 0) s += (double)U[p - 1];
-        if (p < n - 1) s += (double)U[p + 1];
-        return s;
-    }
-    int x = p % n, y = p / n;
-    double s = 0.0;
-    if (x > 0) s += (double)U[p - 1];
-    if (x < n - 1) s += (double)U[p + 1];
-    if (y > 0) s += (double)U[p - n];
-    if (y < n - 1) s += (double)U[p + n];
-    return s;
+    double v[4];
+    nbr_vals(U, dims, n, p, v);
+    return ((v[0] + v[1]) + v[2]) + v[3];
 }
 
 __device__ inline void two_sum(double a, double b, double &s, double &e)
@@ -86,62 +94,135 @@ __device__ inline void two_sum(double a, double b, double &s, double &e)
 template <typename Ptr>
 __device__ inline void stencil_dd(Ptr H, Ptr Lo, int dims, int n, int p, double &shi, double &slo)
 {
+    double h[4], l[4];
+    nbr_vals(H, dims, n, p, h);
+    nbr_vals(Lo, dims, n, p, l);
     double s = (dims == 1 ? 2.0 : 4.0) * H[p], e, acc = 0.0;
     double lo = (dims == 1 ? 2.0 : 4.0) * Lo[p];
-    if (dims == 1) {
-        if (p > 0) { two_sum(s, -H[p - 1], s, e); acc += e; lo -= Lo[p - 1]; }
-        if (p < n - 1) { two_sum(s, -H[p + 1], s, e); acc += e; lo -= Lo[p + 1]; }
-    } else {
-        int x = p % n, y = p / n;
-        if (x > 0) { two_sum(s, -H[p - 1], s, e); acc += e; lo -= Lo[p - 1]; }
-        if (x < n - 1) { two_sum(s, -H[p + 1], s, e); acc += e; lo -= Lo[p + 1]; }
-        if (y > 0) { two_sum(s, -H[p - n], s, e); acc += e; lo -= Lo[p - n]; }
-        if (y < n - 1) { two_sum(s, -H[p + n], s, e); acc += e; lo -= Lo[p + n]; }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {   // a zero neighbour leaves s exact and adds nothing
+        two_sum(s, -h[k], s, e);
+        acc += e;
+        lo -= l[k];
     }
     shi = s;
     slo = acc + lo;
 }
 
 // ---------------------------------------------------------------------------
-// Epilogue of the Toeplitz products, element (i, p) with product value acc.
+// Epilogue of the Toeplitz products, element (i, p) with product value acc,
+// in two parts so that a thread can issue the loads of all its elements
+// before any store (a store may alias a later load, so interleaved
+// read-modify-writes would wait for every load in turn): epi_pre reads what
+// the element needs, epi_put combines it with acc and stores.
 template <int EPI>
-__device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
+__device__ inline double epi_pre(const EpiArgs &e, int i, int p)
+{
+    const GLOBAL double *out = gview<double>(e.out);
+    if constexpr (EPI == EPI_SUB || EPI == EPI_ADD) {
+        return out[(long)i * e.ldo + p];
+    } else if constexpr (EPI == EPI_SCATTER_ADD) {
+        return out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)];
+    } else if constexpr (EPI == EPI_SCATTER_DIAG) {
+        return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + p];
+    } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
+        // the stencil part of the residual (as OpPost), fused; no load
+        // behind a branch (without g, F stands in for it and is not used;
+        // diag = 0 subtracts an exact zero)
+        const long k = (long)i * e.ldo;
+        const GLOBAL double *Uk = gview<double>(e.U) + k;
+        const double gv = gview<double>(e.g ? e.g : e.F)[p], cdv = gview<double>(e.cd)[i];
+        double rhs = gview<double>(e.F)[k + p];
+        if (e.g) rhs += cdv * gv;
+        rhs -= e.diag * Uk[p];
+        if constexpr (EPI == EPI_RESID_DD) {
+            double shi, slo;
+            stencil_dd(Uk, gview<double>(e.lo) + k, e.dims, e.n, p, shi, slo);
+            return (rhs - shi * e.ih2) - slo * e.ih2;
+        } else {
+            double st = (e.dims == 1 ? 2.0 : 4.0) * Uk[p] - nbr_sum(Uk, e.dims, e.n, p);
+            return rhs - st * e.ih2;
+        }
+    } else {
+        return 0.0;
+    }
+}
+
+template <int EPI>
+__device__ inline void epi_put(const EpiArgs &e, int i, int p, double pre, double acc)
 {
     GLOBAL double *out = gview_rw<double>(e.out);
     if constexpr (EPI == EPI_STORE) {
         out[(long)i * e.ldo + p] = acc;
     } else if constexpr (EPI == EPI_SUB) {
-        GLOBAL double *o = out + (long)i * e.ldo + p;
-        *o = *o - acc;
+        out[(long)i * e.ldo + p] = pre - acc;
+    } else if constexpr (EPI == EPI_ADD) {
+        out[(long)i * e.ldo + p] = pre + acc;
     } else if constexpr (EPI == EPI_SCATTER) {
         out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = acc;
-    } else if constexpr (EPI == EPI_SCATTER_ADD) {
-        GLOBAL double *o = out + (long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p);
-        *o = *o + acc;
-    } else if constexpr (EPI == EPI_ADD) {
-        GLOBAL double *o = out + (long)i * e.ldo + p;
-        *o = *o + acc;
-    } else if constexpr (EPI == EPI_SCATTER_DIAG) {
-        out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] =
-            e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + p] + acc;
-    } else if constexpr (EPI == EPI_RESID) {
-        // the stencil part of the residual (as OpPost), fused
-        const long k = (long)i * e.ldo;
-        const GLOBAL double *Uk = gview<double>(e.U) + k;
-        double rhs = gview<double>(e.F)[k + p];
-        if (e.g) rhs += gview<double>(e.cd)[i] * gview<double>(e.g)[p];
-        if (e.diag != 0.0) rhs -= e.diag * Uk[p];
-        double r;
-        if (e.lo) {
-            double shi, slo;
-            stencil_dd(Uk, gview<double>(e.lo) + k, e.dims, e.n, p, shi, slo);
-            r = (rhs - shi * e.ih2) - slo * e.ih2;
-        } else {
-            double st = (e.dims == 1 ? 2.0 : 4.0) * Uk[p] - nbr_sum(Uk, e.dims, e.n, p);
-            r = rhs - st * e.ih2;
-        }
-        out[k + p] = r - acc;
+    } else if constexpr (EPI == EPI_SCATTER_ADD || EPI == EPI_SCATTER_DIAG) {
+        out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = pre + acc;
+    } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
+        out[(long)i * e.ldo + p] = pre - acc;
     }
+}
+
+// Residual epilogue values (as epi_pre) of the adjacent columns p and p + 1
+// of row i on a 1D level, the second only meaningful when p + 1 < n: the
+// neighbour values the two share are loaded once, at clamped indices.
+template <bool DD>
+__device__ inline void resid_pre_pair_1d(const EpiArgs &e, int i, int p, double &r0, double &r1)
+{
+    const int n = e.n;
+    const long k = (long)i * e.ldo;
+    const int pl = p > 0 ? p - 1 : p, p1 = min(p + 1, n - 1), p2 = min(p + 2, n - 1);
+    const GLOBAL double *Uk = gview<double>(e.U) + k, *Fk = gview<double>(e.F) + k;
+    const GLOBAL double *g = gview<double>(e.g ? e.g : e.F);
+    double uL = Uk[pl], u0 = Uk[p], u1 = Uk[p1], uR = Uk[p2];
+    const double f0 = Fk[p], f1 = Fk[p1], g0 = g[p], g1 = g[p1], cdv = gview<double>(e.cd)[i];
+    double lL = 0.0, l0 = 0.0, l1 = 0.0, lR = 0.0;
+    if constexpr (DD) {
+        const GLOBAL double *Lk = gview<double>(e.lo) + k;
+        lL = Lk[pl]; l0 = Lk[p]; l1 = Lk[p1]; lR = Lk[p2];
+    }
+    if (p == 0) uL = lL = 0.0;
+    const double u1n = (p + 1 < n) ? u1 : 0.0, uRn = (p + 2 < n) ? uR : 0.0;
+    const double l1n = (p + 1 < n) ? l1 : 0.0, lRn = (p + 2 < n) ? lR : 0.0;
+    double rhs0 = f0, rhs1 = f1;
+    if (e.g) {
+        rhs0 += cdv * g0;
+        rhs1 += cdv * g1;
+    }
+    rhs0 -= e.diag * u0;
+    rhs1 -= e.diag * u1;
+    if constexpr (DD) {
+        // stencil_dd of both points
+        double s0 = 2.0 * u0, s1 = 2.0 * u1, e0, e1, a0 = 0.0, a1 = 0.0;
+        double lo0 = 2.0 * l0, lo1 = 2.0 * l1;
+        two_sum(s0, -uL, s0, e0); a0 += e0; lo0 -= lL;
+        two_sum(s0, -u1n, s0, e0); a0 += e0; lo0 -= l1n;
+        two_sum(s1, -u0, s1, e1); a1 += e1; lo1 -= l0;
+        two_sum(s1, -uRn, s1, e1); a1 += e1; lo1 -= lRn;
+        r0 = (rhs0 - s0 * e.ih2) - (a0 + lo0) * e.ih2;
+        r1 = (rhs1 - s1 * e.ih2) - (a1 + lo1) * e.ih2;
+    } else {
+        r0 = rhs0 - (2.0 * u0 - (uL + u1n)) * e.ih2;
+        r1 = rhs1 - (2.0 * u1 - (u0 + uRn)) * e.ih2;
+    }
+}
+
+// Rows of a thread's outputs whose epilogue loads are issued together (of
+// n): the residual's stencil reads several values per element, so two rows
+// (four elements) at a time keep them in registers.
+template <int EPI> __host__ __device__ constexpr int epi_rows(int n)
+{
+    return (EPI == EPI_RESID || EPI == EPI_RESID_DD) ? 2 : n;
+}
+
+template <int EPI>
+__device__ inline void epi_apply(const EpiArgs &e, int i, int p, double acc)
+{
+    epi_put<EPI>(e, i, p, epi_pre<EPI>(e, i, p), acc);
 }
 
 // Kernel parameters (passed by value).
@@ -1136,16 +1217,28 @@ __global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
     }
     dft_reg<T, R, SIGN>(v, tw, a.Ltw);
     const int base = (j / a.Ns) * a.Ns * R + jm;
+    if constexpr (DST == FD_CPLX) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int tau = base + r * a.Ns;
-        if constexpr (DST == FD_CPLX) {
-            gview_rw<C>(a.dst)[(long)tau * a.Q + q] = v[r];
-        } else {
-            if (tau < a.M) {
-                const int c = a.c0 + 2 * q;
-                if (c < a.P) epi_apply<EPI>(a.ea, tau, c, (double)v[r].x * a.scale);
-                if (c + 1 < a.P) epi_apply<EPI>(a.ea, tau, c + 1, (double)v[r].y * a.scale);
+        for (int r = 0; r < R; ++r) gview_rw<C>(a.dst)[(long)(base + r * a.Ns) * a.Q + q] = v[r];
+    } else {
+        // the epilogue in groups of rows: their loads, then their stores
+        const int c = a.c0 + 2 * q;
+        constexpr int G8 = epi_rows<EPI>(R < 8 ? R : 8);
+#pragma unroll
+        for (int r0 = 0; r0 < R; r0 += G8) {
+            double pre[G8][2];
+#pragma unroll
+            for (int r = 0; r < G8; ++r) {   // at clamped indices: no load behind a branch
+                const int tau = min(base + (r0 + r) * a.Ns, a.M - 1);
+                pre[r][0] = epi_pre<EPI>(a.ea, tau, min(c, a.P - 1));
+                pre[r][1] = epi_pre<EPI>(a.ea, tau, min(c + 1, a.P - 1));
+            }
+#pragma unroll
+            for (int r = 0; r < G8; ++r) {
+                const int tau = base + (r0 + r) * a.Ns;
+                if (tau >= a.M) continue;
+                if (c < a.P) epi_put<EPI>(a.ea, tau, c, pre[r][0], (double)v[r0 + r].x * a.scale);
+                if (c + 1 < a.P) epi_put<EPI>(a.ea, tau, c + 1, pre[r][1], (double)v[r0 + r].y * a.scale);
             }
         }
     }
@@ -1218,16 +1311,49 @@ __global__ __launch_bounds__(256) void k_fft_lds(FftPass a)
         for (int r2 = 0; r2 < R2; ++r2) v[r2] = sh[(k1 * R2 + r2) * NC + c];
         dft_reg<T, R2, SIGN>(v, tw, a.Ltw);
         if (q >= a.Q) continue;
+        if constexpr (DST == FD_CPLX) {
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) {
-            const int tau = base + (k1 + R1 * k2) * a.Ns;
-            if constexpr (DST == FD_CPLX) {
-                gview_rw<C>(a.dst)[(long)tau * a.Q + q] = v[k2];
-            } else {
-                if (tau < a.M) {
-                    const int cc = a.c0 + 2 * q;
-                    if (cc < a.P) epi_apply<EPI>(a.ea, tau, cc, (double)v[k2].x * a.scale);
-                    if (cc + 1 < a.P) epi_apply<EPI>(a.ea, tau, cc + 1, (double)v[k2].y * a.scale);
+            for (int k2 = 0; k2 < R2; ++k2)
+                gview_rw<C>(a.dst)[(long)(base + (k1 + R1 * k2) * a.Ns) * a.Q + q] = v[k2];
+        } else {
+            // the epilogue in groups of rows: their loads, then their stores
+            const int cc = a.c0 + 2 * q;
+            constexpr int CH = epi_rows<EPI>(R2);
+            if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
+                if (a.ea.dims == 1) {   // cc < P; cc + 1 may be P
+#pragma unroll
+                    for (int k0 = 0; k0 < R2; k0 += CH) {
+                        double pre[CH][2];
+#pragma unroll
+                        for (int k = 0; k < CH; ++k)
+                            resid_pre_pair_1d<EPI == EPI_RESID_DD>(
+                                a.ea, min(base + (k1 + R1 * (k0 + k)) * a.Ns, a.M - 1), cc, pre[k][0], pre[k][1]);
+#pragma unroll
+                        for (int k = 0; k < CH; ++k) {
+                            const int tau = base + (k1 + R1 * (k0 + k)) * a.Ns;
+                            if (tau >= a.M) continue;
+                            epi_put<EPI>(a.ea, tau, cc, pre[k][0], (double)v[k0 + k].x * a.scale);
+                            if (cc + 1 < a.P) epi_put<EPI>(a.ea, tau, cc + 1, pre[k][1], (double)v[k0 + k].y * a.scale);
+                        }
+                    }
+                    continue;
+                }
+            }
+#pragma unroll
+            for (int k0 = 0; k0 < R2; k0 += CH) {
+                double pre[CH][2];
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {   // at clamped indices: no load behind a branch
+                    const int tau = min(base + (k1 + R1 * (k0 + k)) * a.Ns, a.M - 1);
+                    pre[k][0] = epi_pre<EPI>(a.ea, tau, min(cc, a.P - 1));
+                    pre[k][1] = epi_pre<EPI>(a.ea, tau, min(cc + 1, a.P - 1));
+                }
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const int tau = base + (k1 + R1 * (k0 + k)) * a.Ns;
+                    if (tau >= a.M) continue;
+                    if (cc < a.P) epi_put<EPI>(a.ea, tau, cc, pre[k][0], (double)v[k0 + k].x * a.scale);
+                    if (cc + 1 < a.P) epi_put<EPI>(a.ea, tau, cc + 1, pre[k][1], (double)v[k0 + k].y * a.scale);
                 }
             }
         }
@@ -1469,6 +1595,7 @@ static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
                 case EPI_SCATTER_ADD: launch_fft_last<T, EPI_SCATTER_ADD>(plan[i], p, s); break;
                 case EPI_SCATTER_DIAG: launch_fft_last<T, EPI_SCATTER_DIAG>(plan[i], p, s); break;
                 case EPI_RESID: launch_fft_last<T, EPI_RESID>(plan[i], p, s); break;
+                case EPI_RESID_DD: launch_fft_last<T, EPI_RESID_DD>(plan[i], p, s); break;
                 default: return hipErrorInvalidValue;
                 }
             }
