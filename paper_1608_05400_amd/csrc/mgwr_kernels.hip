@@ -1250,13 +1250,14 @@ __global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
 // through LDS, then R2-point DFTs.  Rows of 16 column pairs (256 bytes in
 // FP64, 128 in FP32) are read and written whole; 16 pairs with one DFT per
 // thread measured faster than 8 (narrow rows) or 32 (two DFTs per thread).
-template <typename T> constexpr int fft_lds_cols() { return 16; }
+template <typename T> constexpr int fft_lds_cols() { return sizeof(T) == 4 ? 32 : 16; }
+template <typename T> constexpr int fft_lds_threads() { return 16 * fft_lds_cols<T>(); }
 
 template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
-__global__ __launch_bounds__(256) void k_fft_lds(FftPass a)
+__global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_lds(FftPass a)
 {
     using C = typename Cx<T>::v;
-    constexpr int R1 = 16, R = R1 * R2, NC = fft_lds_cols<T>();
+    constexpr int R1 = 16, R = R1 * R2, NC = fft_lds_cols<T>(), NT = fft_lds_threads<T>();
     __shared__ C sh[R * NC];
     const int nj = a.L / R;
     const int qblocks = (a.Q + NC - 1) / NC;
@@ -1266,7 +1267,7 @@ __global__ __launch_bounds__(256) void k_fft_lds(FftPass a)
     const int jm = j % a.Ns;
     const long pstep = (long)jm * (a.Ltw / (a.Ns * R));   // twiddles of the pass
     const int wstep = a.Ltw / R;                           // twiddles inside the R-point DFT
-    for (int job = threadIdx.x; job < R2 * NC; job += 256) {
+    for (int job = threadIdx.x; job < R2 * NC; job += NT) {
         const int c = job % NC, r2 = job / NC, q = q0 + c;
         C v[R1];
 #pragma unroll
@@ -1304,7 +1305,7 @@ __global__ __launch_bounds__(256) void k_fft_lds(FftPass a)
     }
     __syncthreads();
     const int base = (j / a.Ns) * a.Ns * R + jm;
-    for (int job = threadIdx.x; job < R1 * NC; job += 256) {
+    for (int job = threadIdx.x; job < R1 * NC; job += NT) {
         const int c = job % NC, k1 = job / NC, q = q0 + c;
         C v[R2];
 #pragma unroll
@@ -1369,11 +1370,11 @@ __global__ __launch_bounds__(256) void k_fft_lds(FftPass a)
 // of them from LDS and writes rows j' RI + t.  One read and one write of the
 // work array less per product than the two passes.
 template <typename T, int RI>
-__global__ __launch_bounds__(256) void k_fft_mid(FftPass a)
+__global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
 {
     using C = typename Cx<T>::v;
-    constexpr int R = 256, NC = fft_lds_cols<T>(), G = R / RI;
-    static_assert(16 * NC == 256, "one radix-256 job per thread");
+    constexpr int R = 256, NC = fft_lds_cols<T>(), NT = fft_lds_threads<T>(), G = R / RI;
+    static_assert(16 * NC == NT, "one radix-256 job per thread");
     __shared__ C sh[R * NC];
     const int nj = a.L / R;
     const int qblocks = (a.Q + NC - 1) / NC;
@@ -1417,7 +1418,7 @@ __global__ __launch_bounds__(256) void k_fft_mid(FftPass a)
     // inverse: group g takes x[s] = Y[g + G s], s < RI, and writes its DFT
     // X[t] to row (j + g nj) RI + t
     if constexpr (RI <= 16) {
-        for (int job = threadIdx.x; job < G * NC; job += 256) {
+        for (int job = threadIdx.x; job < G * NC; job += NT) {
             const int c = job % NC, g = job / NC, q = q0 + c;
             C v[RI];
 #pragma unroll
@@ -1433,7 +1434,7 @@ __global__ __launch_bounds__(256) void k_fft_mid(FftPass a)
         // inner twiddles, then RI2-point DFTs giving X[k1 + 16 k2]
         constexpr int RI2 = RI / 16;
         const int wi = a.Ltw / RI;
-        for (int job = threadIdx.x; job < G * RI2 * NC; job += 256) {
+        for (int job = threadIdx.x; job < G * RI2 * NC; job += NT) {
             const int c = job % NC, s2 = (job / NC) % RI2, g = job / (NC * RI2);
             C v[16];
 #pragma unroll
@@ -1447,7 +1448,7 @@ __global__ __launch_bounds__(256) void k_fft_mid(FftPass a)
             }
         }
         __syncthreads();
-        for (int job = threadIdx.x; job < G * 16 * NC; job += 256) {
+        for (int job = threadIdx.x; job < G * 16 * NC; job += NT) {
             const int c = job % NC, k1 = (job / NC) % 16, g = job / (NC * 16), q = q0 + c;
             C v[RI2];
 #pragma unroll
@@ -1464,17 +1465,17 @@ __global__ __launch_bounds__(256) void k_fft_mid(FftPass a)
 template <typename T>
 static void launch_fft_mid(int RI, const FftPass &p, hipStream_t s)
 {
-    constexpr int NC = fft_lds_cols<T>();
+    constexpr int NC = fft_lds_cols<T>(), NT = fft_lds_threads<T>();
     const dim3 grid((unsigned)((long)((p.Q + NC - 1) / NC) * (p.L / 256)));
     switch (RI) {
-    case 2: hipLaunchKernelGGL((k_fft_mid<T, 2>), grid, dim3(256), 0, s, p); break;
-    case 4: hipLaunchKernelGGL((k_fft_mid<T, 4>), grid, dim3(256), 0, s, p); break;
-    case 8: hipLaunchKernelGGL((k_fft_mid<T, 8>), grid, dim3(256), 0, s, p); break;
-    case 16: hipLaunchKernelGGL((k_fft_mid<T, 16>), grid, dim3(256), 0, s, p); break;
-    case 32: hipLaunchKernelGGL((k_fft_mid<T, 32>), grid, dim3(256), 0, s, p); break;
-    case 64: hipLaunchKernelGGL((k_fft_mid<T, 64>), grid, dim3(256), 0, s, p); break;
-    case 128: hipLaunchKernelGGL((k_fft_mid<T, 128>), grid, dim3(256), 0, s, p); break;
-    default: hipLaunchKernelGGL((k_fft_mid<T, 256>), grid, dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_fft_mid<T, 2>), grid, dim3(NT), 0, s, p); break;
+    case 4: hipLaunchKernelGGL((k_fft_mid<T, 4>), grid, dim3(NT), 0, s, p); break;
+    case 8: hipLaunchKernelGGL((k_fft_mid<T, 8>), grid, dim3(NT), 0, s, p); break;
+    case 16: hipLaunchKernelGGL((k_fft_mid<T, 16>), grid, dim3(NT), 0, s, p); break;
+    case 32: hipLaunchKernelGGL((k_fft_mid<T, 32>), grid, dim3(NT), 0, s, p); break;
+    case 64: hipLaunchKernelGGL((k_fft_mid<T, 64>), grid, dim3(NT), 0, s, p); break;
+    case 128: hipLaunchKernelGGL((k_fft_mid<T, 128>), grid, dim3(NT), 0, s, p); break;
+    default: hipLaunchKernelGGL((k_fft_mid<T, 256>), grid, dim3(NT), 0, s, p); break;
     }
 }
 
@@ -1501,9 +1502,9 @@ static std::vector<int> fft_plan(int L)
 template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
 static void launch_fft_lds(const FftPass &p, hipStream_t s)
 {
-    constexpr int R = 16 * R2, NC = fft_lds_cols<T>();
+    constexpr int R = 16 * R2, NC = fft_lds_cols<T>(), NT = fft_lds_threads<T>();
     const long blocks = (long)((p.Q + NC - 1) / NC) * (p.L / R);
-    hipLaunchKernelGGL((k_fft_lds<T, TIN, R2, SIGN, SRC, DST, EPI>), dim3((unsigned)blocks), dim3(256), 0, s, p);
+    hipLaunchKernelGGL((k_fft_lds<T, TIN, R2, SIGN, SRC, DST, EPI>), dim3((unsigned)blocks), dim3(NT), 0, s, p);
 }
 
 template <typename T, typename TIN, int SIGN, int SRC, int DST, int EPI>
