@@ -1143,11 +1143,57 @@ struct FftPass {
 enum FftSrc { FS_REAL = 0, FS_CPLX = 1, FS_SPEC = 2 };
 enum FftDst { FD_CPLX = 0, FD_EPI = 1 };
 
+// cos and sin of 2 pi i / 32, i < 32, at compile time: Taylor series on
+// [0, pi/4] (14 terms: the remainder is far below the rounding of a double)
+// and the symmetries of the circle for the other octants.
+constexpr double kPi = 3.14159265358979323846;
+constexpr double cx_sin_red(double x)
+{
+    double x2 = x * x, term = x, sum = x;
+    for (int n = 1; n < 14; ++n) {
+        term *= -x2 / ((2.0 * n) * (2.0 * n + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double cx_cos_red(double x)
+{
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int n = 1; n < 14; ++n) {
+        term *= -x2 / ((2.0 * n - 1.0) * (2.0 * n));
+        sum += term;
+    }
+    return sum;
+}
+struct Tw32 {
+    double c[32], s[32];
+    constexpr Tw32() : c(), s()
+    {
+        for (int i = 0; i < 32; ++i) {
+            const int qd = i / 8, r = i % 8;
+            double cr, sr;   // angle r pi / 16 in [0, pi / 2)
+            if (r <= 4) {
+                cr = cx_cos_red(r * kPi / 16);
+                sr = cx_sin_red(r * kPi / 16);
+            } else {
+                cr = cx_sin_red((8 - r) * kPi / 16);
+                sr = cx_cos_red((8 - r) * kPi / 16);
+            }
+            // rotate by qd quarter turns
+            const double cc[4] = {cr, -sr, -cr, sr}, ss[4] = {sr, cr, -sr, -cr};
+            c[i] = cc[qd];
+            s[i] = ss[qd];
+        }
+    }
+};
+constexpr Tw32 kTw32{};
+
 // R-point DFT (R a power of two <= 32) of v in natural order, in registers:
 // bit-reversal permutation (register renaming once unrolled), then radix-2
-// butterflies; SIGN -1 forward, +1 inverse (unnormalised).
+// butterflies with compile-time twiddles; SIGN -1 forward, +1 inverse
+// (unnormalised).
 template <typename T, int R, int SIGN>
-__device__ inline void dft_reg(typename Cx<T>::v (&v)[R], const GLOBAL typename Cx<T>::v *tw, int Ltw)
+__device__ inline void dft_reg(typename Cx<T>::v (&v)[R])
 {
     using C = typename Cx<T>::v;
     constexpr int LG = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : (R == 16) ? 4 : 5;
@@ -1166,8 +1212,8 @@ __device__ inline void dft_reg(typename Cx<T>::v (&v)[R], const GLOBAL typename 
     for (int m = 2; m <= R; m <<= 1) {
 #pragma unroll
         for (int t = 0; t < m / 2; ++t) {
-            C w = tw[(long)t * (Ltw / m)];
-            if (SIGN > 0) w.y = -w.y;
+            // exp(SIGN 2 pi i t / m)
+            C w = C{(T)kTw32.c[t * (32 / m)], (T)(SIGN * kTw32.s[t * (32 / m)])};
 #pragma unroll
             for (int k = 0; k < R; k += m) {
                 const C a = v[k + t], b = cmul(v[k + t + m / 2], w);
@@ -1215,7 +1261,7 @@ __global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
             v[r] = cmul(v[r], w);
         }
     }
-    dft_reg<T, R, SIGN>(v, tw, a.Ltw);
+    dft_reg<T, R, SIGN>(v);
     const int base = (j / a.Ns) * a.Ns * R + jm;
     if constexpr (DST == FD_CPLX) {
 #pragma unroll
@@ -1295,7 +1341,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_lds(FftPass a)
             }
             v[r1] = x;
         }
-        dft_reg<T, R1, SIGN>(v, tw, a.Ltw);
+        dft_reg<T, R1, SIGN>(v);
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) {
             C w = tw[(long)(r2 * k1) * wstep];
@@ -1310,7 +1356,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_lds(FftPass a)
         C v[R2];
 #pragma unroll
         for (int r2 = 0; r2 < R2; ++r2) v[r2] = sh[(k1 * R2 + r2) * NC + c];
-        dft_reg<T, R2, SIGN>(v, tw, a.Ltw);
+        dft_reg<T, R2, SIGN>(v);
         if (q >= a.Q) continue;
         if constexpr (DST == FD_CPLX) {
 #pragma unroll
@@ -1397,7 +1443,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
             if (r > 0) x = cmul(x, tw[pstep * r]);
             v[r1] = x;
         }
-        dft_reg<T, 16, -1>(v, tw, a.Ltw);
+        dft_reg<T, 16, -1>(v);
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) sh[(k1 * 16 + r2) * NC + c] = cmul(v[k1], tw[(long)(r2 * k1) * wstep]);
     }
@@ -1407,7 +1453,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
         C v[16];
 #pragma unroll
         for (int r2 = 0; r2 < 16; ++r2) v[r2] = sh[(k1 * 16 + r2) * NC + c];
-        dft_reg<T, 16, -1>(v, tw, a.Ltw);
+        dft_reg<T, 16, -1>(v);
 #pragma unroll
         for (int k2 = 0; k2 < 16; ++k2) v[k2] = cmul(v[k2], spec[j + (k1 + 16 * k2) * nj]);
         __syncthreads();
@@ -1423,7 +1469,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
             C v[RI];
 #pragma unroll
             for (int s2 = 0; s2 < RI; ++s2) v[s2] = sh[(g + G * s2) * NC + c];
-            dft_reg<T, RI, 1>(v, tw, a.Ltw);
+            dft_reg<T, RI, 1>(v);
             if (q >= a.Q) continue;
             const long row = (long)(j + g * nj) * RI;
 #pragma unroll
@@ -1439,7 +1485,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
             C v[16];
 #pragma unroll
             for (int s1 = 0; s1 < 16; ++s1) v[s1] = sh[(g + G * (RI2 * s1 + s2)) * NC + c];
-            dft_reg<T, 16, 1>(v, tw, a.Ltw);
+            dft_reg<T, 16, 1>(v);
 #pragma unroll
             for (int k1 = 0; k1 < 16; ++k1) {
                 C w = tw[(long)(s2 * k1) * wi];
@@ -1453,7 +1499,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
             C v[RI2];
 #pragma unroll
             for (int s2 = 0; s2 < RI2; ++s2) v[s2] = sh[(g + G * (RI2 * k1 + s2)) * NC + c];
-            dft_reg<T, RI2, 1>(v, tw, a.Ltw);
+            dft_reg<T, RI2, 1>(v);
             if (q >= a.Q) continue;
             const long row = (long)(j + g * nj) * RI;
 #pragma unroll

@@ -164,7 +164,7 @@ def test_fft32_product_matches_oracle_coefficients(B, M, P):
 # the plans (2 ... 256) that the fused middle kernel (last forward pass,
 # spectrum, first inverse pass) is built for, with one and two blocks of
 # column pairs.
-@pytest.mark.parametrize("M", [200, 300, 1000, 2048, 4096, 5000, 16384, 20000])
+@pytest.mark.parametrize("M", [200, 300, 1000, 2048, 4096, 5000, 9000, 12345, 16384, 20000])
 @pytest.mark.parametrize("P", [3, 33])
 def test_fft_product_every_plan(B, M, P):
     alpha = 0.55
