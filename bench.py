@@ -442,8 +442,14 @@ def main():
         "modes": results,
         "rooflines": rooflines,
     }
-    if "fp64" in results and primary != "fp64":
-        line["speedup_vs_fp64"] = p["value"] / results["fp64"]["value"]
+    # FP64 modes compared with the primary one; a mode that stops short of
+    # the tolerance (plain FP64 stagnates at its rounding floor) is flagged:
+    # its rate is not to the same accuracy
+    for m in ("fp64", "fp64r"):
+        if m in results and primary != m:
+            line["speedup_vs_" + m] = p["value"] / results[m]["value"]
+            st = results[m]["status"]   # per problem, or counts per status
+            line[m + "_reaches_tol"] = all(x == "ok" for x in st) if isinstance(st, list) else set(st) == {"ok"}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)

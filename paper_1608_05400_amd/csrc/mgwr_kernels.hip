@@ -1140,6 +1140,8 @@ struct FftPass {
     double scale;          // 1 / L (last inverse pass)
     EpiArgs ea;
 };
+// The work arrays are read once and written once per pass: their loads and
+// stores are nontemporal (measured a few per cent faster).
 enum FftSrc { FS_REAL = 0, FS_CPLX = 1, FS_SPEC = 2 };
 enum FftDst { FD_CPLX = 0, FD_EPI = 1 };
 
@@ -1246,7 +1248,7 @@ __global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
             }
             v[r] = C{re, im};
         } else {
-            v[r] = gview<C>(a.src)[(long)tau * a.Q + q];
+            v[r] = __builtin_nontemporal_load(&gview<C>(a.src)[(long)tau * a.Q + q]);
             if constexpr (SRC == FS_SPEC) v[r] = cmul(v[r], gview<C>(a.spec)[tau]);
         }
     }
@@ -1265,7 +1267,7 @@ __global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
     const int base = (j / a.Ns) * a.Ns * R + jm;
     if constexpr (DST == FD_CPLX) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) gview_rw<C>(a.dst)[(long)(base + r * a.Ns) * a.Q + q] = v[r];
+        for (int r = 0; r < R; ++r) __builtin_nontemporal_store(v[r], &gview_rw<C>(a.dst)[(long)(base + r * a.Ns) * a.Q + q]);
     } else {
         // the epilogue in groups of rows: their loads, then their stores
         const int c = a.c0 + 2 * q;
@@ -1330,7 +1332,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_lds(FftPass a)
                     }
                     x = C{re, im};
                 } else {
-                    x = gview<C>(a.src)[(long)tau * a.Q + q];
+                    x = __builtin_nontemporal_load(&gview<C>(a.src)[(long)tau * a.Q + q]);
                     if constexpr (SRC == FS_SPEC) x = cmul(x, gview<C>(a.spec)[tau]);
                 }
             }
@@ -1361,7 +1363,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_lds(FftPass a)
         if constexpr (DST == FD_CPLX) {
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2)
-                gview_rw<C>(a.dst)[(long)(base + (k1 + R1 * k2) * a.Ns) * a.Q + q] = v[k2];
+                __builtin_nontemporal_store(v[k2], &gview_rw<C>(a.dst)[(long)(base + (k1 + R1 * k2) * a.Ns) * a.Q + q]);
         } else {
             // the epilogue in groups of rows: their loads, then their stores
             const int cc = a.c0 + 2 * q;
@@ -1439,7 +1441,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
         for (int r1 = 0; r1 < 16; ++r1) {
             const int r = 16 * r1 + r2;
             C x = C{0, 0};
-            if (q < a.Q) x = src[(long)(j + r * nj) * a.Q + q];
+            if (q < a.Q) x = __builtin_nontemporal_load(&src[(long)(j + r * nj) * a.Q + q]);
             if (r > 0) x = cmul(x, tw[pstep * r]);
             v[r1] = x;
         }
@@ -1473,7 +1475,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
             if (q >= a.Q) continue;
             const long row = (long)(j + g * nj) * RI;
 #pragma unroll
-            for (int t = 0; t < RI; ++t) dst[(row + t) * a.Q + q] = v[t];
+            for (int t = 0; t < RI; ++t) __builtin_nontemporal_store(v[t], &dst[(row + t) * a.Q + q]);
         }
     } else {
         // RI = 16 x RI2: 16-point DFTs over s = RI2 s1 + s2 (in place), the
@@ -1503,7 +1505,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
             if (q >= a.Q) continue;
             const long row = (long)(j + g * nj) * RI;
 #pragma unroll
-            for (int k2 = 0; k2 < RI2; ++k2) dst[(row + k1 + 16 * k2) * a.Q + q] = v[k2];
+            for (int k2 = 0; k2 < RI2; ++k2) __builtin_nontemporal_store(v[k2], &dst[(row + k1 + 16 * k2) * a.Q + q]);
         }
     }
 }
