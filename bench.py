@@ -251,7 +251,8 @@ def fft_pass_bytes(r):
 def roofline_of(records, steps):
     """Dominant Toeplitz-product kernel (largest total time) and its achieved
     rate from the per-launch HIP events: algorithmic FLOP/s against the matrix
-    cores for the dense kernels, bytes/s against HBM for the FFT route."""
+    cores for the dense kernels, bytes/s against HBM for the FFT route (its
+    finest-level launches)."""
     if not records:
         return None
     from paper_1608_05400_amd import binding as B
@@ -265,12 +266,20 @@ def roofline_of(records, steps):
     d = by[kid]
     mode = (kid >> 4) & 15
     if (kid >> 8) == 4:
+        # the FFT route's launches of the finest level (the largest products
+        # of the class; the coarser levels' are the same kernels on fewer columns)
         rs = [r for r in records if r["kernel"] == kid]
+        top = max(r["level"] for r in rs)
+        rs = [r for r in rs if r["level"] == top]
+        ms = sum(r["ms"] for r in rs)
         nbytes = sum(fft_pass_bytes(r) for r in rs)
-        achieved = nbytes / (d["ms"] * 1e-3) / 1e9
+        achieved = nbytes / (ms * 1e-3) / 1e9
         out = {
             "bound": "hbm",
             "kernel": B.kernel_name(kid),
+            "level": top,
+            "P": sorted(set(r["P"] for r in rs)),
+            "M": rs[0]["M"],
             "dtype": "f64" if mode == 0 else "f32",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
@@ -278,13 +287,13 @@ def roofline_of(records, steps):
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
             "algorithmic_bytes": nbytes / len(rs),
-            "launches_per_step": d["n"] // max(1, steps),
-            "avg_launch_ms": round(d["ms"] / d["n"], 4),
-            "dense_equivalent_tflops": round(d["flops"] / (d["ms"] * 1e-3) / 1e12, 1),
+            "launches_per_step": len(rs) // max(1, steps),
+            "avg_launch_ms": round(ms / len(rs), 4),
+            "dense_equivalent_tflops": round(sum(r["flops"] for r in rs) / (ms * 1e-3) / 1e12, 1),
             "share_of_product_time": round(d["ms"] / sum(v["ms"] for v in by.values()), 3),
         }
         tr = measured_traffic(out["kernel"])
-        if tr:
+        if tr and tr.get("level") == top and tr.get("P") == out["P"]:
             out["traffic"] = tr["bytes_per_launch"]
             out["traffic_unit"] = "bytes/launch (FETCH_SIZE x %g + WRITE_SIZE x %g)" % (tr["fetch_factor"],
                                                                                        tr["write_factor"])
