@@ -236,7 +236,8 @@ int mgwr_batch_destroy(mgwr_batch_t b);
  * 4 = add (D&C base block, history part), 5 = colour scatter of the diagonal
  * term plus the history part (smoother, FFT route), 6 = residual (FFT route:
  * the stencil part minus the product, written as the residual), 7 = the
- * same for a double-double iterate.
+ * same for a double-double iterate, 8 = the residual at one colour's points
+ * (inner cycles of the refinement after pre-smoothing).
  * A record covers one launch, possibly over several problems: M and K are
  * those of the first, P the sum of the columns, flops the sum of the
  * multiply-adds that are not structurally zero, times 2.  ms covers the

@@ -853,9 +853,34 @@ int sweep(Exec &ex, const std::vector<Task> &ts)
     return MGWR_OK;
 }
 
+// Whether the residual of a task's level takes the FFT route.
+bool residual_fft(const Task &t)
+{
+    const int mode = level_mode(*t.H, t.H->h->lv[t.lev].P);
+    return mode == GM_F64 ? fft_for(t.H->h, t.lev) : fft_for(t.H->h, t.lev, mode);
+}
+
+// Whether the residual before restriction is computed at one colour only.
+// After a red-black sweep the second colour's line solves have made its
+// residual zero up to their rounding, so with pre-smoothing the inner cycles
+// of the refinement compute only the first colour's residual, on the FFT
+// route, which reads those columns directly; the restriction then reads that
+// colour alone.  Not in plain FP64 cycles: the FFT route's rounding is
+// relative to the largest terms of a time line, so at the early time levels
+// the line solves' residual is not small against the local values, and
+// Algorithm 1 on the iterate itself has no outer FP64 residual to correct
+// for leaving it out (measured: error 5e-10 against 4e-12 on the 1D
+// N = 4095, M = 16384 problem).
+bool colour_residual(const Task &t)
+{
+    return t.H->prec != MGWR_FP64 && t.H->h->opt.nu1 >= 1 && residual_fft(t);
+}
+
 // out = f + c d g - T_M u - A_h u on each task's level: the Toeplitz product
 // (all of T_M u in FP64, its history part otherwise) stored into out, then the
-// stencil part and the diagonal r_1 u applied by a bandwidth kernel.
+// stencil part and the diagonal r_1 u applied by a bandwidth kernel (on the
+// FFT route by the product's last pass; at the first colour's points only
+// where colour_residual holds).
 int level_residual(Exec &ex, const std::vector<Task> &ts)
 {
     std::vector<OperandArgs> ops;
@@ -894,6 +919,13 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
             a.epi = EPI_RESID;
             a.ea.F = t.H->f[t.lev]; a.ea.U = t.H->u[t.lev]; a.ea.lo = nullptr; a.ea.cd = h->cd;
             a.ea.g = fine ? t.H->g : nullptr; a.ea.ih2 = L.ih2; a.ea.diag = diag;
+            if (colour_residual(t)) {
+                const int colour = h->opt.first_colour;
+                a.epi = EPI_RESID_C;
+                a.P = L.Pc[colour];
+                a.b_colour = colour;
+                a.ea.colour = colour;
+            }
             prods.push_back(a);
             continue;
         }
@@ -938,7 +970,8 @@ int cycle(Exec &ex, const std::vector<Task> &ts)
     std::vector<FillArgs> zs;
     for (const Task &t : fine) {
         mgwr_ctx *h = t.H->h;
-        rs.push_back(XferArgs{0, h->dims, h->lv[t.lev].n, h->M, t.H->rscratch, t.H->f[t.lev - 1]});
+        rs.push_back(XferArgs{0, h->dims, h->lv[t.lev].n, h->M, t.H->rscratch, t.H->f[t.lev - 1],
+                              colour_residual(t) ? 1 - h->opt.first_colour : -1});
         zs.push_back(FillArgs{h->M, h->lv[t.lev - 1].P, nullptr, nullptr, t.H->u[t.lev - 1], 0});
         pr.push_back(XferArgs{1, h->dims, h->lv[t.lev - 1].n, h->M, t.H->u[t.lev - 1], t.H->u[t.lev]});
     }

@@ -52,7 +52,10 @@ enum EpiKind {
                          //   diagonal term of the line solve plus its history product)
     EPI_RESID = 6,       // out[i][p] = (F + cd g - diag U - A_h U) - acc at (i, p)  (the
                          //   residual; FFT route only)
-    EPI_RESID_DD = 7     // the same with the iterate U + lo (double-double)
+    EPI_RESID_DD = 7,    // the same with the iterate U + lo (double-double)
+    EPI_RESID_C = 8      // EPI_RESID at the points of one colour: product column p is
+                         //   point colour_point(p) (the other colour's residual is zero
+                         //   after a red-black sweep and is neither computed nor written)
 };
 
 struct EpiArgs {
@@ -101,6 +104,9 @@ struct GemmArgs {
     const void *fft_tw = nullptr;    // complex [fft_Ltw]: exp(-2 pi i k / fft_Ltw)
     int fft_L = 0, fft_Ltw = 0;      // powers of two, 64 <= fft_L <= fft_Ltw
     bool fft_b64 = true;
+    // b_colour >= 0: product column j is point colour_point(ea.dims, ea.n,
+    // b_colour, j) of B's rows (FFT route)
+    int b_colour = -1;
     void *fft_buf0 = nullptr, *fft_buf1 = nullptr;  // work arrays, fft_buf_cap bytes each:
     size_t fft_buf_cap = 0;          // columns are transformed in chunks of 2 fft_buf_cap / (16 fft_L)
 };
@@ -193,6 +199,7 @@ struct XferArgs {
     int dir, dims, n, M;
     const double *src;
     double *dst;
+    int zero_colour = -1;   // restriction: src holds only the other colour (this one is zero)
 };
 // u[k][p] = scaled ? cd[k] g[p] : g[p]  (g == nullptr: 0)
 struct FillArgs {

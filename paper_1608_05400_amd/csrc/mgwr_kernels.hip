@@ -125,10 +125,11 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
         return out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)];
     } else if constexpr (EPI == EPI_SCATTER_DIAG) {
         return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + p];
-    } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
+    } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C) {
         // the stencil part of the residual (as OpPost), fused; no load
         // behind a branch (without g, F stands in for it and is not used;
         // diag = 0 subtracts an exact zero)
+        if constexpr (EPI == EPI_RESID_C) p = colour_point(e.dims, e.n, e.colour, p);
         const long k = (long)i * e.ldo;
         const GLOBAL double *Uk = gview<double>(e.U) + k;
         const double gv = gview<double>(e.g ? e.g : e.F)[p], cdv = gview<double>(e.cd)[i];
@@ -164,30 +165,36 @@ __device__ inline void epi_put(const EpiArgs &e, int i, int p, double pre, doubl
         out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = pre + acc;
     } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
         out[(long)i * e.ldo + p] = pre - acc;
+    } else if constexpr (EPI == EPI_RESID_C) {
+        out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = pre - acc;
     }
 }
 
-// Residual epilogue values (as epi_pre) of the adjacent columns p and p + 1
-// of row i on a 1D level, the second only meaningful when p + 1 < n: the
-// neighbour values the two share are loaded once, at clamped indices.
-template <bool DD>
+// Residual epilogue values (as epi_pre) of points p and p + S of row i on a
+// 1D level (S = 1: adjacent points; S = 2: adjacent points of one colour),
+// the second only meaningful when p + S < n: the neighbour values the two
+// share are loaded once, at clamped indices.
+template <bool DD, int S>
 __device__ inline void resid_pre_pair_1d(const EpiArgs &e, int i, int p, double &r0, double &r1)
 {
     const int n = e.n;
     const long k = (long)i * e.ldo;
-    const int pl = p > 0 ? p - 1 : p, p1 = min(p + 1, n - 1), p2 = min(p + 2, n - 1);
+    const int pl = p > 0 ? p - 1 : p, p1 = min(p + S, n - 1), p2 = min(p + S + 1, n - 1), pm = min(p + 1, n - 1);
     const GLOBAL double *Uk = gview<double>(e.U) + k, *Fk = gview<double>(e.F) + k;
     const GLOBAL double *g = gview<double>(e.g ? e.g : e.F);
     double uL = Uk[pl], u0 = Uk[p], u1 = Uk[p1], uR = Uk[p2];
+    const double uM = (S == 2) ? Uk[pm] : u1;   // right of p (and left of p + 2)
     const double f0 = Fk[p], f1 = Fk[p1], g0 = g[p], g1 = g[p1], cdv = gview<double>(e.cd)[i];
-    double lL = 0.0, l0 = 0.0, l1 = 0.0, lR = 0.0;
+    double lL = 0.0, l0 = 0.0, l1 = 0.0, lR = 0.0, lM = 0.0;
     if constexpr (DD) {
         const GLOBAL double *Lk = gview<double>(e.lo) + k;
         lL = Lk[pl]; l0 = Lk[p]; l1 = Lk[p1]; lR = Lk[p2];
+        lM = (S == 2) ? Lk[pm] : l1;
     }
     if (p == 0) uL = lL = 0.0;
-    const double u1n = (p + 1 < n) ? u1 : 0.0, uRn = (p + 2 < n) ? uR : 0.0;
-    const double l1n = (p + 1 < n) ? l1 : 0.0, lRn = (p + 2 < n) ? lR : 0.0;
+    // neighbours: right of p, left of p + S, right of p + S (zero outside)
+    const double ur0 = (p + 1 < n) ? uM : 0.0, ul1 = (S == 1) ? u0 : uM, ur1 = (p + S + 1 < n) ? uR : 0.0;
+    const double lr0 = (p + 1 < n) ? lM : 0.0, ll1 = (S == 1) ? l0 : lM, lr1 = (p + S + 1 < n) ? lR : 0.0;
     double rhs0 = f0, rhs1 = f1;
     if (e.g) {
         rhs0 += cdv * g0;
@@ -200,14 +207,14 @@ __device__ inline void resid_pre_pair_1d(const EpiArgs &e, int i, int p, double 
         double s0 = 2.0 * u0, s1 = 2.0 * u1, e0, e1, a0 = 0.0, a1 = 0.0;
         double lo0 = 2.0 * l0, lo1 = 2.0 * l1;
         two_sum(s0, -uL, s0, e0); a0 += e0; lo0 -= lL;
-        two_sum(s0, -u1n, s0, e0); a0 += e0; lo0 -= l1n;
-        two_sum(s1, -u0, s1, e1); a1 += e1; lo1 -= l0;
-        two_sum(s1, -uRn, s1, e1); a1 += e1; lo1 -= lRn;
+        two_sum(s0, -ur0, s0, e0); a0 += e0; lo0 -= lr0;
+        two_sum(s1, -ul1, s1, e1); a1 += e1; lo1 -= ll1;
+        two_sum(s1, -ur1, s1, e1); a1 += e1; lo1 -= lr1;
         r0 = (rhs0 - s0 * e.ih2) - (a0 + lo0) * e.ih2;
         r1 = (rhs1 - s1 * e.ih2) - (a1 + lo1) * e.ih2;
     } else {
-        r0 = rhs0 - (2.0 * u0 - (uL + u1n)) * e.ih2;
-        r1 = rhs1 - (2.0 * u1 - (u0 + uRn)) * e.ih2;
+        r0 = rhs0 - (2.0 * u0 - (uL + ur0)) * e.ih2;
+        r1 = rhs1 - (2.0 * u1 - (ul1 + ur1)) * e.ih2;
     }
 }
 
@@ -216,7 +223,7 @@ __device__ inline void resid_pre_pair_1d(const EpiArgs &e, int i, int p, double 
 // (four elements) at a time keep them in registers.
 template <int EPI> __host__ __device__ constexpr int epi_rows(int n)
 {
-    return (EPI == EPI_RESID || EPI == EPI_RESID_DD) ? 2 : n;
+    return (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C) ? 2 : n;
 }
 
 template <int EPI>
@@ -1129,6 +1136,7 @@ template <typename C> __device__ inline C cmul(C a, C b)
 
 struct FftPass {
     int L, Q, Ns;          // length, column pairs of this chunk, length of the sub-transforms done
+    int b_colour;          // >= 0: product column j reads B's point colour_point(j)
     int M, K, P, c0;       // output rows, input rows, columns, first column of this chunk
     const void *src;       // complex [L][Q]
     void *dst;             // complex [L][Q]
@@ -1143,6 +1151,12 @@ struct FftPass {
 // The work arrays are read once and written once per pass: their loads and
 // stores are nontemporal (measured a few per cent faster).
 enum FftSrc { FS_REAL = 0, FS_CPLX = 1, FS_SPEC = 2 };
+
+// Column of B read for product column j (the colour's points when b_colour >= 0).
+__device__ inline int fft_bcol(const FftPass &a, int j)
+{
+    return a.b_colour < 0 ? j : colour_point(a.ea.dims, a.ea.n, a.b_colour, j);
+}
 enum FftDst { FD_CPLX = 0, FD_EPI = 1 };
 
 // cos and sin of 2 pi i / 32, i < 32, at compile time: Taylor series on
@@ -1242,9 +1256,9 @@ __global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
         if constexpr (SRC == FS_REAL) {
             T re = 0, im = 0;
             if (tau < a.K) {
-                const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb + a.c0;
-                if (a.c0 + 2 * q < a.P) re = (T)row[2 * q];
-                if (a.c0 + 2 * q + 1 < a.P) im = (T)row[2 * q + 1];
+                const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb;
+                if (a.c0 + 2 * q < a.P) re = (T)row[fft_bcol(a, a.c0 + 2 * q)];
+                if (a.c0 + 2 * q + 1 < a.P) im = (T)row[fft_bcol(a, a.c0 + 2 * q + 1)];
             }
             v[r] = C{re, im};
         } else {
@@ -1326,9 +1340,9 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_lds(FftPass a)
                 if constexpr (SRC == FS_REAL) {
                     T re = 0, im = 0;
                     if (tau < a.K) {
-                        const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb + a.c0;
-                        if (a.c0 + 2 * q < a.P) re = (T)row[2 * q];
-                        if (a.c0 + 2 * q + 1 < a.P) im = (T)row[2 * q + 1];
+                        const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb;
+                        if (a.c0 + 2 * q < a.P) re = (T)row[fft_bcol(a, a.c0 + 2 * q)];
+                        if (a.c0 + 2 * q + 1 < a.P) im = (T)row[fft_bcol(a, a.c0 + 2 * q + 1)];
                     }
                     x = C{re, im};
                 } else {
@@ -1368,15 +1382,17 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_lds(FftPass a)
             // the epilogue in groups of rows: their loads, then their stores
             const int cc = a.c0 + 2 * q;
             constexpr int CH = epi_rows<EPI>(R2);
-            if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
+            if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C) {
                 if (a.ea.dims == 1) {   // cc < P; cc + 1 may be P
+                    // first point of the pair: column cc, or the colour's point cc
+                    const int pt = (EPI == EPI_RESID_C) ? colour_point(1, a.ea.n, a.ea.colour, cc) : cc;
 #pragma unroll
                     for (int k0 = 0; k0 < R2; k0 += CH) {
                         double pre[CH][2];
 #pragma unroll
                         for (int k = 0; k < CH; ++k)
-                            resid_pre_pair_1d<EPI == EPI_RESID_DD>(
-                                a.ea, min(base + (k1 + R1 * (k0 + k)) * a.Ns, a.M - 1), cc, pre[k][0], pre[k][1]);
+                            resid_pre_pair_1d<EPI == EPI_RESID_DD, EPI == EPI_RESID_C ? 2 : 1>(
+                                a.ea, min(base + (k1 + R1 * (k0 + k)) * a.Ns, a.M - 1), pt, pre[k][0], pre[k][1]);
 #pragma unroll
                         for (int k = 0; k < CH; ++k) {
                             const int tau = base + (k1 + R1 * (k0 + k)) * a.Ns;
@@ -1600,7 +1616,7 @@ static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
         p.L = a.fft_L;
         p.Q = (int)std::min(qcap, (long)(a.P - c0 + 1) / 2);
         p.M = a.M; p.K = a.K; p.P = a.P; p.c0 = (int)c0;
-        p.B = a.B; p.ldb = a.ldb;
+        p.B = a.B; p.ldb = a.ldb; p.b_colour = a.b_colour;
         p.spec = a.fft_spec; p.tw = a.fft_tw; p.Ltw = a.fft_Ltw;
         p.scale = 1.0 / a.fft_L;
         p.ea = a.ea;
@@ -1645,6 +1661,7 @@ static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
                 case EPI_SCATTER_DIAG: launch_fft_last<T, EPI_SCATTER_DIAG>(plan[i], p, s); break;
                 case EPI_RESID: launch_fft_last<T, EPI_RESID>(plan[i], p, s); break;
                 case EPI_RESID_DD: launch_fft_last<T, EPI_RESID_DD>(plan[i], p, s); break;
+                case EPI_RESID_C: launch_fft_last<T, EPI_RESID_C>(plan[i], p, s); break;
                 default: return hipErrorInvalidValue;
                 }
             }
@@ -1831,16 +1848,26 @@ struct OpXfer {
             int k = (int)(e / Pc);
             long q = e - (long)k * Pc;
             const GLOBAL double *r = gview<double>(a.src) + (long)k * Pf;
+            // the coarse point is a colour-0 point of the fine grid, its
+            // edge neighbours colour 1, its corners (2D) colour 0; with
+            // zero_colour set, that colour's entries are zero and not read
             double v;
             if (a.dims == 1) {
                 int x = 2 * (int)q + 1;
-                v = 0.25 * (r[x - 1] + 2.0 * r[x] + r[x + 1]);
+                if (a.zero_colour == 1) v = 0.25 * (2.0 * r[x]);
+                else if (a.zero_colour == 0) v = 0.25 * (r[x - 1] + r[x + 1]);
+                else v = 0.25 * (r[x - 1] + 2.0 * r[x] + r[x + 1]);
             } else {
                 int I = (int)(q % nc), J = (int)(q / nc);
                 int x = 2 * I + 1, y = 2 * J + 1;
                 const GLOBAL double *r0 = r + (long)(y - 1) * nf, *r1 = r + (long)y * nf, *r2 = r + (long)(y + 1) * nf;
-                v = (r0[x - 1] + 2.0 * r0[x] + r0[x + 1] + 2.0 * (r1[x - 1] + 2.0 * r1[x] + r1[x + 1])
-                     + r2[x - 1] + 2.0 * r2[x] + r2[x + 1]) * (1.0 / 16.0);
+                if (a.zero_colour == 1)
+                    v = (r0[x - 1] + r0[x + 1] + 2.0 * (2.0 * r1[x]) + r2[x - 1] + r2[x + 1]) * (1.0 / 16.0);
+                else if (a.zero_colour == 0)
+                    v = (2.0 * r0[x] + 2.0 * (r1[x - 1] + r1[x + 1]) + 2.0 * r2[x]) * (1.0 / 16.0);
+                else
+                    v = (r0[x - 1] + 2.0 * r0[x] + r0[x + 1] + 2.0 * (r1[x - 1] + 2.0 * r1[x] + r1[x + 1])
+                         + r2[x - 1] + 2.0 * r2[x] + r2[x + 1]) * (1.0 / 16.0);
             }
             gview_rw<double>(a.dst)[e] = v;
         }

@@ -179,3 +179,41 @@ def test_fft_product_every_plan(B, M, P):
         C32 = host(s.toeplitz_apply(dev(X), which=-1, precision="fp32"))
     assert relmax(C, ref, scale) <= 1e-12
     assert relmax(C32, ref, scale) <= 1e-6
+
+
+@pytest.mark.parametrize("dims,N,M,alpha", [(1, 127, 200, 0.3), (2, 31, 64, 0.7), (1, 255, 600, 0.5), (2, 63, 520, 0.4)])
+@pytest.mark.parametrize("first", [0, 1])
+@pytest.mark.parametrize("nu", [(1, 1), (0, 1), (2, 1)])
+def test_fft_cycle_matches_oracle(B, dims, N, M, alpha, first, nu):
+    """One plain FP64 cycle with every product on the FFT route, both colour
+    orders and with and without pre-smoothing."""
+    rng = np.random.default_rng(N + M + first)
+    shape = (M, N) if dims == 1 else (M, N, N)
+    f, u, g = rng.standard_normal(shape), rng.standard_normal(shape), rng.standard_normal(shape[1:])
+    ref = oracle.vcycle(dims, N, M, alpha, f, u, g=g, nu1=nu[0], nu2=nu[1], first=first)
+    with B.Solver(N, M, alpha, dims=dims, nu1=nu[0], nu2=nu[1], first_colour=first, fft=2) as s:
+        U = dev(u)
+        s.vcycle(dev(f), U, g=dev(g))
+        U = host(U)
+    assert relmax(U, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64r", 1e-10), ("bf16x3", 1e-8)])
+@pytest.mark.parametrize("first", [0, 1])
+@pytest.mark.parametrize("dims,N,M,alpha", [(1, 255, 1500, 0.45), (2, 63, 600, 0.6)])
+def test_fft_refinement_with_colour_residual(B, prec, tol, first, dims, N, M, alpha):
+    """Refinement solves whose inner cycles compute the residual before
+    restriction at the first colour only (FFT route, pre-smoothing): the
+    outer FP64 residual brings them to the exact discrete solution."""
+    if dims == 1:
+        w = W.random_modes_1d(N, M, alpha, seed=80 + first)
+    else:
+        w = W.manufactured_2d(N, M, alpha)
+    f = w.forcing()
+    ref = oracle.direct_solve(dims, w.N, w.M, w.alpha, f)
+    with B.Solver(w.N, w.M, w.alpha, dims=dims, precision=prec, first_colour=first, fft=2) as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(dev(f), U, tol=1e-12)
+        U = host(U)
+    assert info["rc"] in (0, 2), info
+    assert relmax(U, ref) <= tol, (info, relmax(U, ref))
