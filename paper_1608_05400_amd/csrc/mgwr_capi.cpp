@@ -676,6 +676,7 @@ struct Hier {
 struct Task {
     Hier *H;
     int lev;
+    bool zero = false;   // the level's iterate is zero on entry to the cycle
 };
 
 int level_mode(const Hier &H, long cols)
@@ -808,25 +809,40 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
         GemmArgs a = gemm_base(h, mode);
         a.M = h->M; a.P = Pc; a.K = h->M; a.off = 0;
         a.ea.out = t.H->u[t.lev]; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n; a.ea.colour = colour;
-        if (mode == GM_F64) {
+        // On the FFT route, a zero iterate (first half-sweep of a level that
+        // starts from zero, no initial-condition term) makes the right-hand
+        // sides the colour's points of F: the products read them there and
+        // no panel is built.
+        const bool from_f = t.zero && !g;
+        auto rhs_panel = [&]() {
+            if (from_f) {
+                a.B = t.H->f[t.lev]; a.ldb = L.P; a.b_colour = colour;
+            } else {
+                rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd,
+                                      g, L.ih2, 0.0, h->panel64, nullptr, Pc});
+                a.B = h->panel64; a.ldb = Pc;
+            }
+        };
+        if (mode == GM_F64 && fft_for(h, t.lev)) {
+            a.coef = &L.inv; a.epi = EPI_SCATTER;
+            set_fft(h, a, L.spec_inv);
+            rhs_panel();
+        } else if (mode == GM_F64) {
             rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
                                   L.ih2, 0.0, h->panel64, nullptr, Pc});
             a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
-            if (fft_for(h, t.lev)) set_fft(h, a, L.spec_inv);
         } else if (fft_for(h, t.lev, mode) && h->c > kFft32MaxHist * L.sigma) {
-            rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
-                                  L.ih2, 0.0, h->panel64, nullptr, Pc});
-            a.mode = GM_F64; a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
+            a.mode = GM_F64; a.coef = &L.inv; a.epi = EPI_SCATTER;
             set_fft(h, a, L.spec_inv);
+            rhs_panel();
         } else if (fft_for(h, t.lev, mode)) {
             // FP64 right-hand sides; the FFT's first pass rounds them to FP32
             // and its last pass writes lambda_0 b + history into the colour's
             // points of U (one store, the diagonal term in FP64)
-            rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
-                                  L.ih2, 0.0, h->panel64, nullptr, Pc});
-            a.coef = &L.inv_h; a.epi = EPI_SCATTER_DIAG; a.B = h->panel64; a.ldb = Pc;
-            a.ea.b = h->panel64; a.ea.ldb_diag = Pc; a.ea.diag = L.lam0;
+            a.coef = &L.inv_h; a.epi = EPI_SCATTER_DIAG; a.ea.diag = L.lam0;
             set_fft32(h, a, L.spec32_inv_h, true);
+            rhs_panel();
+            a.ea.b = (const double *)a.B; a.ea.ldb_diag = a.ldb; a.ea.b_colour = a.b_colour;
         } else if (mode == GM_F32) {
             rhs.push_back(RhsArgs{1, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
                                   L.ih2, L.lam0, h->panel32, nullptr, Pc});
@@ -849,7 +865,10 @@ int sweep(Exec &ex, const std::vector<Task> &ts)
 {
     if (ts.empty()) return MGWR_OK;
     CHK(half_sweep(ex, ts, 0));
-    CHK(half_sweep(ex, ts, 1));
+    // after the first half-sweep no iterate is zero
+    std::vector<Task> ts1 = ts;
+    for (Task &t : ts1) t.zero = false;
+    CHK(half_sweep(ex, ts1, 1));
     return MGWR_OK;
 }
 
@@ -961,7 +980,10 @@ int cycle(Exec &ex, const std::vector<Task> &ts)
     for (int i = 0; i < nu1; ++i) {
         std::vector<Task> sel;
         for (const Task &t : ts)
-            if ((t.lev > 0 && i < t.H->h->opt.nu1) || (t.lev == 0 && i == 0)) sel.push_back(t);
+            if ((t.lev > 0 && i < t.H->h->opt.nu1) || (t.lev == 0 && i == 0)) {
+                sel.push_back(t);
+                if (i > 0) sel.back().zero = false;
+            }
         CHK(sweep(ex, sel));
     }
     if (fine.empty()) return MGWR_OK;
@@ -980,14 +1002,17 @@ int cycle(Exec &ex, const std::vector<Task> &ts)
     for (int k = 0; k < gam; ++k) {
         std::vector<Task> down;
         for (const Task &t : fine)
-            if (k < t.H->h->opt.gamma) down.push_back(Task{t.H, t.lev - 1});
+            if (k < t.H->h->opt.gamma) down.push_back(Task{t.H, t.lev - 1, true});
         CHK(cycle(ex, down));
     }
     HIPCHK(launch_xfer(pr, ex.st, ex.s));
     for (int i = 0; i < nu2; ++i) {
         std::vector<Task> sel;
         for (const Task &t : fine)
-            if (i < t.H->h->opt.nu2) sel.push_back(t);
+            if (i < t.H->h->opt.nu2) {
+                sel.push_back(t);
+                sel.back().zero = false;
+            }
         CHK(sweep(ex, sel));
     }
     return MGWR_OK;
@@ -1291,7 +1316,7 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
                     plain.push_back(Task{&Hp[i], top});
                 } else {
                     Level &L = h->lv.back();
-                    inner.push_back(Task{&Hi[i], top});
+                    inner.push_back(Task{&Hi[i], top, true});
                     zero.push_back(FillArgs{h->M, L.P, nullptr, nullptr, L.e, 0});
                     upd.push_back(DDArgs{(long)h->M * L.P, L.e, u[i], h->ulo});
                 }
@@ -1361,7 +1386,7 @@ int time_cycle(Runner &R, const std::vector<mgwr_ctx *> &hs, int prec, int reps,
         std::vector<FillArgs> zero;
         for (size_t i = 0; i < hs.size(); ++i) {
             Level &L = hs[i]->lv.back();
-            ts.push_back(Task{&H[i], (int)hs[i]->lv.size() - 1});
+            ts.push_back(Task{&H[i], (int)hs[i]->lv.size() - 1, true});
             zero.push_back(FillArgs{hs[i]->M, L.P, nullptr, nullptr, L.e, 0});
         }
         HIPCHK(launch_fill(zero, ex.st, ex.s));

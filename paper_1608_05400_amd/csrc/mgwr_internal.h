@@ -64,6 +64,7 @@ struct EpiArgs {
     int dims = 1, n = 1, colour = 0;   // grid of the level (points per dim) and colour
     const double *b = nullptr; // EPI_SCATTER_DIAG: right-hand sides [M][ldb_diag]
     long ldb_diag = 0;
+    int b_colour = -1;         // >= 0: column p of them is point colour_point(p) of b's rows
     double diag = 0.0;         // EPI_SCATTER_DIAG: first entry of the inverse column;
                                // EPI_RESID: coefficient of U (r_1 when acc is the history part)
     // EPI_RESID: the level's right-hand side F [M][P], iterate U (+ lo, its

@@ -124,7 +124,8 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
     } else if constexpr (EPI == EPI_SCATTER_ADD) {
         return out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)];
     } else if constexpr (EPI == EPI_SCATTER_DIAG) {
-        return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + p];
+        const int pb = e.b_colour < 0 ? p : colour_point(e.dims, e.n, e.b_colour, p);
+        return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + pb];
     } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C) {
         // the stencil part of the residual (as OpPost), fused; no load
         // behind a branch (without g, F stands in for it and is not used;
