@@ -1307,20 +1307,27 @@ __global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
     }
 }
 
-// A Stockham pass of radix R = 16 R2 (64, 128 or 256) by one block for C
+// A Stockham pass of radix R = 16 R2 (64, 128 or 256) by one block for NC
 // column pairs: the R-point DFT as two stages (Cooley-Tukey, R = 16 x R2):
 // 16-point DFTs over elements R2 apart in registers, twiddles, an exchange
-// through LDS, then R2-point DFTs.  Rows of 16 column pairs (256 bytes in
-// FP64, 128 in FP32) are read and written whole; 16 pairs with one DFT per
-// thread measured faster than 8 (narrow rows) or 32 (two DFTs per thread).
-template <typename T> constexpr int fft_lds_cols() { return sizeof(T) == 4 ? 32 : 16; }
-template <typename T> constexpr int fft_lds_threads() { return 16 * fft_lds_cols<T>(); }
+// through LDS, then R2-point DFTs, one DFT per thread (16 NC threads).  Rows
+// of NC pairs are read and written whole: 16 pairs in FP64 (256 bytes), 32
+// in FP32 (256 bytes, 7 % faster than 16 on the largest products) except in
+// the FP32 last passes that scatter into a colour's points (EPI), where 16
+// measured 5 % faster.  16 pairs per block beat 8 (narrow rows) and two DFTs
+// per thread.
+template <typename T, int EPI = -1> constexpr int fft_lds_cols()
+{
+    return (sizeof(T) == 4 && EPI != EPI_SCATTER && EPI != EPI_SCATTER_ADD && EPI != EPI_SCATTER_DIAG) ? 32 : 16;
+}
+template <typename T, int EPI = -1> constexpr int fft_lds_threads() { return 16 * fft_lds_cols<T, EPI>(); }
 
 template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
-__global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_lds(FftPass a)
+__global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) void k_fft_lds(FftPass a)
 {
     using C = typename Cx<T>::v;
-    constexpr int R1 = 16, R = R1 * R2, NC = fft_lds_cols<T>(), NT = fft_lds_threads<T>();
+    constexpr int E = DST == FD_EPI ? EPI : -1;
+    constexpr int R1 = 16, R = R1 * R2, NC = fft_lds_cols<T, E>(), NT = fft_lds_threads<T, E>();
     __shared__ C sh[R * NC];
     const int nj = a.L / R;
     const int qblocks = (a.Q + NC - 1) / NC;
@@ -1567,7 +1574,8 @@ static std::vector<int> fft_plan(int L)
 template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
 static void launch_fft_lds(const FftPass &p, hipStream_t s)
 {
-    constexpr int R = 16 * R2, NC = fft_lds_cols<T>(), NT = fft_lds_threads<T>();
+    constexpr int E = DST == FD_EPI ? EPI : -1;
+    constexpr int R = 16 * R2, NC = fft_lds_cols<T, E>(), NT = fft_lds_threads<T, E>();
     const long blocks = (long)((p.Q + NC - 1) / NC) * (p.L / R);
     hipLaunchKernelGGL((k_fft_lds<T, TIN, R2, SIGN, SRC, DST, EPI>), dim3((unsigned)blocks), dim3(NT), 0, s, p);
 }
