@@ -102,10 +102,17 @@ typedef struct {
                            dense matrix-core products: 0 = never, 1 = per level as the
                            autotuner chose (before tuning: when M >= 1024), 2 = always
                            (M >= 32).  The two routes agree to rounding (default 1)       */
+    int inner_cycles;   /* refinement precisions: cycles of the error equation per
+                           refinement step, 1..8 (default 1).  More cycles per step save
+                           FP64 residuals but the later cycles of a step work from a
+                           residual with the FFT route's FP32 rounding, which is relative
+                           to the largest values of a time line: on the 1D N = 4095,
+                           M = 16384 problems two per step took 14 cycles against 10   */
 } mgwr_options;
 
 typedef struct {
-    int iters;          /* cycles done                                                        */
+    int iters;          /* cycles done (refinement precisions: refinement steps, each of
+                           inner_cycles cycles)                                            */
     int status;         /* the return code of mgwr_solve                                      */
     double r0;          /* norm of the initial residual                                       */
     double rk;          /* norm of the final residual                                         */
@@ -237,7 +244,8 @@ int mgwr_batch_destroy(mgwr_batch_t b);
  * term plus the history part (smoother, FFT route), 6 = residual (FFT route:
  * the stencil part minus the product, written as the residual), 7 = the
  * same for a double-double iterate, 8 = the residual at one colour's points
- * (inner cycles of the refinement after pre-smoothing).
+ * (inner cycles of the refinement after pre-smoothing), 9 = the same in 1D
+ * with colour 0 first, written restricted to the coarse grid.
  * A record covers one launch, possibly over several problems: M and K are
  * those of the first, P the sum of the columns, flops the sum of the
  * multiply-adds that are not structurally zero, times 2.  ms covers the

@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("first_colour", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("dc_block", ctypes.c_int),
                 ("L", ctypes.c_double), ("stall", ctypes.c_double), ("graph", ctypes.c_int),
-                ("fft", ctypes.c_int)]
+                ("fft", ctypes.c_int), ("inner_cycles", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):

@@ -494,6 +494,7 @@ int check_opts(const mgwr_options *o)
     if (!(o->L > 0) || !std::isfinite(o->L)) return fail(MGWR_EINVAL, "L must be positive");
     if (!(o->stall >= 0) || o->stall >= 1.0) return fail(MGWR_EINVAL, "stall must be in [0, 1)");
     if (o->graph != 0 && o->graph != 1) return fail(MGWR_EINVAL, "graph must be 0 or 1");
+    if (o->inner_cycles < 1 || o->inner_cycles > 8) return fail(MGWR_EINVAL, "inner_cycles must be in [1, 8]");
     if (o->fft < 0 || o->fft > 2) return fail(MGWR_EINVAL, "fft must be 0, 1 or 2");
     return MGWR_OK;
 }
@@ -895,6 +896,15 @@ bool colour_residual(const Task &t)
     return t.H->prec != MGWR_FP64 && t.H->h->opt.nu1 >= 1 && residual_fft(t);
 }
 
+// In 1D with colour 0 relaxed first, the colour-0 points are exactly the
+// coarse points, so full weighting of a residual that is zero at colour 1
+// is 0.25 (2 r) at each of them: the residual kernel writes the coarse
+// right-hand side itself.
+bool restricted_residual(const Task &t)
+{
+    return colour_residual(t) && t.H->h->dims == 1 && t.H->h->opt.first_colour == 0;
+}
+
 // out = f + c d g - T_M u - A_h u on each task's level: the Toeplitz product
 // (all of T_M u in FP64, its history part otherwise) stored into out, then the
 // stencil part and the diagonal r_1 u applied by a bandwidth kernel (on the
@@ -937,13 +947,18 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
             // FFT route: its last pass applies the stencil part itself
             a.epi = EPI_RESID;
             a.ea.F = t.H->f[t.lev]; a.ea.U = t.H->u[t.lev]; a.ea.lo = nullptr; a.ea.cd = h->cd;
-            a.ea.g = fine ? t.H->g : nullptr; a.ea.ih2 = L.ih2; a.ea.diag = diag;
+            a.ea.g = fine ? t.H->g : nullptr; a.ea.ih2 = L.ih2; a.ea.diag = diag; a.ea.ldu = L.P;
             if (colour_residual(t)) {
                 const int colour = h->opt.first_colour;
                 a.epi = EPI_RESID_C;
                 a.P = L.Pc[colour];
                 a.b_colour = colour;
                 a.ea.colour = colour;
+                if (restricted_residual(t)) {
+                    a.epi = EPI_RESID_R;
+                    a.ea.out = t.H->f[t.lev - 1];
+                    a.ea.ldo = h->lv[t.lev - 1].P;
+                }
             }
             prods.push_back(a);
             continue;
@@ -992,8 +1007,9 @@ int cycle(Exec &ex, const std::vector<Task> &ts)
     std::vector<FillArgs> zs;
     for (const Task &t : fine) {
         mgwr_ctx *h = t.H->h;
-        rs.push_back(XferArgs{0, h->dims, h->lv[t.lev].n, h->M, t.H->rscratch, t.H->f[t.lev - 1],
-                              colour_residual(t) ? 1 - h->opt.first_colour : -1});
+        if (!restricted_residual(t))
+            rs.push_back(XferArgs{0, h->dims, h->lv[t.lev].n, h->M, t.H->rscratch, t.H->f[t.lev - 1],
+                                  colour_residual(t) ? 1 - h->opt.first_colour : -1});
         zs.push_back(FillArgs{h->M, h->lv[t.lev - 1].P, nullptr, nullptr, t.H->u[t.lev - 1], 0});
         pr.push_back(XferArgs{1, h->dims, h->lv[t.lev - 1].n, h->M, t.H->u[t.lev - 1], t.H->u[t.lev]});
     }
@@ -1073,7 +1089,7 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
                 // the FFT route's last pass applies the stencil part itself
                 a.epi = r.lo ? EPI_RESID_DD : EPI_RESID;
                 a.ea.F = r.f; a.ea.U = r.u; a.ea.lo = r.lo; a.ea.cd = h->cd; a.ea.g = r.g;
-                a.ea.ih2 = L.ih2; a.ea.diag = 0.0;
+                a.ea.ih2 = L.ih2; a.ea.diag = 0.0; a.ea.ldu = L.P;
                 fused = true;
             }
             prods.push_back(a);
@@ -1324,7 +1340,18 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
             }
             CHK(cycle(ex, plain));
             HIPCHK(launch_fill(zero, ex.st, ex.s));
-            CHK(cycle(ex, inner));
+            // inner_cycles cycles of the error equation, the first from zero
+            int kmax = 0;
+            for (const Task &t : inner) kmax = std::max(kmax, t.H->h->opt.inner_cycles);
+            for (int k = 0; k < kmax; ++k) {
+                std::vector<Task> sel;
+                for (const Task &t : inner)
+                    if (k < t.H->h->opt.inner_cycles) {
+                        sel.push_back(t);
+                        sel.back().zero = (k == 0);
+                    }
+                CHK(cycle(ex, sel));
+            }
             HIPCHK(launch_dd_update(upd, ex.st, ex.s));
             return fine_residuals(ex, res);
         };
@@ -1631,6 +1658,7 @@ int mgwr_default_options(mgwr_options *o)
     o->warm_start = 0; o->precision = MGWR_FP64; o->first_colour = 0;
     o->smoother = MGWR_SMOOTH_INVERSE; o->dc_block = 0; o->L = 1.0; o->stall = 0.5; o->graph = 1;
     o->fft = 1;
+    o->inner_cycles = 1;
     return MGWR_OK;
 }
 

@@ -53,9 +53,13 @@ enum EpiKind {
     EPI_RESID = 6,       // out[i][p] = (F + cd g - diag U - A_h U) - acc at (i, p)  (the
                          //   residual; FFT route only)
     EPI_RESID_DD = 7,    // the same with the iterate U + lo (double-double)
-    EPI_RESID_C = 8      // EPI_RESID at the points of one colour: product column p is
+    EPI_RESID_C = 8,     // EPI_RESID at the points of one colour: product column p is
                          //   point colour_point(p) (the other colour's residual is zero
                          //   after a red-black sweep and is neither computed nor written)
+    EPI_RESID_R = 9      // 1D, colour 0: EPI_RESID_C restricted on the fly: colour 0's
+                         //   points are the coarse points and the other colour's
+                         //   residual is zero, so out[i][p] = 0.25 (2 r) is the coarse
+                         //   right-hand side (full weighting)
 };
 
 struct EpiArgs {
@@ -72,6 +76,7 @@ struct EpiArgs {
     // (or nullptr) and 1/h^2; out has ldo = P
     const double *F = nullptr, *U = nullptr, *lo = nullptr, *cd = nullptr, *g = nullptr;
     double ih2 = 0.0;
+    long ldu = 0;              // EPI_RESID*: row length of F, U, lo (the level's points)
 };
 
 // Tile choices of the product kernels (set by the autotuner).

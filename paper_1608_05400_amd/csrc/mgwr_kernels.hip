@@ -126,12 +126,12 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
     } else if constexpr (EPI == EPI_SCATTER_DIAG) {
         const int pb = e.b_colour < 0 ? p : colour_point(e.dims, e.n, e.b_colour, p);
         return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + pb];
-    } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C) {
+    } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C || EPI == EPI_RESID_R) {
         // the stencil part of the residual (as OpPost), fused; no load
         // behind a branch (without g, F stands in for it and is not used;
         // diag = 0 subtracts an exact zero)
-        if constexpr (EPI == EPI_RESID_C) p = colour_point(e.dims, e.n, e.colour, p);
-        const long k = (long)i * e.ldo;
+        if constexpr (EPI == EPI_RESID_C || EPI == EPI_RESID_R) p = colour_point(e.dims, e.n, e.colour, p);
+        const long k = (long)i * e.ldu;
         const GLOBAL double *Uk = gview<double>(e.U) + k;
         const double gv = gview<double>(e.g ? e.g : e.F)[p], cdv = gview<double>(e.cd)[i];
         double rhs = gview<double>(e.F)[k + p];
@@ -168,6 +168,8 @@ __device__ inline void epi_put(const EpiArgs &e, int i, int p, double pre, doubl
         out[(long)i * e.ldo + p] = pre - acc;
     } else if constexpr (EPI == EPI_RESID_C) {
         out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = pre - acc;
+    } else if constexpr (EPI == EPI_RESID_R) {
+        out[(long)i * e.ldo + p] = 0.25 * (2.0 * (pre - acc));
     }
 }
 
@@ -179,7 +181,7 @@ template <bool DD, int S>
 __device__ inline void resid_pre_pair_1d(const EpiArgs &e, int i, int p, double &r0, double &r1)
 {
     const int n = e.n;
-    const long k = (long)i * e.ldo;
+    const long k = (long)i * e.ldu;
     const int pl = p > 0 ? p - 1 : p, p1 = min(p + S, n - 1), p2 = min(p + S + 1, n - 1), pm = min(p + 1, n - 1);
     const GLOBAL double *Uk = gview<double>(e.U) + k, *Fk = gview<double>(e.F) + k;
     const GLOBAL double *g = gview<double>(e.g ? e.g : e.F);
@@ -224,7 +226,7 @@ __device__ inline void resid_pre_pair_1d(const EpiArgs &e, int i, int p, double 
 // (four elements) at a time keep them in registers.
 template <int EPI> __host__ __device__ constexpr int epi_rows(int n)
 {
-    return (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C) ? 2 : n;
+    return (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C || EPI == EPI_RESID_R) ? 2 : n;
 }
 
 template <int EPI>
@@ -1390,16 +1392,17 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
             // the epilogue in groups of rows: their loads, then their stores
             const int cc = a.c0 + 2 * q;
             constexpr int CH = epi_rows<EPI>(R2);
-            if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C) {
+            if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C || EPI == EPI_RESID_R) {
                 if (a.ea.dims == 1) {   // cc < P; cc + 1 may be P
                     // first point of the pair: column cc, or the colour's point cc
-                    const int pt = (EPI == EPI_RESID_C) ? colour_point(1, a.ea.n, a.ea.colour, cc) : cc;
+                    constexpr bool colr = EPI == EPI_RESID_C || EPI == EPI_RESID_R;
+                    const int pt = colr ? colour_point(1, a.ea.n, a.ea.colour, cc) : cc;
 #pragma unroll
                     for (int k0 = 0; k0 < R2; k0 += CH) {
                         double pre[CH][2];
 #pragma unroll
                         for (int k = 0; k < CH; ++k)
-                            resid_pre_pair_1d<EPI == EPI_RESID_DD, EPI == EPI_RESID_C ? 2 : 1>(
+                            resid_pre_pair_1d<EPI == EPI_RESID_DD, colr ? 2 : 1>(
                                 a.ea, min(base + (k1 + R1 * (k0 + k)) * a.Ns, a.M - 1), pt, pre[k][0], pre[k][1]);
 #pragma unroll
                         for (int k = 0; k < CH; ++k) {
@@ -1671,6 +1674,7 @@ static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
                 case EPI_RESID: launch_fft_last<T, EPI_RESID>(plan[i], p, s); break;
                 case EPI_RESID_DD: launch_fft_last<T, EPI_RESID_DD>(plan[i], p, s); break;
                 case EPI_RESID_C: launch_fft_last<T, EPI_RESID_C>(plan[i], p, s); break;
+                case EPI_RESID_R: launch_fft_last<T, EPI_RESID_R>(plan[i], p, s); break;
                 default: return hipErrorInvalidValue;
                 }
             }

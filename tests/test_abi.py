@@ -32,6 +32,7 @@ def test_default_options():
     o = binding.default_options()
     assert (o.nu1, o.nu2, o.gamma, o.maxit, o.norm, o.precision) == (1, 1, 1, 100, 0, 0)
     assert o.L == 1.0 and o.first_colour == 0
+    assert (o.fft, o.inner_cycles, o.graph) == (1, 1, 1)
 
 
 @pytest.mark.parametrize("M,alpha", [(64, 0.5), (16384, 0.3), (16384, 0.7), (8192, 0.1), (7, 0.9),
@@ -84,7 +85,7 @@ def test_bad_options_rejected_on_host():
     lib = binding.load()
     h = ctypes.c_void_p()
     for kw in ({"nu1": 0, "nu2": 0}, {"gamma": 3}, {"precision": 9}, {"first_colour": 2},
-               {"stall": 1.5}, {"L": -1.0}):
+               {"stall": 1.5}, {"L": -1.0}, {"inner_cycles": 0}, {"inner_cycles": 9}, {"fft": 3}):
         o = binding.default_options(**kw)
         rc = lib.mgwr_create_ex(7, 16, 0.5, 1.0, 1, ctypes.byref(o), ctypes.byref(h))
         assert rc == binding.MGWR_EINVAL, kw

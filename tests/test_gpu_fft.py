@@ -217,3 +217,19 @@ def test_fft_refinement_with_colour_residual(B, prec, tol, first, dims, N, M, al
         U = host(U)
     assert info["rc"] in (0, 2), info
     assert relmax(U, ref) <= tol, (info, relmax(U, ref))
+
+
+@pytest.mark.parametrize("cycles", [1, 2, 3])
+def test_inner_cycles_per_refinement_step(B, cycles):
+    """Refinement steps of 1, 2 or 3 cycles of the error equation reach the
+    exact discrete solution; more cycles per step, fewer steps."""
+    w = W.random_modes_1d(255, 1500, 0.6, seed=91)
+    f = w.forcing()
+    ref = oracle.direct_solve(1, w.N, w.M, w.alpha, f)
+    with B.Solver(w.N, w.M, w.alpha, precision="bf16x3", inner_cycles=cycles) as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(dev(f), U, tol=1e-12)
+        U = host(U)
+    assert info["rc"] in (0, 2), info
+    assert relmax(U, ref) <= 1e-8, (info, relmax(U, ref))
+    print(f"inner_cycles {cycles}: {info['iters']} refinement steps")
