@@ -447,14 +447,21 @@ GemmArgs gemm_base(mgwr_ctx *h, int mode)
 int run_gemms(Exec &ex, const std::vector<GemmArgs> &as, int level)
 {
     if (as.empty()) return MGWR_OK;
-    if (!ex.prof || !ex.prof->on || ex.record()) {
+    if (!ex.prof || !ex.prof->on) {
         HIPCHK(launch_toep_gemm(as, ex.st, ex.s));
         return MGWR_OK;
     }
+    // profiling: one launch (set) per kernel class between two events; the
+    // record pass of an eager run takes the same classes in the same order,
+    // so that the argument arrays land where the launch pass looks for them
     std::map<int, std::vector<GemmArgs>> cls;
     for (const GemmArgs &a : as)
         if (a.M > 0 && a.P > 0) cls[kernel_id(a)].push_back(a);
     for (auto &kv : cls) {
+        if (ex.record()) {
+            HIPCHK(launch_toep_gemm(kv.second, ex.st, ex.s));
+            continue;
+        }
         Profiler::Pending p;
         p.a = ex.prof->take();
         p.b = ex.prof->take();
@@ -1124,7 +1131,7 @@ int run_eager(Runner &R, const Body &body)
     }
     Staging st;
     st.record = true;
-    Exec rec{R.stream, &st, nullptr};
+    Exec rec{R.stream, &st, &R.prof};   // (the profiler only decides the order of the records)
     CHK(body(rec));
     if (!st.host.empty()) {
         // earlier launches on the stream may still read the arena

@@ -52,6 +52,12 @@ __device__ inline uint16_t f2bf(float x)
 }
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+#define RET_IF(e)                          \
+    do {                                   \
+        hipError_t e_ = (e);               \
+        if (e_ != hipSuccess) return e_;   \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // Stencils of the negative Laplacian (Section 2: 3-point; Section 6: 5-point)
 // with zero Dirichlet values, on one time row U of a level with n points/dim.
@@ -1036,26 +1042,25 @@ static hipError_t launch_mode(int epi, std::vector<KP> &kps, const std::vector<G
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_toep_fft(const GemmArgs &a, hipStream_t s);
+static hipError_t launch_toep_fft(const std::vector<const GemmArgs *> &all, Staging *st, hipStream_t s);
 
 hipError_t launch_toep_gemm(const std::vector<GemmArgs> &as, Staging *st, hipStream_t s)
 {
     // classes of (mode, epilogue, kernel); one launch each
     std::map<int, std::vector<size_t>> cls;
+    std::vector<const GemmArgs *> ffts;
     std::vector<Geo> geo(as.size());
     for (size_t i = 0; i < as.size(); ++i) {
         const GemmArgs &a = as[i];
         if (a.M <= 0 || a.P <= 0) continue;
-        if (a.fft_spec) {   // FFT route: launched on its own (arguments by value)
-            if (!(st && st->record)) {
-                hipError_t e = launch_toep_fft(a, s);
-                if (e != hipSuccess) return e;
-            }
+        if (a.fft_spec) {   // FFT route: grouped below
+            ffts.push_back(&a);
             continue;
         }
         geo[i] = geometry(a.mode, a.M, a.P, a.K, a.off, a.coef->n, a.part ? a.part_cap : 0, a.knobs);
         cls[(a.mode << 8) | (a.epi << 4) | geo[i].kind].push_back(i);
     }
+    RET_IF(launch_toep_fft(ffts, st, s));
     for (auto &kv : cls) {
         const std::vector<size_t> &idx = kv.second;
         std::vector<KP> kps;
@@ -1244,10 +1249,13 @@ __device__ inline void dft_reg(typename Cx<T>::v (&v)[R])
 }
 
 template <typename T, typename TIN, int R, int SIGN, int SRC, int DST, int EPI>
-__global__ __launch_bounds__(256) void k_fft_pass(FftPass a)
+__global__ __launch_bounds__(256) void k_fft_pass(Grp<FftPass> grp)
 {
+    FftPass a;
+    long lb, nb;
+    grp_select(grp, a, lb, nb);
     using C = typename Cx<T>::v;
-    const long g = (long)blockIdx.x * 256 + threadIdx.x;
+    const long g = lb * 256 + threadIdx.x;
     const int nj = a.L / R;
     if (g >= (long)a.Q * nj) return;
     const int q = (int)(g % a.Q), j = (int)(g / a.Q);
@@ -1325,15 +1333,18 @@ template <typename T, int EPI = -1> constexpr int fft_lds_cols()
 template <typename T, int EPI = -1> constexpr int fft_lds_threads() { return 16 * fft_lds_cols<T, EPI>(); }
 
 template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
-__global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) void k_fft_lds(FftPass a)
+__global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) void k_fft_lds(Grp<FftPass> grp)
 {
+    FftPass a;
+    long lb, nb;
+    grp_select(grp, a, lb, nb);
     using C = typename Cx<T>::v;
     constexpr int E = DST == FD_EPI ? EPI : -1;
     constexpr int R1 = 16, R = R1 * R2, NC = fft_lds_cols<T, E>(), NT = fft_lds_threads<T, E>();
     __shared__ C sh[R * NC];
     const int nj = a.L / R;
     const int qblocks = (a.Q + NC - 1) / NC;
-    const int qb = blockIdx.x % qblocks, j = blockIdx.x / qblocks;
+    const int qb = (int)(lb % qblocks), j = (int)(lb / qblocks);
     const int q0 = qb * NC;
     const GLOBAL C *tw = gview<C>(a.tw);
     const int jm = j % a.Ns;
@@ -1445,15 +1456,18 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
 // of them from LDS and writes rows j' RI + t.  One read and one write of the
 // work array less per product than the two passes.
 template <typename T, int RI>
-__global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
+__global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(Grp<FftPass> grp)
 {
+    FftPass a;
+    long lb, nb;
+    grp_select(grp, a, lb, nb);
     using C = typename Cx<T>::v;
     constexpr int R = 256, NC = fft_lds_cols<T>(), NT = fft_lds_threads<T>(), G = R / RI;
     static_assert(16 * NC == NT, "one radix-256 job per thread");
     __shared__ C sh[R * NC];
     const int nj = a.L / R;
     const int qblocks = (a.Q + NC - 1) / NC;
-    const int qb = blockIdx.x % qblocks, j = blockIdx.x / qblocks;
+    const int qb = (int)(lb % qblocks), j = (int)(lb / qblocks);
     const int q0 = qb * NC;
     const GLOBAL C *tw = gview<C>(a.tw);
     const GLOBAL C *src = gview<C>(a.src), *spec = gview<C>(a.spec);
@@ -1537,20 +1551,65 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(FftPass a)
     }
 }
 
+// The FFT passes are launched for a group of products at once (the same
+// transform length and epilogue: one entry per product, blocks after one
+// another, each block finding its product as the grouped bandwidth kernels
+// do); without a staging area, one launch per product.
+template <typename Launch>
+static hipError_t fft_launch(Launch &&launch, const std::vector<FftPass> &ps, const std::vector<long> &blocks,
+                             Staging *st)
+{
+    if (ps.empty()) return hipSuccess;
+    if (ps.size() > 1 && !st) {
+        for (size_t i = 0; i < ps.size(); ++i) {
+            hipError_t e = fft_launch(launch, std::vector<FftPass>{ps[i]}, std::vector<long>{blocks[i]}, nullptr);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    Grp<FftPass> g{};
+    long total = 0;
+    if (ps.size() == 1) {
+        if (st && st->record) return hipSuccess;
+        g.one = ps[0];
+        g.n = 1;
+        total = blocks[0];
+    } else {
+        std::vector<int> start(ps.size() + 1, 0);
+        for (size_t i = 0; i < ps.size(); ++i) start[i + 1] = start[i] + (int)blocks[i];
+        const void *dm = st->put(ps.data(), sizeof(FftPass) * ps.size());
+        const void *ds = st->put(start.data(), sizeof(int) * start.size());
+        if (st->record) return hipSuccess;
+        g.one = ps[0];
+        g.many = (const FftPass *)dm;
+        g.start = (const int *)ds;
+        g.n = (int)ps.size();
+        total = start.back();
+    }
+    if (total <= 0) return hipSuccess;
+    launch(dim3((unsigned)total), g);
+    return hipGetLastError();
+}
+
 template <typename T>
-static void launch_fft_mid(int RI, const FftPass &p, hipStream_t s)
+static hipError_t launch_fft_mid(int RI, const std::vector<FftPass> &ps, Staging *st, hipStream_t s)
 {
     constexpr int NC = fft_lds_cols<T>(), NT = fft_lds_threads<T>();
-    const dim3 grid((unsigned)((long)((p.Q + NC - 1) / NC) * (p.L / 256)));
+    std::vector<long> blocks;
+    for (const FftPass &p : ps) blocks.push_back((long)((p.Q + NC - 1) / NC) * (p.L / 256));
+    auto go = [&](auto kern) {
+        return fft_launch([&](dim3 grid, const Grp<FftPass> &g) { hipLaunchKernelGGL(kern, grid, dim3(NT), 0, s, g); },
+                          ps, blocks, st);
+    };
     switch (RI) {
-    case 2: hipLaunchKernelGGL((k_fft_mid<T, 2>), grid, dim3(NT), 0, s, p); break;
-    case 4: hipLaunchKernelGGL((k_fft_mid<T, 4>), grid, dim3(NT), 0, s, p); break;
-    case 8: hipLaunchKernelGGL((k_fft_mid<T, 8>), grid, dim3(NT), 0, s, p); break;
-    case 16: hipLaunchKernelGGL((k_fft_mid<T, 16>), grid, dim3(NT), 0, s, p); break;
-    case 32: hipLaunchKernelGGL((k_fft_mid<T, 32>), grid, dim3(NT), 0, s, p); break;
-    case 64: hipLaunchKernelGGL((k_fft_mid<T, 64>), grid, dim3(NT), 0, s, p); break;
-    case 128: hipLaunchKernelGGL((k_fft_mid<T, 128>), grid, dim3(NT), 0, s, p); break;
-    default: hipLaunchKernelGGL((k_fft_mid<T, 256>), grid, dim3(NT), 0, s, p); break;
+    case 2: return go(k_fft_mid<T, 2>);
+    case 4: return go(k_fft_mid<T, 4>);
+    case 8: return go(k_fft_mid<T, 8>);
+    case 16: return go(k_fft_mid<T, 16>);
+    case 32: return go(k_fft_mid<T, 32>);
+    case 64: return go(k_fft_mid<T, 64>);
+    case 128: return go(k_fft_mid<T, 128>);
+    default: return go(k_fft_mid<T, 256>);
     }
 }
 
@@ -1575,123 +1634,181 @@ static std::vector<int> fft_plan(int L)
 }
 
 template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
-static void launch_fft_lds(const FftPass &p, hipStream_t s)
+static hipError_t launch_fft_lds(const std::vector<FftPass> &ps, Staging *st, hipStream_t s)
 {
     constexpr int E = DST == FD_EPI ? EPI : -1;
     constexpr int R = 16 * R2, NC = fft_lds_cols<T, E>(), NT = fft_lds_threads<T, E>();
-    const long blocks = (long)((p.Q + NC - 1) / NC) * (p.L / R);
-    hipLaunchKernelGGL((k_fft_lds<T, TIN, R2, SIGN, SRC, DST, EPI>), dim3((unsigned)blocks), dim3(NT), 0, s, p);
+    std::vector<long> blocks;
+    for (const FftPass &p : ps) blocks.push_back((long)((p.Q + NC - 1) / NC) * (p.L / R));
+    return fft_launch(
+        [&](dim3 grid, const Grp<FftPass> &g) {
+            hipLaunchKernelGGL((k_fft_lds<T, TIN, R2, SIGN, SRC, DST, EPI>), grid, dim3(NT), 0, s, g);
+        },
+        ps, blocks, st);
 }
 
 template <typename T, typename TIN, int SIGN, int SRC, int DST, int EPI>
-static void launch_fft_pass(int R, const FftPass &p, hipStream_t s)
+static hipError_t launch_fft_pass(int R, const std::vector<FftPass> &ps, Staging *st, hipStream_t s)
 {
     if (R >= 64) {
         if constexpr (DST == FD_CPLX) {
-            if (R == 64) launch_fft_lds<T, TIN, 4, SIGN, SRC, DST, EPI>(p, s);
-            else if (R == 128) launch_fft_lds<T, TIN, 8, SIGN, SRC, DST, EPI>(p, s);
-            else launch_fft_lds<T, TIN, 16, SIGN, SRC, DST, EPI>(p, s);
+            if (R == 64) return launch_fft_lds<T, TIN, 4, SIGN, SRC, DST, EPI>(ps, st, s);
+            if (R == 128) return launch_fft_lds<T, TIN, 8, SIGN, SRC, DST, EPI>(ps, st, s);
+            return launch_fft_lds<T, TIN, 16, SIGN, SRC, DST, EPI>(ps, st, s);
         }
-        return;
+        return hipErrorInvalidValue;
     }
-    const long threads = (long)p.Q * (p.L / R);
-    const dim3 grid((unsigned)((threads + 255) / 256));
+    std::vector<long> blocks;
+    for (const FftPass &p : ps) blocks.push_back(((long)p.Q * (p.L / R) + 255) / 256);
+    auto go = [&](auto kern) {
+        return fft_launch([&](dim3 grid, const Grp<FftPass> &g) { hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, g); },
+                          ps, blocks, st);
+    };
     switch (R) {
-    case 2: hipLaunchKernelGGL((k_fft_pass<T, TIN, 2, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
-    case 4: hipLaunchKernelGGL((k_fft_pass<T, TIN, 4, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
-    case 8: hipLaunchKernelGGL((k_fft_pass<T, TIN, 8, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
-    case 16: hipLaunchKernelGGL((k_fft_pass<T, TIN, 16, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
-    default: hipLaunchKernelGGL((k_fft_pass<T, TIN, 32, SIGN, SRC, DST, EPI>), grid, dim3(256), 0, s, p); break;
+    case 2: return go(k_fft_pass<T, TIN, 2, SIGN, SRC, DST, EPI>);
+    case 4: return go(k_fft_pass<T, TIN, 4, SIGN, SRC, DST, EPI>);
+    case 8: return go(k_fft_pass<T, TIN, 8, SIGN, SRC, DST, EPI>);
+    case 16: return go(k_fft_pass<T, TIN, 16, SIGN, SRC, DST, EPI>);
+    default: return go(k_fft_pass<T, TIN, 32, SIGN, SRC, DST, EPI>);
     }
 }
 
 template <typename T, int EPI>
-static void launch_fft_last(int R, const FftPass &p, hipStream_t s)
+static hipError_t launch_fft_last(int R, const std::vector<FftPass> &ps, Staging *st, hipStream_t s)
 {
-    if (R == 256) {
-        launch_fft_lds<T, T, 16, 1, FS_CPLX, FD_EPI, EPI>(p, s);
-        return;
-    }
-    const dim3 grid((unsigned)(((long)p.Q * (p.L / 32) + 255) / 256));
-    hipLaunchKernelGGL((k_fft_pass<T, T, 32, 1, FS_CPLX, FD_EPI, EPI>), grid, dim3(256), 0, s, p);
+    if (R == 256) return launch_fft_lds<T, T, 16, 1, FS_CPLX, FD_EPI, EPI>(ps, st, s);
+    if (R != 32) return hipErrorInvalidValue;
+    std::vector<long> blocks;
+    for (const FftPass &p : ps) blocks.push_back(((long)p.Q * (p.L / 32) + 255) / 256);
+    return fft_launch(
+        [&](dim3 grid, const Grp<FftPass> &g) {
+            hipLaunchKernelGGL((k_fft_pass<T, T, 32, 1, FS_CPLX, FD_EPI, EPI>), grid, dim3(256), 0, s, g);
+        },
+        ps, blocks, st);
 }
 
+// Products of one group (the same transform length, arithmetic and
+// epilogue), each in one chunk of columns starting at c0[i]: every pass is
+// one launch over all of them.
 template <typename T, typename TIN>
-static hipError_t fft_product(const GemmArgs &a, hipStream_t s)
+static hipError_t fft_group(const std::vector<const GemmArgs *> &as, const std::vector<long> &c0, Staging *st,
+                            hipStream_t s)
 {
-    const std::vector<int> plan = fft_plan(a.fft_L);
+    const GemmArgs &a0 = *as[0];
+    const std::vector<int> plan = fft_plan(a0.fft_L);
     if (plan.size() < 2) return hipErrorInvalidValue;
-    const long qcap = (long)(a.fft_buf_cap / (2 * sizeof(T) * (size_t)a.fft_L));
-    if (qcap < 1) return hipErrorInvalidValue;
-    for (long c0 = 0; c0 < a.P; c0 += 2 * qcap) {
-        FftPass p{};
+    const size_t n = plan.size(), m = as.size();
+    std::vector<FftPass> ps(m);
+    for (size_t k = 0; k < m; ++k) {
+        const GemmArgs &a = *as[k];
+        const long qcap = (long)(a.fft_buf_cap / (2 * sizeof(T) * (size_t)a.fft_L));
+        FftPass &p = ps[k];
         p.L = a.fft_L;
-        p.Q = (int)std::min(qcap, (long)(a.P - c0 + 1) / 2);
-        p.M = a.M; p.K = a.K; p.P = a.P; p.c0 = (int)c0;
+        p.Q = (int)std::min(qcap, (long)(a.P - c0[k] + 1) / 2);
+        p.M = a.M; p.K = a.K; p.P = a.P; p.c0 = (int)c0[k];
         p.B = a.B; p.ldb = a.ldb; p.b_colour = a.b_colour;
         p.spec = a.fft_spec; p.tw = a.fft_tw; p.Ltw = a.fft_Ltw;
         p.scale = 1.0 / a.fft_L;
         p.ea = a.ea;
-        void *bufs[2] = {a.fft_buf0, a.fft_buf1};
-        int cur = 0;   // buffer the next pass writes
-        // a plan that ends in radix 256 (L >= 512) does its last forward
-        // pass, the spectrum and its first inverse pass in one kernel
-        const size_t n = plan.size();
-        const bool mid = plan.back() == 256;
-        // forward transform
-        p.Ns = 1;
-        for (size_t i = 0; i + (mid ? 1 : 0) < n; ++i) {
-            p.dst = bufs[cur];
-            if (i == 0) launch_fft_pass<T, TIN, -1, FS_REAL, FD_CPLX, 0>(plan[i], p, s);
-            else launch_fft_pass<T, T, -1, FS_CPLX, FD_CPLX, 0>(plan[i], p, s);
-            p.src = bufs[cur];
-            cur ^= 1;
-            p.Ns *= plan[i];
-        }
-        size_t i0 = 0;
-        if (mid) {
-            p.dst = bufs[cur];
-            launch_fft_mid<T>(plan[0], p, s);
-            p.src = bufs[cur];
-            cur ^= 1;
-            i0 = 1;
-        }
-        // times the coefficient spectrum (unless done), inverse transform, epilogue
-        p.Ns = mid ? plan[0] : 1;
-        for (size_t i = i0; i < n; ++i) {
-            if (i + 1 < n) {
-                p.dst = bufs[cur];
-                if (i == 0) launch_fft_pass<T, T, 1, FS_SPEC, FD_CPLX, 0>(plan[i], p, s);
-                else launch_fft_pass<T, T, 1, FS_CPLX, FD_CPLX, 0>(plan[i], p, s);
-                p.src = bufs[cur];
-                cur ^= 1;
-            } else {
-                switch (a.epi) {
-                case EPI_STORE: launch_fft_last<T, EPI_STORE>(plan[i], p, s); break;
-                case EPI_SCATTER: launch_fft_last<T, EPI_SCATTER>(plan[i], p, s); break;
-                case EPI_SCATTER_ADD: launch_fft_last<T, EPI_SCATTER_ADD>(plan[i], p, s); break;
-                case EPI_SCATTER_DIAG: launch_fft_last<T, EPI_SCATTER_DIAG>(plan[i], p, s); break;
-                case EPI_RESID: launch_fft_last<T, EPI_RESID>(plan[i], p, s); break;
-                case EPI_RESID_DD: launch_fft_last<T, EPI_RESID_DD>(plan[i], p, s); break;
-                case EPI_RESID_C: launch_fft_last<T, EPI_RESID_C>(plan[i], p, s); break;
-                case EPI_RESID_R: launch_fft_last<T, EPI_RESID_R>(plan[i], p, s); break;
-                default: return hipErrorInvalidValue;
-                }
-            }
-            p.Ns *= plan[i];
-        }
     }
-    return hipGetLastError();
+    int cur = 0;   // buffer the next pass writes (each product has its own two)
+    auto to = [&]() { for (size_t k = 0; k < m; ++k) ps[k].dst = cur ? as[k]->fft_buf1 : as[k]->fft_buf0; };
+    auto from = [&]() { for (size_t k = 0; k < m; ++k) ps[k].src = ps[k].dst; cur ^= 1; };
+    auto ns = [&](int v) { for (FftPass &p : ps) p.Ns = v; };
+    // a plan that ends in radix 256 (L >= 512) does its last forward pass,
+    // the spectrum and its first inverse pass in one kernel
+    const bool mid = plan.back() == 256;
+    // forward transform
+    int Ns = 1;
+    for (size_t i = 0; i + (mid ? 1 : 0) < n; ++i) {
+        ns(Ns);
+        to();
+        RET_IF((i == 0 ? launch_fft_pass<T, TIN, -1, FS_REAL, FD_CPLX, 0>(plan[i], ps, st, s)
+                       : launch_fft_pass<T, T, -1, FS_CPLX, FD_CPLX, 0>(plan[i], ps, st, s)));
+        from();
+        Ns *= plan[i];
+    }
+    size_t i0 = 0;
+    if (mid) {
+        ns(Ns);
+        to();
+        RET_IF(launch_fft_mid<T>(plan[0], ps, st, s));
+        from();
+        i0 = 1;
+    }
+    // times the coefficient spectrum (unless done), inverse transform, epilogue
+    Ns = mid ? plan[0] : 1;
+    for (size_t i = i0; i < n; ++i) {
+        ns(Ns);
+        if (i + 1 < n) {
+            to();
+            RET_IF((i == 0 ? launch_fft_pass<T, T, 1, FS_SPEC, FD_CPLX, 0>(plan[i], ps, st, s)
+                           : launch_fft_pass<T, T, 1, FS_CPLX, FD_CPLX, 0>(plan[i], ps, st, s)));
+            from();
+        } else {
+            switch (a0.epi) {
+            case EPI_STORE: RET_IF((launch_fft_last<T, EPI_STORE>(plan[i], ps, st, s))); break;
+            case EPI_SCATTER: RET_IF((launch_fft_last<T, EPI_SCATTER>(plan[i], ps, st, s))); break;
+            case EPI_SCATTER_ADD: RET_IF((launch_fft_last<T, EPI_SCATTER_ADD>(plan[i], ps, st, s))); break;
+            case EPI_SCATTER_DIAG: RET_IF((launch_fft_last<T, EPI_SCATTER_DIAG>(plan[i], ps, st, s))); break;
+            case EPI_RESID: RET_IF((launch_fft_last<T, EPI_RESID>(plan[i], ps, st, s))); break;
+            case EPI_RESID_DD: RET_IF((launch_fft_last<T, EPI_RESID_DD>(plan[i], ps, st, s))); break;
+            case EPI_RESID_C: RET_IF((launch_fft_last<T, EPI_RESID_C>(plan[i], ps, st, s))); break;
+            case EPI_RESID_R: RET_IF((launch_fft_last<T, EPI_RESID_R>(plan[i], ps, st, s))); break;
+            default: return hipErrorInvalidValue;
+            }
+        }
+        Ns *= plan[i];
+    }
+    return hipSuccess;
 }
 
-static hipError_t launch_toep_fft(const GemmArgs &a, hipStream_t s)
+// The FFT-route products of one launch stage: grouped by transform length,
+// arithmetic and epilogue (in order of first appearance); a product whose
+// columns need several chunks of the work arrays runs alone, chunk by chunk.
+static hipError_t launch_toep_fft(const std::vector<const GemmArgs *> &all, Staging *st, hipStream_t s)
 {
-    if (a.off != 0 || a.K > a.M || a.fft_L < 2 * a.M || a.fft_L < 64 || a.fft_L > a.fft_Ltw)
-        return hipErrorInvalidValue;
-    if (a.mode == GM_F64) return fft_product<double, double>(a, s);
-    // FP32 arithmetic (the history products of the mixed cycles) on FP64 or FP32 input
-    if (a.fft_b64) return fft_product<float, double>(a, s);
-    return fft_product<float, float>(a, s);
+    std::vector<std::pair<long, std::vector<const GemmArgs *>>> groups;
+    for (const GemmArgs *a : all) {
+        if (a->off != 0 || a->K > a->M || a->fft_L < 2 * a->M || a->fft_L < 64 || a->fft_L > a->fft_Ltw)
+            return hipErrorInvalidValue;
+        const size_t csz = (a->mode == GM_F64) ? 16 : 8;
+        const long qcap = (long)(a->fft_buf_cap / (csz * (size_t)a->fft_L));
+        if (qcap < 1) return hipErrorInvalidValue;
+        const long key = ((long)a->fft_L << 8) | (a->mode << 6) | ((a->fft_b64 ? 1 : 0) << 5) | a->epi;
+        if ((a->P + 1) / 2 > qcap) {   // several chunks: alone
+            groups.push_back({-1, {a}});
+            continue;
+        }
+        // (products of one group must not share work arrays)
+        auto fits = [&](const std::vector<const GemmArgs *> &v) {
+            for (const GemmArgs *b : v)
+                if (b->fft_buf0 == a->fft_buf0) return false;
+            return true;
+        };
+        size_t g = 0;
+        while (g < groups.size() && !(groups[g].first == key && fits(groups[g].second))) ++g;
+        if (g == groups.size()) groups.push_back({key, {}});
+        groups[g].second.push_back(a);
+    }
+    for (auto &kv : groups) {
+        const auto &as = kv.second;
+        const GemmArgs &a0 = *as[0];
+        auto run = [&](const std::vector<long> &c0) -> hipError_t {
+            if (a0.mode == GM_F64) return fft_group<double, double>(as, c0, st, s);
+            // FP32 arithmetic (the history products of the mixed cycles) on FP64 or FP32 input
+            if (a0.fft_b64) return fft_group<float, double>(as, c0, st, s);
+            return fft_group<float, float>(as, c0, st, s);
+        };
+        if (kv.first >= 0) {
+            RET_IF(run(std::vector<long>(as.size(), 0)));
+        } else {
+            const size_t csz = (a0.mode == GM_F64) ? 16 : 8;
+            const long qcap = (long)(a0.fft_buf_cap / (csz * (size_t)a0.fft_L));
+            for (long c = 0; c < a0.P; c += 2 * qcap) RET_IF(run({c}));
+        }
+    }
+    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -2065,12 +2182,6 @@ static hipError_t launch_subset(const std::vector<typename Op::A> &v, Pred pred,
         }
     return launch_group<Op>(sub, blocks, st, s);
 }
-
-#define RET_IF(e)                          \
-    do {                                   \
-        hipError_t e_ = (e);               \
-        if (e_ != hipSuccess) return e_;   \
-    } while (0)
 
 hipError_t launch_rhs(const std::vector<RhsArgs> &v, Staging *st, hipStream_t s)
 {

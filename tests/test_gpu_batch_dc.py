@@ -256,3 +256,26 @@ def test_config4_batch_full_size(B):
         err = _sampled_error(ws[i], us[i])
         assert err <= 1e-8, (i, ws[i].N, ws[i].M, ws[i].alpha, err)
     b.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x3", 1e-8)])
+def test_batch_profiled_with_fft_and_dense_products(B, prec, tol):
+    """A profiled batch solve (products issued class by class between events)
+    whose stages mix FFT-route and dense products: the record pass and the
+    launch pass of each eager program must stage the argument arrays in the
+    same order."""
+    cases = [(255, 2048, 0.4), (127, 512, 0.6), (63, 1500, 0.3), (127, 4096, 0.5)]
+    ws = [_modes_problem(N, M, a, 300 + i) for i, (N, M, a) in enumerate(cases)]
+    refs = [oracle.direct_solve(1, w.N, w.M, w.alpha, f) for w, f in ws]
+    b = B.Batch([w.N for w, _ in ws], [w.M for w, _ in ws], [w.alpha for w, _ in ws], precision=prec)
+    us = [torch.zeros((w.M, w.N), dtype=torch.float64, device="cuda") for w, _ in ws]
+    b.profile(True)
+    rc, infos = b.solve([dev(f) for _, f in ws], us, tol=1e-12)
+    recs = b.profile_records()
+    b.profile(False)
+    b.close()
+    kinds = {r["kernel"] >> 8 for r in recs}
+    assert 4 in kinds and kinds - {4}, kinds   # FFT route and dense products both timed
+    for i, (u, ref, inf) in enumerate(zip(us, refs, infos)):
+        assert inf["status"] in ("ok", "stagnated"), (i, inf)
+        assert relmax(host(u), ref) <= tol, (i, inf, relmax(host(u), ref))
