@@ -10,12 +10,17 @@ problems from u = 0 with a V(1,1) cycle until the FP64 residual is reduced by
 --tol in the max norm.  Inputs are resident in HBM before the timed region.
 
 Modes: "bf16x3" (split-BF16 inner cycle, FP64 double-double refinement; the
-reported value), "fp64" (Algorithm 1 in FP64 on u), "fp32" (FP32 inner
-cycle), "fp64r" (FP64 inner cycle with double-double refinement).
+reported value), "fp64" (Algorithm 1 in FP64 on u; on the default workload it
+stops at its rounding floor above the tolerance, flagged in the JSON line),
+"fp32" (FP32 inner cycle), "fp64r" (FP64 inner cycle with double-double
+refinement: the FP64 method that reaches the tolerance).
 
-Before the timed steps each handle is autotuned (tile shapes of the product
-kernels, and D&C base blocks with --smoother auto/dc); the tuning time is
-reported apart from the timed steps, like handle creation.
+Before the timed steps each handle is autotuned (FFT or dense route per
+level, tile shapes of the dense product kernels, and D&C base blocks with
+--smoother auto/dc); the tuning time is reported apart from the timed steps,
+like handle creation.  The timed steps issue the products one by one between
+HIP events (the roofline's launch times); one more step replays the recorded
+HIP graphs and is reported beside them.
 
 --workload batch solves 256 independent 1D problems of uneven size (N in
 {127..2047}, M in {256..8192}, alpha in (0.1, 0.9), seeded) as one batch:
