@@ -233,3 +233,24 @@ def test_inner_cycles_per_refinement_step(B, cycles):
     assert info["rc"] in (0, 2), info
     assert relmax(U, ref) <= 1e-8, (info, relmax(U, ref))
     print(f"inner_cycles {cycles}: {info['iters']} refinement steps")
+
+
+@pytest.mark.parametrize("dims,N,M,alpha", [(1, 127, 700, 0.5), (2, 31, 520, 0.35)])
+@pytest.mark.parametrize("cyc", [(1, 0, 2), (2, 1, 1), (1, 2, 2)])
+def test_fft_refinement_cycle_shapes(B, dims, N, M, alpha, cyc):
+    """Refinement with every product on the FFT route under other cycle shapes
+    (nu1, nu2, gamma): W-cycles and several pre-smoothing sweeps, where the
+    inner cycles restrict a one-colour residual."""
+    nu1, nu2, gamma = cyc
+    if dims == 1:
+        w = W.random_modes_1d(N, M, alpha, seed=92)
+    else:
+        w = W.manufactured_2d(N, M, alpha)
+    f = w.forcing()
+    ref = oracle.direct_solve(dims, w.N, w.M, w.alpha, f)
+    with B.Solver(w.N, w.M, w.alpha, dims=dims, precision="bf16x3", nu1=nu1, nu2=nu2, gamma=gamma, fft=2) as s:
+        U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        info = s.solve(dev(f), U, tol=1e-12)
+        U = host(U)
+    assert info["rc"] in (0, 2), info
+    assert relmax(U, ref) <= 1e-8, (info, relmax(U, ref))
