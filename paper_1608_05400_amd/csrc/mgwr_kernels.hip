@@ -1351,41 +1351,51 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
     const int jm = j % a.Ns;
     const long pstep = (long)jm * (a.Ltw / (a.Ns * R));   // twiddles of the pass
     const int wstep = a.Ltw / R;                           // twiddles inside the R-point DFT
-    for (int job = threadIdx.x; job < R2 * NC; job += NT) {
-        const int c = job % NC, r2 = job / NC, q = q0 + c;
-        C v[R1];
+    // the block's pass twiddles (exp(-+2 pi i jm r / (Ns R)), r < R) and the
+    // inner twiddles (exp(-+2 pi i t / R), t < R), read once into LDS
+    __shared__ C twp[R], twi[R];
+    const int c = threadIdx.x % NC, r2 = threadIdx.x / NC, q = q0 + c;
+    const bool busy = r2 < R2;   // R2 NC jobs for NT >= R2 NC threads
+    C v[R1];
 #pragma unroll
-        for (int r1 = 0; r1 < R1; ++r1) {
-            const int r = R2 * r1 + r2, tau = j + r * nj;
-            C x = C{0, 0};
-            if (q < a.Q) {
-                if constexpr (SRC == FS_REAL) {
-                    T re = 0, im = 0;
-                    if (tau < a.K) {
-                        const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb;
-                        if (a.c0 + 2 * q < a.P) re = (T)row[fft_bcol(a, a.c0 + 2 * q)];
-                        if (a.c0 + 2 * q + 1 < a.P) im = (T)row[fft_bcol(a, a.c0 + 2 * q + 1)];
-                    }
-                    x = C{re, im};
-                } else {
-                    x = __builtin_nontemporal_load(&gview<C>(a.src)[(long)tau * a.Q + q]);
-                    if constexpr (SRC == FS_SPEC) x = cmul(x, gview<C>(a.spec)[tau]);
+    for (int r1 = 0; r1 < R1; ++r1) {
+        const int r = R2 * r1 + r2, tau = j + r * nj;
+        C x = C{0, 0};
+        if (busy && q < a.Q) {
+            if constexpr (SRC == FS_REAL) {
+                T re = 0, im = 0;
+                if (tau < a.K) {
+                    const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb;
+                    if (a.c0 + 2 * q < a.P) re = (T)row[fft_bcol(a, a.c0 + 2 * q)];
+                    if (a.c0 + 2 * q + 1 < a.P) im = (T)row[fft_bcol(a, a.c0 + 2 * q + 1)];
                 }
+                x = C{re, im};
+            } else {
+                x = __builtin_nontemporal_load(&gview<C>(a.src)[(long)tau * a.Q + q]);
+                if constexpr (SRC == FS_SPEC) x = cmul(x, gview<C>(a.spec)[tau]);
             }
-            if (a.Ns > 1 && r > 0) {
-                C w = tw[pstep * r];
-                if (SIGN > 0) w.y = -w.y;
-                x = cmul(x, w);
-            }
-            v[r1] = x;
+        }
+        v[r1] = x;
+    }
+    for (int t = threadIdx.x; t < R; t += NT) {
+        C w = a.Ns > 1 ? tw[pstep * t] : C{1, 0}, wi = tw[(long)t * wstep];
+        if (SIGN > 0) {
+            w.y = -w.y;
+            wi.y = -wi.y;
+        }
+        twp[t] = w;
+        twi[t] = wi;
+    }
+    __syncthreads();
+    if (busy) {
+        if (a.Ns > 1) {
+#pragma unroll
+            for (int r1 = 0; r1 < R1; ++r1)
+                if (R2 * r1 + r2 > 0) v[r1] = cmul(v[r1], twp[R2 * r1 + r2]);
         }
         dft_reg<T, R1, SIGN>(v);
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) {
-            C w = tw[(long)(r2 * k1) * wstep];
-            if (SIGN > 0) w.y = -w.y;
-            sh[(k1 * R2 + r2) * NC + c] = cmul(v[k1], w);
-        }
+        for (int k1 = 0; k1 < R1; ++k1) sh[(k1 * R2 + r2) * NC + c] = cmul(v[k1], twi[r2 * k1]);
     }
     __syncthreads();
     const int base = (j / a.Ns) * a.Ns * R + jm;
@@ -1474,22 +1484,39 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(Grp<FftPass> g
     const GLOBAL C *src = gview<C>(a.src), *spec = gview<C>(a.spec);
     GLOBAL C *dst = gview_rw<C>(a.dst);
     const int wstep = a.Ltw / R;
+    // the block's twiddles and spectrum values, read once into LDS: pass
+    // twiddles exp(-2 pi i j r / L), inner twiddles exp(-2 pi i t / 256),
+    // spectrum rows j + t nj and the inverse inner twiddles exp(2 pi i t / RI)
+    __shared__ C twp[R], twi[R], sp[R], twv[RI > 16 ? RI : 1];
     {   // forward, first stage: 16-point DFTs over r = 16 r1 + r2 after the
-        // pass twiddles exp(-2 pi i j r / L), then the inner twiddles
+        // pass twiddles, then the inner twiddles
         const int c = threadIdx.x % NC, r2 = threadIdx.x / NC, q = q0 + c;
         const long pstep = (long)j * (a.Ltw / a.L);
         C v[16];
 #pragma unroll
         for (int r1 = 0; r1 < 16; ++r1) {
             const int r = 16 * r1 + r2;
-            C x = C{0, 0};
-            if (q < a.Q) x = __builtin_nontemporal_load(&src[(long)(j + r * nj) * a.Q + q]);
-            if (r > 0) x = cmul(x, tw[pstep * r]);
-            v[r1] = x;
+            v[r1] = q < a.Q ? __builtin_nontemporal_load(&src[(long)(j + r * nj) * a.Q + q]) : C{0, 0};
         }
+        for (int t = threadIdx.x; t < R; t += NT) {
+            twp[t] = tw[pstep * t];
+            twi[t] = tw[(long)t * wstep];
+            sp[t] = spec[j + t * nj];
+            if constexpr (RI > 16) {
+                if (t < RI) {
+                    C w = tw[(long)t * (a.Ltw / RI)];
+                    w.y = -w.y;
+                    twv[t] = w;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r1 = 1; r1 < 16; ++r1) v[r1] = cmul(v[r1], twp[16 * r1 + r2]);
+        if (r2 > 0) v[0] = cmul(v[0], twp[r2]);
         dft_reg<T, 16, -1>(v);
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) sh[(k1 * 16 + r2) * NC + c] = cmul(v[k1], tw[(long)(r2 * k1) * wstep]);
+        for (int k1 = 0; k1 < 16; ++k1) sh[(k1 * 16 + r2) * NC + c] = cmul(v[k1], twi[r2 * k1]);
     }
     __syncthreads();
     {   // forward, second stage: Y[k], k = k1 + 16 k2 (row j + k nj), times the spectrum
@@ -1499,7 +1526,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(Grp<FftPass> g
         for (int r2 = 0; r2 < 16; ++r2) v[r2] = sh[(k1 * 16 + r2) * NC + c];
         dft_reg<T, 16, -1>(v);
 #pragma unroll
-        for (int k2 = 0; k2 < 16; ++k2) v[k2] = cmul(v[k2], spec[j + (k1 + 16 * k2) * nj]);
+        for (int k2 = 0; k2 < 16; ++k2) v[k2] = cmul(v[k2], sp[k1 + 16 * k2]);
         __syncthreads();
 #pragma unroll
         for (int k2 = 0; k2 < 16; ++k2) sh[(k1 + 16 * k2) * NC + c] = v[k2];
@@ -1523,7 +1550,6 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(Grp<FftPass> g
         // RI = 16 x RI2: 16-point DFTs over s = RI2 s1 + s2 (in place), the
         // inner twiddles, then RI2-point DFTs giving X[k1 + 16 k2]
         constexpr int RI2 = RI / 16;
-        const int wi = a.Ltw / RI;
         for (int job = threadIdx.x; job < G * RI2 * NC; job += NT) {
             const int c = job % NC, s2 = (job / NC) % RI2, g = job / (NC * RI2);
             C v[16];
@@ -1531,11 +1557,7 @@ __global__ __launch_bounds__(fft_lds_threads<T>()) void k_fft_mid(Grp<FftPass> g
             for (int s1 = 0; s1 < 16; ++s1) v[s1] = sh[(g + G * (RI2 * s1 + s2)) * NC + c];
             dft_reg<T, 16, 1>(v);
 #pragma unroll
-            for (int k1 = 0; k1 < 16; ++k1) {
-                C w = tw[(long)(s2 * k1) * wi];
-                w.y = -w.y;
-                sh[(g + G * (RI2 * k1 + s2)) * NC + c] = cmul(v[k1], w);
-            }
+            for (int k1 = 0; k1 < 16; ++k1) sh[(g + G * (RI2 * k1 + s2)) * NC + c] = cmul(v[k1], twv[s2 * k1]);
         }
         __syncthreads();
         for (int job = threadIdx.x; job < G * 16 * NC; job += NT) {
