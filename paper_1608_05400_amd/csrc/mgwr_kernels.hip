@@ -1318,10 +1318,12 @@ __global__ __launch_bounds__(256) void k_fft_pass(Grp<FftPass> grp)
     }
 }
 
-// A Stockham pass of radix R = 16 R2 (64, 128 or 256) by one block for NC
-// column pairs: the R-point DFT as two stages (Cooley-Tukey, R = 16 x R2):
-// 16-point DFTs over elements R2 apart in registers, twiddles, an exchange
-// through LDS, then R2-point DFTs, one DFT per thread (16 NC threads).  Rows
+// A Stockham pass of radix R = R1 R2 (64, 128 or 256) by one block for NC
+// column pairs: the R-point DFT as two stages (Cooley-Tukey, R = R1 x R2):
+// R1-point DFTs over elements R2 apart in registers, twiddles, an exchange
+// through LDS, then R2-point DFTs, one DFT per thread (16 NC threads; the
+// passes other than the last take R2 = 16, so that every thread has a DFT of
+// the first stage, the one that reads the input).  Rows
 // of NC pairs are read and written whole: 16 pairs in FP64 (256 bytes), 32
 // in FP32 (256 bytes, 7 % faster than 16 on the largest products) except in
 // the FP32 last passes that scatter into a colour's points (EPI), where 16
@@ -1333,7 +1335,7 @@ template <typename T, int EPI = -1> constexpr int fft_lds_cols()
 }
 template <typename T, int EPI = -1> constexpr int fft_lds_threads() { return 16 * fft_lds_cols<T, EPI>(); }
 
-template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
+template <typename T, typename TIN, int R1, int R2, int SIGN, int SRC, int DST, int EPI>
 __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) void k_fft_lds(Grp<FftPass> grp)
 {
     FftPass a;
@@ -1341,7 +1343,8 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
     grp_select(grp, a, lb, nb);
     using C = typename Cx<T>::v;
     constexpr int E = DST == FD_EPI ? EPI : -1;
-    constexpr int R1 = 16, R = R1 * R2, NC = fft_lds_cols<T, E>(), NT = fft_lds_threads<T, E>();
+    constexpr int R = R1 * R2, NC = fft_lds_cols<T, E>(), NT = fft_lds_threads<T, E>();
+    static_assert(R2 * NC <= NT && R1 * NC <= NT, "one DFT per thread and stage");
     __shared__ C sh[R * NC];
     const int nj = a.L / R;
     const int qblocks = (a.Q + NC - 1) / NC;
@@ -1656,16 +1659,16 @@ static std::vector<int> fft_plan(int L)
     return r;
 }
 
-template <typename T, typename TIN, int R2, int SIGN, int SRC, int DST, int EPI>
+template <typename T, typename TIN, int R1, int R2, int SIGN, int SRC, int DST, int EPI>
 static hipError_t launch_fft_lds(const std::vector<FftPass> &ps, Staging *st, hipStream_t s)
 {
     constexpr int E = DST == FD_EPI ? EPI : -1;
-    constexpr int R = 16 * R2, NC = fft_lds_cols<T, E>(), NT = fft_lds_threads<T, E>();
+    constexpr int R = R1 * R2, NC = fft_lds_cols<T, E>(), NT = fft_lds_threads<T, E>();
     std::vector<long> blocks;
     for (const FftPass &p : ps) blocks.push_back((long)((p.Q + NC - 1) / NC) * (p.L / R));
     return fft_launch(
         [&](dim3 grid, const Grp<FftPass> &g) {
-            hipLaunchKernelGGL((k_fft_lds<T, TIN, R2, SIGN, SRC, DST, EPI>), grid, dim3(NT), 0, s, g);
+            hipLaunchKernelGGL((k_fft_lds<T, TIN, R1, R2, SIGN, SRC, DST, EPI>), grid, dim3(NT), 0, s, g);
         },
         ps, blocks, st);
 }
@@ -1675,9 +1678,9 @@ static hipError_t launch_fft_pass(int R, const std::vector<FftPass> &ps, Staging
 {
     if (R >= 64) {
         if constexpr (DST == FD_CPLX) {
-            if (R == 64) return launch_fft_lds<T, TIN, 4, SIGN, SRC, DST, EPI>(ps, st, s);
-            if (R == 128) return launch_fft_lds<T, TIN, 8, SIGN, SRC, DST, EPI>(ps, st, s);
-            return launch_fft_lds<T, TIN, 16, SIGN, SRC, DST, EPI>(ps, st, s);
+            if (R == 64) return launch_fft_lds<T, TIN, 4, 16, SIGN, SRC, DST, EPI>(ps, st, s);
+            if (R == 128) return launch_fft_lds<T, TIN, 8, 16, SIGN, SRC, DST, EPI>(ps, st, s);
+            return launch_fft_lds<T, TIN, 16, 16, SIGN, SRC, DST, EPI>(ps, st, s);
         }
         return hipErrorInvalidValue;
     }
@@ -1699,7 +1702,7 @@ static hipError_t launch_fft_pass(int R, const std::vector<FftPass> &ps, Staging
 template <typename T, int EPI>
 static hipError_t launch_fft_last(int R, const std::vector<FftPass> &ps, Staging *st, hipStream_t s)
 {
-    if (R == 256) return launch_fft_lds<T, T, 16, 1, FS_CPLX, FD_EPI, EPI>(ps, st, s);
+    if (R == 256) return launch_fft_lds<T, T, 16, 16, 1, FS_CPLX, FD_EPI, EPI>(ps, st, s);
     if (R != 32) return hipErrorInvalidValue;
     std::vector<long> blocks;
     for (const FftPass &p : ps) blocks.push_back(((long)p.Q * (p.L / 32) + 255) / 256);
