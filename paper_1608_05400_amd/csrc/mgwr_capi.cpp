@@ -302,7 +302,7 @@ void drop_program(Program &p)
 void clear_programs(Runner &R)
 {
     if (R.progs.empty()) return;
-    hipStreamSynchronize(R.stream);
+    (void)hipStreamSynchronize(R.stream);   // teardown: nothing to report to
     for (auto &kv : R.progs) drop_program(kv.second);
     R.progs.clear();
     R.lru.clear();
@@ -311,10 +311,10 @@ void clear_programs(Runner &R)
 void release_runner(Runner &R)
 {
     clear_programs(R);
-    if (R.arena) hipFree(R.arena);
-    if (R.norms_dev) hipFree(R.norms_dev);
-    if (R.norms_host) hipHostFree(R.norms_host);
-    if (R.capture) hipStreamDestroy(R.capture);
+    if (R.arena) (void)hipFree(R.arena);
+    if (R.norms_dev) (void)hipFree(R.norms_dev);
+    if (R.norms_host) (void)hipHostFree(R.norms_host);
+    if (R.capture) (void)hipStreamDestroy(R.capture);
     R.prof.release();
     R.arena = nullptr; R.norms_dev = nullptr; R.norms_host = nullptr; R.capture = nullptr;
 }
@@ -396,7 +396,7 @@ int dmalloc(std::vector<void *> &list, void **p, size_t bytes)
 
 void free_list(std::vector<void *> &list)
 {
-    for (void *p : list) hipFree(p);
+    for (void *p : list) (void)hipFree(p);
     list.clear();
 }
 
@@ -1137,7 +1137,7 @@ int run_eager(Runner &R, const Body &body)
         // earlier launches on the stream may still read the arena
         HIPCHK(hipStreamSynchronize(R.stream));
         if (st.host.size() > R.arena_cap) {
-            if (R.arena) hipFree(R.arena);
+            if (R.arena) (void)hipFree(R.arena);
             R.arena = nullptr;
             R.arena_cap = 0;
             HIPCHK(hipMalloc((void **)&R.arena, st.host.size()));
@@ -1188,7 +1188,7 @@ int run_program(Runner &R, const std::string &key, const Body &body)
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(R.capture, &graph);
         if (rc < 0 || e != hipSuccess) {
-            if (graph) hipGraphDestroy(graph);
+            if (graph) (void)hipGraphDestroy(graph);
             drop_program(p);
             if (rc < 0) return rc;
             HIPCHK(e);
@@ -1434,18 +1434,19 @@ int time_cycle(Runner &R, const std::vector<mgwr_ctx *> &hs, int prec, int reps,
     const bool prof = R.prof.on;
     R.prof.on = false;
     for (int r = 0; r < reps && rc == MGWR_OK; ++r) {
-        hipEventRecord(a, R.stream);
-        rc = run_eager(R, body);
-        hipEventRecord(b, R.stream);
-        if (rc == MGWR_OK && hipEventSynchronize(b) == hipSuccess) {
-            float t = 0;
-            hipEventElapsedTime(&t, a, b);
-            ms = std::min(ms, (double)t);
-        }
+        hipError_t e = hipEventRecord(a, R.stream);
+        if (e == hipSuccess) rc = run_eager(R, body);
+        if (e == hipSuccess && rc == MGWR_OK) e = hipEventRecord(b, R.stream);
+        if (e == hipSuccess && rc == MGWR_OK) e = hipEventSynchronize(b);
+        float t = 0;
+        if (e == hipSuccess && rc == MGWR_OK) e = hipEventElapsedTime(&t, a, b);
+        if (e != hipSuccess && rc == MGWR_OK)
+            rc = fail(MGWR_EDEVICE, "autotuner timing: %s", hipGetErrorString(e));
+        if (rc == MGWR_OK) ms = std::min(ms, (double)t);
     }
     R.prof.on = prof;
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     return rc;
 }
 
@@ -1689,9 +1690,10 @@ int mgwr_create(int N, int M, double alpha, double T, int dims, mgwr_t *out)
 int mgwr_destroy(mgwr_t h)
 {
     if (!h) return MGWR_OK;
-    hipSetDevice(h->device);
-    if (h->stream) hipStreamSynchronize(h->stream);
-    hipDeviceSynchronize();
+    // teardown: errors here have no caller to go to
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    (void)hipDeviceSynchronize();
     release_runner(h->run);
     free_list(h->inner_alloc);
     free_list(h->alloc);
@@ -1990,8 +1992,10 @@ int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int
         }
         return run_gemms(ex, {a}, which);
     }();
-    hipStreamSynchronize(h->stream);
+    // the temporaries are freed only after the stream is done with them
+    const hipError_t se = hipStreamSynchronize(h->stream);
     free_list(tmp);
+    if (rc >= 0 && se != hipSuccess) return fail(MGWR_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(se));
     return rc;
 }
 
@@ -2134,7 +2138,7 @@ int mgwr_batch_profile_get(mgwr_batch_t b, int i, mgwr_kernel_record *rec)
 int mgwr_batch_destroy(mgwr_batch_t b)
 {
     if (!b) return MGWR_OK;
-    if (b->run.stream) hipStreamSynchronize(b->run.stream);
+    if (b->run.stream) (void)hipStreamSynchronize(b->run.stream);
     release_runner(b->run);
     for (auto h : b->hs) mgwr_destroy(h);
     delete b;

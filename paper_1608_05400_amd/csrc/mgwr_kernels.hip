@@ -868,7 +868,7 @@ static Geo tiles(int mode, int M, int P, const TileKnobs &kn)
     return g;
 }
 
-static int split_cap(const Geo &g, int mode, int M, int P, int ns, size_t part_cap)
+static int split_cap(int mode, int M, int P, int ns, size_t part_cap)
 {
     const size_t esz = (mode == GM_F64) ? 8 : 4;
     while (ns > 1 && (size_t)ns * M * P * esz > part_cap) --ns;
@@ -891,7 +891,7 @@ static Geo geometry(int mode, int M, int P, int K, int off, int ncoef, size_t pa
         ns = std::min(ns, 64);
         ns = std::min(ns, std::max(1, nk / 8));
     }
-    g.nsplit = split_cap(g, mode, M, P, ns, part_cap);
+    g.nsplit = split_cap(mode, M, P, ns, part_cap);
     g.part_bytes = g.nsplit > 1 ? (size_t)g.nsplit * M * P * ((mode == GM_F64) ? 8 : 4) : 0;
     return g;
 }
@@ -1087,7 +1087,7 @@ hipError_t launch_toep_gemm(const std::vector<GemmArgs> &as, Staging *st, hipStr
                 Geo g = tiles(a.mode, a.M, a.P, a.knobs);
                 int ns = (int)std::ceil(longest[j] / share);
                 ns = std::min(ns, std::min(64, std::max(1, longest[j] / 8)));
-                g.nsplit = split_cap(g, a.mode, a.M, a.P, ns, a.part ? a.part_cap : 0);
+                g.nsplit = split_cap(a.mode, a.M, a.P, ns, a.part ? a.part_cap : 0);
                 geo[idx[j]] = g;
             }
         }
@@ -1196,7 +1196,7 @@ struct Tw32 {
     {
         for (int i = 0; i < 32; ++i) {
             const int qd = i / 8, r = i % 8;
-            double cr, sr;   // angle r pi / 16 in [0, pi / 2)
+            double cr = 0.0, sr = 0.0;   // angle r pi / 16 in [0, pi / 2)
             if (r <= 4) {
                 cr = cx_cos_red(r * kPi / 16);
                 sr = cx_sin_red(r * kPi / 16);
@@ -2085,7 +2085,7 @@ __device__ inline void block_reduce(double &mx, double &sq)
     ssum[threadIdx.x] = sq;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if ((int)threadIdx.x < w) {
             smax[threadIdx.x] = nan_max(smax[threadIdx.x + w], smax[threadIdx.x]);
             ssum[threadIdx.x] += ssum[threadIdx.x + w];
         }
