@@ -1025,7 +1025,7 @@ int cycle(Exec &ex, const std::vector<Task> &ts)
     for (int k = 0; k < gam; ++k) {
         std::vector<Task> down;
         for (const Task &t : fine)
-            if (k < t.H->h->opt.gamma) down.push_back(Task{t.H, t.lev - 1, true});
+            if (k < t.H->h->opt.gamma) down.push_back(Task{t.H, t.lev - 1, k == 0});   // zero only at the first visit
         CHK(cycle(ex, down));
     }
     HIPCHK(launch_xfer(pr, ex.st, ex.s));

@@ -184,14 +184,18 @@ def test_fft_product_every_plan(B, M, P):
 @pytest.mark.parametrize("dims,N,M,alpha", [(1, 127, 200, 0.3), (2, 31, 64, 0.7), (1, 255, 600, 0.5), (2, 63, 520, 0.4)])
 @pytest.mark.parametrize("first", [0, 1])
 @pytest.mark.parametrize("nu", [(1, 1), (0, 1), (2, 1)])
-def test_fft_cycle_matches_oracle(B, dims, N, M, alpha, first, nu):
-    """One plain FP64 cycle with every product on the FFT route, both colour
-    orders and with and without pre-smoothing."""
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_fft_cycle_matches_oracle(B, dims, N, M, alpha, first, nu, gamma):
+    """One plain FP64 V- or W-cycle with every product on the FFT route, both
+    colour orders and with and without pre-smoothing.  In a W-cycle the second
+    visit of a coarse level starts from the first visit's result, not from
+    zero (a regression case: its first half-sweep once took the right-hand
+    side as if the level's iterate were zero)."""
     rng = np.random.default_rng(N + M + first)
     shape = (M, N) if dims == 1 else (M, N, N)
     f, u, g = rng.standard_normal(shape), rng.standard_normal(shape), rng.standard_normal(shape[1:])
-    ref = oracle.vcycle(dims, N, M, alpha, f, u, g=g, nu1=nu[0], nu2=nu[1], first=first)
-    with B.Solver(N, M, alpha, dims=dims, nu1=nu[0], nu2=nu[1], first_colour=first, fft=2) as s:
+    ref = oracle.vcycle(dims, N, M, alpha, f, u, g=g, nu1=nu[0], nu2=nu[1], gamma=gamma, first=first)
+    with B.Solver(N, M, alpha, dims=dims, nu1=nu[0], nu2=nu[1], gamma=gamma, first_colour=first, fft=2) as s:
         U = dev(u)
         s.vcycle(dev(f), U, g=dev(g))
         U = host(U)
