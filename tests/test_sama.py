@@ -1,0 +1,106 @@
+"""Semi-algebraic mode analysis (Section 4): the predicted two-grid factors
+against the paper's Table 2, and the 2M x 2M symbol against the two-grid
+operator assembled as plain dense matrices on a periodic grid, where Fourier
+modes are exact eigenfunctions.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy import linalg
+
+from conftest import load_golden
+from paper_1608_05400_amd import sama
+
+
+@pytest.mark.parametrize("row", load_golden("table2_wcycle_1d.txt"))
+def test_table2_predicted_two_grid_factor(row):
+    """Section 4, Table 2: alpha = 0.4, one pre-smoothing step; the predicted
+    column (the numerical eigenvalues of the symbol, reading in DESIGN)."""
+    l2lam, M, predicted, _measured = row
+    rho = sama.two_grid_factor(0.4, 2.0 ** l2lam, int(M))
+    assert abs(rho - predicted) <= 0.004, rho
+
+
+def test_exact_radius_does_not_depend_on_M():
+    """The symbol is block lower triangular in time with one 2 x 2 diagonal
+    block: its exact spectral radius is that block's for every M, and at M = 1
+    the numerical eigenvalues are exact."""
+    r = [sama.two_grid_factor(0.4, 4.0, M, exact=True) for M in (1, 8, 32)]
+    assert max(r) - min(r) <= 1e-12
+    assert abs(sama.two_grid_factor(0.4, 4.0, 1) - r[0]) <= 1e-12
+
+
+def test_laplacian_symbol_is_the_stencil_on_a_mode():
+    x = np.arange(-3, 4)
+    for theta in (0.3, 1.1, 2.9):
+        phi = np.exp(1j * theta * x)
+        Aphi = 2 * phi[3] - phi[2] - phi[4]
+        assert abs(Aphi - sama.symbol_laplacian(theta) * phi[3]) <= 1e-13
+
+
+def _periodic_two_grid(n, Tm, nu1, nu2, red_parity):
+    """The two-grid error operator on n periodic points (h = 1) as a function
+    on complex arrays e[m, j]: red-black sweeps (red = points of parity
+    red_parity), full weighting, linear interpolation, exact coarse solve."""
+    M = Tm.shape[0]
+    Mt = Tm + 2.0 * np.eye(M)
+
+    def A(e):
+        return Tm @ e + 2.0 * e - np.roll(e, 1, axis=1) - np.roll(e, -1, axis=1)
+
+    def half(e, parity):
+        e = e.copy()
+        for j in range(parity, n, 2):
+            e[:, j] = linalg.solve_triangular(Mt, e[:, (j - 1) % n] + e[:, (j + 1) % n], lower=True)
+        return e
+
+    def sweep(e):
+        return half(half(e, red_parity), 1 - red_parity)
+
+    def restrict(r):
+        return 0.25 * (np.roll(r, 1, axis=1) + 2.0 * r + np.roll(r, -1, axis=1))[:, 0::2]
+
+    def prolong(ec):
+        e = np.zeros((M, n), complex)
+        e[:, 0::2] = ec
+        e[:, 1::2] = 0.5 * (ec + np.roll(ec, -1, axis=1))
+        return e
+
+    def coarse_solve(rc):
+        nc = rc.shape[1]
+        Ac = np.kron(np.eye(nc), Tm) + np.kron(0.25 * (2.0 * np.eye(nc) - np.roll(np.eye(nc), 1, 0)
+                                                       - np.roll(np.eye(nc), -1, 0)), np.eye(M))
+        return np.linalg.solve(Ac, rc.T.reshape(-1)).reshape(nc, M).T
+
+    def E(e):
+        for _ in range(nu1):
+            e = sweep(e)
+        e = e - prolong(coarse_solve(restrict(A(e))))
+        for _ in range(nu2):
+            e = sweep(e)
+        return e
+
+    return E
+
+
+@pytest.mark.parametrize("nu", [(1, 0), (1, 1), (0, 1)])
+def test_symbol_matches_periodic_two_grid_operator(nu):
+    n, M, alpha, lam = 16, 3, 0.6, 2.0
+    Tm = sama.time_matrix(M, alpha, lam)
+    E = _periodic_two_grid(n, Tm, nu[0], nu[1], red_parity=0)
+    j = np.arange(n)
+    for k in (1, 2, 3, 4):
+        t0 = 2 * math.pi * k / n
+        vs = [np.exp(1j * t0 * j), np.exp(1j * (t0 - math.pi) * j)]
+        D = np.zeros((2 * M, 2 * M), complex)
+        for a in range(2):
+            for m in range(M):
+                e = np.zeros((M, n), complex)
+                e[m] = vs[a]
+                out = E(e)
+                for b in range(2):   # coordinates on the two harmonics
+                    D[b * M:(b + 1) * M, a * M + m] = out @ vs[b].conj() / n
+                # the pair of harmonics is invariant
+                back = sum(np.outer(D[b * M:(b + 1) * M, a * M + m], vs[b]) for b in range(2))
+                assert np.abs(out - back).max() <= 1e-12
+        np.testing.assert_allclose(D, sama.two_grid_symbol(t0, Tm, nu[0], nu[1]), atol=1e-12)
