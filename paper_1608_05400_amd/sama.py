@@ -80,3 +80,67 @@ def two_grid_factor(alpha: float, lam: float, M: int, nu1: int = 1, nu2: int = 0
     Tm = time_matrix(M, alpha, lam)
     thetas = np.linspace(math.pi / 2, 0.0, ntheta, endpoint=False)[::-1]
     return max(_radius(two_grid_symbol(t, Tm, nu1, nu2), exact) for t in thetas)
+
+
+# ---------------------------------------------------------------------------
+# 2D (Section 6): the four harmonics theta^00, theta^11, theta^10, theta^01
+# (theta^ab = theta - (a pi, b pi)) of a low frequency theta in (0, pi/2]^2
+# span an invariant space; the operators become 4M x 4M matrices.  The red-
+# black mask e^{i pi (x + y)} pairs theta^00 with theta^11 and theta^10 with
+# theta^01, so each half-sweep acts on those pairs as in 1D, with the
+# splitting M_h = 4/h^2, N_h(theta) = 2 cos theta_x + 2 cos theta_y.
+
+def _harmonics_2d(tx: float, ty: float):
+    return [(tx, ty), (tx - math.pi, ty - math.pi), (tx - math.pi, ty), (tx, ty - math.pi)]
+
+
+def symbol_laplacian_2d(tx: float, ty: float) -> float:
+    """Symbol of the 5-point A_h (h = 1): 4 sin^2(theta_x / 2) + 4 sin^2(theta_y / 2)."""
+    return symbol_laplacian(tx) + symbol_laplacian(ty)
+
+
+def two_grid_symbol_2d(tx: float, ty: float, Tm: np.ndarray, nu1: int = 1, nu2: int = 0) -> np.ndarray:
+    """4M x 4M matrix of the 2D two-grid operator on the harmonics of (tx, ty)."""
+    M = Tm.shape[0]
+    I = np.eye(M)
+    Z = np.zeros((M, M))
+    hs = _harmonics_2d(tx, ty)
+    Mt = Tm + 4.0 * I
+    Sj = [linalg.solve_triangular(Mt, (2.0 * math.cos(a) + 2.0 * math.cos(b)) * I, lower=True) for a, b in hs]
+
+    def half(red: bool) -> np.ndarray:
+        out = np.zeros((4 * M, 4 * M))
+        s = 1.0 if red else -1.0
+        for a, b in ((0, 1), (2, 3)):   # pairs coupled by the colour mask
+            ia, ib = slice(a * M, (a + 1) * M), slice(b * M, (b + 1) * M)
+            out[ia, ia] = 0.5 * (Sj[a] + I)
+            out[ib, ib] = 0.5 * (Sj[b] + I)
+            out[ia, ib] = 0.5 * s * (Sj[b] - I)
+            out[ib, ia] = 0.5 * s * (Sj[a] - I)
+        return out
+
+    S = half(False) @ half(True)
+    w = [0.25 * (1.0 + math.cos(a)) * (1.0 + math.cos(b)) for a, b in hs]
+    R = np.hstack([wk * I for wk in w])
+    P = R.T
+    A = np.block([[Tm + symbol_laplacian_2d(*hs[k]) * I if k == l else Z for l in range(4)] for k in range(4)])
+    Ac = Tm + 0.25 * symbol_laplacian_2d(2.0 * tx, 2.0 * ty) * I
+    C = np.eye(4 * M) - P @ linalg.solve_triangular(Ac, R @ A, lower=True)
+    return np.linalg.matrix_power(S, nu2) @ C @ np.linalg.matrix_power(S, nu1)
+
+
+def _radius_blocks(T: np.ndarray, nb: int, exact: bool) -> float:
+    if exact:
+        M = T.shape[0] // nb
+        idx = [k * M for k in range(nb)]
+        return float(max(abs(np.linalg.eigvals(T[np.ix_(idx, idx)]))))
+    return float(max(abs(np.linalg.eigvals(T))))
+
+
+def two_grid_factor_2d(alpha: float, lam: float, M: int, nu1: int = 1, nu2: int = 0, ntheta: int = 16,
+                       exact: bool = False) -> float:
+    """Predicted 2D two-grid factor: max over (theta_x, theta_y) h in (0, pi/2]^2
+    (ntheta samples per direction)."""
+    Tm = time_matrix(M, alpha, lam)
+    ts = np.linspace(math.pi / 2, 0.0, ntheta, endpoint=False)[::-1]
+    return max(_radius_blocks(two_grid_symbol_2d(a, b, Tm, nu1, nu2), 4, exact) for a in ts for b in ts)

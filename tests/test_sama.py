@@ -104,3 +104,98 @@ def test_symbol_matches_periodic_two_grid_operator(nu):
                 back = sum(np.outer(D[b * M:(b + 1) * M, a * M + m], vs[b]) for b in range(2))
                 assert np.abs(out - back).max() <= 1e-12
         np.testing.assert_allclose(D, sama.two_grid_symbol(t0, Tm, nu[0], nu[1]), atol=1e-12)
+
+
+def _periodic_two_grid_2d(n, Tm, nu1, nu2):
+    """The 2D two-grid error operator on an n x n periodic grid (h = 1) as a
+    function on complex arrays e[m, y, x]: red-black sweeps (red: x + y even,
+    first), 9-point full weighting, bilinear interpolation, exact coarse solve."""
+    M = Tm.shape[0]
+    Mt = Tm + 4.0 * np.eye(M)
+
+    def nbr(e):
+        return (np.roll(e, 1, axis=2) + np.roll(e, -1, axis=2) + np.roll(e, 1, axis=1) + np.roll(e, -1, axis=1))
+
+    def A(e, scale=1.0):
+        return np.einsum("ab,byx->ayx", Tm, e) + scale * (4.0 * e - nbr(e))
+
+    def half(e, parity):
+        e = e.copy()
+        for y in range(n):
+            for x in range(n):
+                if (x + y) % 2 == parity:
+                    s = (e[:, y, (x - 1) % n] + e[:, y, (x + 1) % n] + e[:, (y - 1) % n, x] + e[:, (y + 1) % n, x])
+                    e[:, y, x] = linalg.solve_triangular(Mt, s, lower=True)
+        return e
+
+    def sweep(e):
+        return half(half(e, 0), 1)
+
+    def restrict(r):
+        rx = 0.25 * (np.roll(r, 1, axis=2) + 2.0 * r + np.roll(r, -1, axis=2))
+        rxy = 0.25 * (np.roll(rx, 1, axis=1) + 2.0 * rx + np.roll(rx, -1, axis=1))
+        return rxy[:, 0::2, 0::2]
+
+    def prolong(ec):
+        ex = np.zeros((M, ec.shape[1], n), complex)
+        ex[:, :, 0::2] = ec
+        ex[:, :, 1::2] = 0.5 * (ec + np.roll(ec, -1, axis=2))
+        e = np.zeros((M, n, n), complex)
+        e[:, 0::2, :] = ex
+        e[:, 1::2, :] = 0.5 * (ex + np.roll(ex, -1, axis=1))
+        return e
+
+    def coarse_solve(rc):
+        nc = rc.shape[1]
+        cols = []
+        for k in range(M * nc * nc):   # the coarse operator T_M + A_2h as a dense matrix
+            u = np.zeros(M * nc * nc)
+            u[k] = 1.0
+            cols.append(A(u.reshape(M, nc, nc), 0.25).reshape(-1))
+        return np.linalg.solve(np.array(cols).T, rc.reshape(-1)).reshape(rc.shape)
+
+    def E(e):
+        for _ in range(nu1):
+            e = sweep(e)
+        e = e - prolong(coarse_solve(restrict(A(e))))
+        for _ in range(nu2):
+            e = sweep(e)
+        return e
+
+    return E
+
+
+@pytest.mark.parametrize("nu", [(1, 0), (1, 1)])
+def test_symbol_2d_matches_periodic_two_grid_operator(nu):
+    n, M, alpha, lam = 8, 2, 0.4, 1.5
+    Tm = sama.time_matrix(M, alpha, lam)
+    E = _periodic_two_grid_2d(n, Tm, nu[0], nu[1])
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    for kx, ky in ((1, 1), (1, 2), (2, 1)):
+        tx, ty = 2 * math.pi * kx / n, 2 * math.pi * ky / n
+        hs = [(tx, ty), (tx - math.pi, ty - math.pi), (tx - math.pi, ty), (tx, ty - math.pi)]
+        vs = [np.exp(1j * (a * x + b * y)) for a, b in hs]
+        D = np.zeros((4 * M, 4 * M), complex)
+        for a in range(4):
+            for m in range(M):
+                e = np.zeros((M, n, n), complex)
+                e[m] = vs[a]
+                out = E(e)
+                for b in range(4):
+                    D[b * M:(b + 1) * M, a * M + m] = np.einsum("myx,yx->m", out, vs[b].conj()) / n ** 2
+                back = sum(np.einsum("m,yx->myx", D[b * M:(b + 1) * M, a * M + m], vs[b]) for b in range(4))
+                assert np.abs(out - back).max() <= 1e-12
+        np.testing.assert_allclose(D, sama.two_grid_symbol_2d(tx, ty, Tm, nu[0], nu[1]), atol=1e-12)
+
+
+def test_2d_factors_bounded():
+    """Section 6: the 2D two-grid factors for one smoothing step stay below
+    0.25 over lambda and the fractional order (the exact radius, which does
+    not depend on M)."""
+    rho = {(alpha, l2): sama.two_grid_factor_2d(alpha, 2.0 ** l2, 4, ntheta=12, exact=True)
+           for alpha in (0.1, 0.5, 0.9) for l2 in (-8, -4, 0, 4, 8)}
+    assert max(rho.values()) <= 0.25, rho
+    # and, against lambda = tau^alpha Gamma(2 - alpha) / h^2, they hardly
+    # depend on the fractional order
+    for l2 in (-8, -4, 0, 4, 8):
+        assert max(abs(rho[(a, l2)] - rho[(0.5, l2)]) for a in (0.1, 0.9)) <= 0.01
