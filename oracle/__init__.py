@@ -57,6 +57,7 @@ def _load():
         lib.orc_direct_solve.argtypes = [ii, ii, ii, dd, dd, dd, _D, _D, _D, ii]
         lib.orc_modal_solve.argtypes = [ii, ii, ii, dd, dd, dd, ii, _I, _I, _D, _D, _D]
         lib.orc_modal_eval.argtypes = [ii, ii, ii, dd, ii, _I, _I, _D, ii, _I, _D]
+        lib.orc_mittag_leffler.argtypes = [dd, ii, _D, _D]
         _lib = lib
     return _lib
 
@@ -185,3 +186,21 @@ def modal_grid(dims, N, M, kx, v, ky=None, L=1.0):
                           indexing="ij")
     pts = np.stack([m.ravel(), n.ravel(), l.ravel()], axis=1)
     return modal_eval(dims, N, M, kx, v, pts, ky, L).reshape(M, N, N)
+
+
+def mittag_leffler(alpha, z):
+    """E_alpha(z) by its defining series (Section 7), for |z| <= 1."""
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+    if np.abs(z).max(initial=0.0) > 1.0:
+        raise ValueError("the series is summed for |z| <= 1 only")
+    out = np.zeros_like(z)
+    _load().orc_mittag_leffler(alpha, z.size, _dp(z), _dp(out))
+    return out
+
+
+def paper_test1_exact(N, M, alpha, T=1.0):
+    """Exact solution E_alpha(-t^alpha) sin x of the first test problem of
+    Section 7 (x in [0, pi], f = 0, g = sin x) on the grid, [M, N]."""
+    t = T * np.arange(1, M + 1) / M
+    x = np.pi * np.arange(1, N + 1) / (N + 1)
+    return np.outer(mittag_leffler(alpha, -t ** alpha), np.sin(x))

@@ -96,3 +96,32 @@ def test_table2_wcycle_asymptotic_factor(B, row, fft):
     fac = (norms[-1] / norms[-6]) ** (1 / 5)
     print(f"log2 lambda {l2lam} M {M} fft {fft}: factor {fac:.4f} (paper {measured})")
     assert abs(fac - measured) <= 0.012, fac
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("alpha", [0.5, 0.7])
+def test_first_test_problem_error_decays_like_tau_alpha(B, alpha, prec):
+    """Section 7, first test problem solved on the GPU (V(0,1), odd points
+    first) for M = 64, 256, 1024: the maximum error against the exact
+    solution E_alpha(-t^alpha) sin x is the discrete solution's (oracle
+    direct solve) and decays like tau^alpha."""
+    import oracle
+    N = 255
+    x = np.pi * np.arange(1, N + 1) / (N + 1)
+    g = np.sin(x)
+    errs = []
+    for M in (64, 256, 1024):
+        exact = oracle.paper_test1_exact(N, M, alpha)
+        ref = oracle.direct_solve(1, N, M, alpha, np.zeros((M, N)), g=g, L=math.pi)
+        with B.Solver(N, M, alpha, dims=1, nu1=0, nu2=1, first_colour=1, L=math.pi, precision=prec) as s:
+            U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+            info = s.solve(dev(np.zeros((M, N))), U, g=dev(g), tol=1e-12)
+            torch.cuda.synchronize()
+            U = U.cpu().numpy()
+        assert info["rc"] in (0, 2), info
+        err, err_ref = np.abs(U - exact).max(), np.abs(ref - exact).max()
+        print(f"alpha {alpha} {prec} M {M}: max error {err:.4e} (discrete solution {err_ref:.4e})")
+        assert abs(err - err_ref) <= 1e-9
+        errs.append(err)
+    orders = np.log(np.array(errs[:-1]) / np.array(errs[1:])) / np.log(4.0)
+    assert abs(orders[1] - alpha) <= 0.05, orders

@@ -393,3 +393,31 @@ def test_table2_wcycle_asymptotic_factor(row):
         norms.append(np.linalg.norm(oracle.residual(1, N, M, alpha, f, u, T=T)))
     fac = (norms[-1] / norms[-6]) ** (1 / 5)
     assert abs(fac - measured) <= 0.012, fac
+
+
+# --------------------------------------------------------------------------
+# first test problem of Section 7: exact solution E_alpha(-t^alpha) sin x
+
+def test_mittag_leffler_closed_forms():
+    """The series against closed forms: E_1(-t) = e^-t, E_1/2(-sqrt t) =
+    e^t erfc(sqrt t), E_2(-t^2) = cos t, E_a(0) = 1."""
+    from scipy import special
+    t = np.linspace(0.0, 1.0, 21)
+    assert np.abs(oracle.mittag_leffler(1.0, -t) - np.exp(-t)).max() <= 1e-15
+    assert np.abs(oracle.mittag_leffler(0.5, -np.sqrt(t)) - np.exp(t) * special.erfc(np.sqrt(t))).max() <= 1e-14
+    assert np.abs(oracle.mittag_leffler(2.0, -t ** 2) - np.cos(t)).max() <= 1e-15
+    assert oracle.mittag_leffler(0.3, [0.0])[0] == 1.0
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.7])
+def test_first_test_problem_time_order_alpha(alpha):
+    """Section 7: the maximum error of the discrete solution of the first test
+    problem against E_alpha(-t^alpha) sin x decays like tau^alpha (h fine)."""
+    N = 255
+    x = np.pi * np.arange(1, N + 1) / (N + 1)
+    errs = []
+    for M in (64, 256, 1024):
+        u = oracle.direct_solve(1, N, M, alpha, np.zeros((M, N)), g=np.sin(x), L=math.pi)
+        errs.append(np.abs(u - oracle.paper_test1_exact(N, M, alpha)).max())
+    orders = np.log(np.array(errs[:-1]) / np.array(errs[1:])) / np.log(4.0)
+    assert orders[1] >= orders[0] - 0.01 and abs(orders[1] - alpha) <= 0.05, orders
