@@ -402,7 +402,7 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on one GPU (one problem or one batch per GPU); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -347,7 +347,7 @@ def test_steady_limit_red_black_two_grid_is_exact_1d():
 def test_table3_v01_iterations_1d(row):
     """Reading: the printed V(0,1) figures are reproduced with the odd points
     (the fine-only points) relaxed first; with the even-first order of the
-    text the factor is about 0.2 (both measured; see DESIGN.md)."""
+    text the factor is about 0.2 (both measured)."""
     alpha, S, its_paper, fac_paper = row
     S = int(S)
     w = W.paper_test1(N=S - 1, M=S, alpha=alpha)

@@ -15,7 +15,7 @@ from paper_1608_05400_amd import sama
 @pytest.mark.parametrize("row", load_golden("table2_wcycle_1d.txt"))
 def test_table2_predicted_two_grid_factor(row):
     """Section 4, Table 2: alpha = 0.4, one pre-smoothing step; the predicted
-    column (the numerical eigenvalues of the symbol, reading in DESIGN)."""
+    column, which the numerically computed eigenvalues of the symbol match."""
     l2lam, M, predicted, _measured = row
     rho = sama.two_grid_factor(0.4, 2.0 ** l2lam, int(M))
     assert abs(rho - predicted) <= 0.004, rho
