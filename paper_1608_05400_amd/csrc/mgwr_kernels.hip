@@ -134,14 +134,14 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
         return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + pb];
     } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C || EPI == EPI_RESID_R) {
         // the stencil part of the residual (as OpPost), fused; no load
-        // behind a branch (without g, F stands in for it and is not used;
-        // diag = 0 subtracts an exact zero)
+        // behind a divergent branch (g and cd are read only when there is an
+        // initial condition, a launch-wide choice; diag = 0 subtracts an
+        // exact zero)
         if constexpr (EPI == EPI_RESID_C || EPI == EPI_RESID_R) p = colour_point(e.dims, e.n, e.colour, p);
         const long k = (long)i * e.ldu;
         const GLOBAL double *Uk = gview<double>(e.U) + k;
-        const double gv = gview<double>(e.g ? e.g : e.F)[p], cdv = gview<double>(e.cd)[i];
         double rhs = gview<double>(e.F)[k + p];
-        if (e.g) rhs += cdv * gv;
+        if (e.g) rhs += gview<double>(e.cd)[i] * gview<double>(e.g)[p];
         rhs -= e.diag * Uk[p];
         if constexpr (EPI == EPI_RESID_DD) {
             double shi, slo;
@@ -190,10 +190,16 @@ __device__ inline void resid_pre_pair_1d(const EpiArgs &e, int i, int p, double 
     const long k = (long)i * e.ldu;
     const int pl = p > 0 ? p - 1 : p, p1 = min(p + S, n - 1), p2 = min(p + S + 1, n - 1), pm = min(p + 1, n - 1);
     const GLOBAL double *Uk = gview<double>(e.U) + k, *Fk = gview<double>(e.F) + k;
-    const GLOBAL double *g = gview<double>(e.g ? e.g : e.F);
+    const GLOBAL double *g = gview<double>(e.g);
     double uL = Uk[pl], u0 = Uk[p], u1 = Uk[p1], uR = Uk[p2];
     const double uM = (S == 2) ? Uk[pm] : u1;   // right of p (and left of p + 2)
-    const double f0 = Fk[p], f1 = Fk[p1], g0 = g[p], g1 = g[p1], cdv = gview<double>(e.cd)[i];
+    const double f0 = Fk[p], f1 = Fk[p1];
+    double g0 = 0.0, g1 = 0.0, cdv = 0.0;
+    if (e.g) {   // a launch-wide choice
+        g0 = g[p];
+        g1 = g[p1];
+        cdv = gview<double>(e.cd)[i];
+    }
     double lL = 0.0, l0 = 0.0, l1 = 0.0, lR = 0.0, lM = 0.0;
     if constexpr (DD) {
         const GLOBAL double *Lk = gview<double>(e.lo) + k;
