@@ -58,6 +58,8 @@ def _load():
         lib.orc_modal_solve.argtypes = [ii, ii, ii, dd, dd, dd, ii, _I, _I, _D, _D, _D]
         lib.orc_modal_eval.argtypes = [ii, ii, ii, dd, ii, _I, _I, _D, ii, _I, _D]
         lib.orc_mittag_leffler.argtypes = [dd, ii, _D, _D]
+        lib.orc_nl_solve.argtypes = [ii, ii, dd, dd, dd, dd, ii, ii, ii, dd, ii, _D, _D, _D]
+        lib.orc_nl_solve.restype = ii
         _lib = lib
     return _lib
 
@@ -204,3 +206,14 @@ def paper_test1_exact(N, M, alpha, T=1.0):
     t = T * np.arange(1, M + 1) / M
     x = np.pi * np.arange(1, N + 1) / (N + 1)
     return np.outer(mittag_leffler(alpha, -t ** alpha), np.sin(x))
+
+
+def nl_solve(N, M, alpha, f, c=1.0, q=1.0, nu1=0, nu2=1, first=1, tol=1e-10, maxit=60, T=1.0):
+    """Waveform relaxation FAS for the nonlinear problem of Section 7
+    (D(u) = 1 + q u^2, convection c u_x, zero initial and boundary values);
+    returns (u, hist)."""
+    f = _f64(f)
+    u = np.zeros((M, N))
+    hist = np.zeros(maxit + 1)
+    its = _load().orc_nl_solve(N, M, alpha, T, c, q, nu1, nu2, first, tol, maxit, _dp(f), _dp(u), _dp(hist))
+    return u, hist[:its + 1]

@@ -513,3 +513,124 @@ void orc_mittag_leffler(double a, int n, const double *z, double *out)
         out[i] = s;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Nonlinear problem of Section 7: D_t u = (D(u) u_x)_x + c u_x + f on (0, 1)
+ * with homogeneous Dirichlet values and a zero initial condition, D(u) =
+ * 1 + u^2.  Discretisation: the L1 scheme in time; the diffusion term with
+ * the half-point coefficients a_{n+-1/2} = (D(u_{n+-1}) + D(u_n)) / 2; the
+ * convection term by upwinding (c > 0 carries information from the right,
+ * so u_x is the forward difference).  Solver: the waveform relaxation FAS
+ * method with red-black nonlinear Gauss-Seidel (each point's whole time line
+ * solved with its neighbours fixed, level by level with Newton's method),
+ * full weighting for the residual and the solution, linear interpolation of
+ * the coarse correction, V(nu1, nu2) cycles.  1D only; points n = 1..N.
+ * D(u) = 1 + q u^2 with q = 1 as in Section 7 (q = 0: the linear problem). */
+static double nl_q = 1.0;
+static double nl_D(double v) { return 1.0 + nl_q * v * v; }
+
+/* N(u) at every point: (T_M u)_n + stencil terms (the discrete operator). */
+static void nl_apply(int N, int M, double h, double cc, const double *r, const double *u, double *out)
+{
+    for (int m = 0; m < M; ++m)
+        for (int n = 1; n <= N; ++n) {
+            double s = 0.0;
+            for (int j = 0; j <= m; ++j) s += r[m - j] * u[(size_t)j * N + (n - 1)];
+            const double *v = u + (size_t)m * N;
+            double uc = v[n - 1], ul = at1(v, N, n - 1), ur = at1(v, N, n + 1);
+            double ap = 0.5 * (nl_D(ur) + nl_D(uc)), am = 0.5 * (nl_D(ul) + nl_D(uc));
+            s -= (ap * (ur - uc) - am * (uc - ul)) / (h * h);
+            s -= cc * (ur - uc) / h;
+            out[(size_t)m * N + (n - 1)] = s;
+        }
+}
+
+/* One half-sweep over the points of one colour (0: even n, 1: odd n). */
+static void nl_half_sweep(int N, int M, double h, double cc, const double *r, int colour, const double *f, double *u)
+{
+    for (int n = (colour == 0) ? 2 : 1; n <= N; n += 2) {
+        for (int m = 0; m < M; ++m) {
+            double hist = 0.0;
+            for (int j = 0; j < m; ++j) hist += r[m - j] * u[(size_t)j * N + (n - 1)];
+            const double *row = u + (size_t)m * N;
+            const double ul = at1(row, N, n - 1), ur = at1(row, N, n + 1), fm = f[(size_t)m * N + (n - 1)];
+            double v = row[n - 1];
+            for (int it = 0; it < 50; ++it) {
+                double ap = 0.5 * (nl_D(ur) + nl_D(v)), am = 0.5 * (nl_D(ul) + nl_D(v));
+                double g = r[0] * v + hist - (ap * (ur - v) - am * (v - ul)) / (h * h) - cc * (ur - v) / h - fm;
+                double dg = r[0] + (ap + am - nl_q * v * (ur - v) + nl_q * v * (v - ul)) / (h * h) + cc / h;
+                double dv = g / dg;
+                v -= dv;
+                if (fabs(dv) <= 1e-15 * (1.0 + fabs(v))) break;
+            }
+            u[(size_t)m * N + (n - 1)] = v;
+        }
+    }
+}
+
+static void nl_vcycle(int N, int M, double alpha, double T, double cc, int nu1, int nu2, int first,
+                      const double *f, double *u)
+{
+    double c_unused, *d = (double *)malloc(sizeof(double) * (M + 1)), *r = (double *)malloc(sizeof(double) * M);
+    orc_l1_coeffs(M, alpha, T, &c_unused, d, r);
+    const double h = 1.0 / (N + 1);
+    if (N == 1) {   /* one point: one half-sweep is its exact solve */
+        nl_half_sweep(N, M, h, cc, r, 1, f, u);
+        free(d); free(r);
+        return;
+    }
+    for (int i = 0; i < nu1; ++i) {
+        nl_half_sweep(N, M, h, cc, r, first, f, u);
+        nl_half_sweep(N, M, h, cc, r, 1 - first, f, u);
+    }
+    const int Nc = (N - 1) / 2;
+    size_t sf = (size_t)M * N, sc = (size_t)M * Nc;
+    double *R = (double *)malloc(sizeof(double) * sf), *uc = (double *)malloc(sizeof(double) * sc);
+    double *uc0 = (double *)malloc(sizeof(double) * sc), *fc = (double *)malloc(sizeof(double) * sc);
+    double *rc = (double *)malloc(sizeof(double) * sc);
+    nl_apply(N, M, h, cc, r, u, R);
+    for (size_t i = 0; i < sf; ++i) R[i] = f[i] - R[i];
+    orc_restrict(1, N, M, R, rc);
+    orc_restrict(1, N, M, u, uc0);
+    double *rcoarse = (double *)malloc(sizeof(double) * M);
+    orc_l1_coeffs(M, alpha, T, &c_unused, d, rcoarse);
+    nl_apply(Nc, M, 1.0 / (Nc + 1), cc, rcoarse, uc0, fc);
+    for (size_t i = 0; i < sc; ++i) { fc[i] += rc[i]; uc[i] = uc0[i]; }
+    nl_vcycle(Nc, M, alpha, T, cc, nu1, nu2, first, fc, uc);
+    for (size_t i = 0; i < sc; ++i) uc[i] -= uc0[i];
+    orc_prolong_add(1, Nc, M, uc, u);
+    for (int i = 0; i < nu2; ++i) {
+        nl_half_sweep(N, M, h, cc, r, first, f, u);
+        nl_half_sweep(N, M, h, cc, r, 1 - first, f, u);
+    }
+    free(R); free(uc); free(uc0); free(fc); free(rc); free(rcoarse); free(d); free(r);
+}
+
+/* FAS iteration from u = 0 until the max-norm residual is reduced by tol
+ * (Section 7); returns the cycles done, hist[0..its] the residual norms.
+ * Not reentrant (q is held in a file-scope variable for the recursion). */
+int orc_nl_solve(int N, int M, double alpha, double T, double cc, double q, int nu1, int nu2, int first,
+                 double tol, int maxit, const double *f, double *u, double *hist)
+{
+    nl_q = q;
+    size_t sz = (size_t)M * N;
+    double c_unused, *d = (double *)malloc(sizeof(double) * (M + 1)), *r = (double *)malloc(sizeof(double) * M);
+    orc_l1_coeffs(M, alpha, T, &c_unused, d, r);
+    const double h = 1.0 / (N + 1);
+    double *R = (double *)malloc(sizeof(double) * sz);
+    for (size_t i = 0; i < sz; ++i) u[i] = 0.0;
+    double r0 = 0.0;
+    int it = 0;
+    for (;;) {
+        nl_apply(N, M, h, cc, r, u, R);
+        double rn = 0.0;
+        for (size_t i = 0; i < sz; ++i) rn = fmax(rn, fabs(f[i] - R[i]));
+        if (hist) hist[it] = rn;
+        if (it == 0) r0 = rn;
+        if (rn <= tol * r0 || it >= maxit) break;
+        nl_vcycle(N, M, alpha, T, cc, nu1, nu2, first, f, u);
+        ++it;
+    }
+    free(R); free(d); free(r);
+    return it;
+}

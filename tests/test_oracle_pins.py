@@ -421,3 +421,56 @@ def test_first_test_problem_time_order_alpha(alpha):
         errs.append(np.abs(u - oracle.paper_test1_exact(N, M, alpha)).max())
     orders = np.log(np.array(errs[:-1]) / np.array(errs[1:])) / np.log(4.0)
     assert orders[1] >= orders[0] - 0.01 and abs(orders[1] - alpha) <= 0.05, orders
+
+
+# --------------------------------------------------------------------------
+# nonlinear problem of Section 7 (waveform relaxation FAS)
+
+def test_fas_linear_case_is_the_direct_solution():
+    """With D = 1 and no convection the problem is the linear one: FAS gives
+    the exact discrete solution of the linear oracle."""
+    N, M, alpha = 31, 20, 0.6
+    f = np.random.default_rng(2).standard_normal((M, N))
+    u, _ = oracle.nl_solve(N, M, alpha, f, c=0.0, q=0.0, tol=1e-13)
+    assert np.abs(u - oracle.direct_solve(1, N, M, alpha, f)).max() <= 1e-12
+
+
+def test_fas_solution_solves_the_assembled_nonlinear_system():
+    """Brute force: the global nonlinear system written out from the
+    discretisation (L1 history, half-point diffusion coefficients, upwind
+    convection) and solved by a library Newton-type solver."""
+    from scipy import optimize
+    N, M, alpha, c = 7, 5, 0.4, 1.0
+    h = 1.0 / (N + 1)
+    _, _, r = oracle.l1_coeffs(M, alpha)
+    F = np.ones((M, N))
+
+    def res(x):
+        Z = np.zeros((M, N + 2))
+        Z[:, 1:-1] = x.reshape(M, N)
+        D = 1.0 + Z ** 2
+        out = np.zeros((M, N))
+        for m in range(M):
+            hist = sum(r[m - j] * Z[j, 1:-1] for j in range(m + 1))
+            ap, am = 0.5 * (D[m, 2:] + D[m, 1:-1]), 0.5 * (D[m, :-2] + D[m, 1:-1])
+            diff = (ap * (Z[m, 2:] - Z[m, 1:-1]) - am * (Z[m, 1:-1] - Z[m, :-2])) / h ** 2
+            out[m] = hist - diff - c * (Z[m, 2:] - Z[m, 1:-1]) / h - F[m]
+        return out.ravel()
+
+    ref = optimize.fsolve(res, np.zeros(M * N), xtol=1e-14).reshape(M, N)
+    assert np.abs(res(ref.ravel())).max() <= 1e-12
+    u, _ = oracle.nl_solve(N, M, alpha, F, tol=1e-13)
+    assert np.abs(u - ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("row", load_golden("table5_fas_1d.txt"))
+def test_table5_fas_iterations(row):
+    """Section 7, Table 5: V(0,1) FAS cycles, the odd points relaxed first (as
+    for Table 3)."""
+    alpha, S, its_paper, fac_paper = row
+    S = int(S)
+    u, hist = oracle.nl_solve(S - 1, S, alpha, np.ones((S, S - 1)))
+    its = len(hist) - 1
+    fac = (hist[-1] / hist[0]) ** (1.0 / its)
+    assert abs(its - its_paper) <= 1
+    assert fac <= fac_paper + 0.035
