@@ -121,6 +121,28 @@ typedef struct {
     double hist[128];   /* residual norms after 0..min(iters,127) cycles                      */
 } mgwr_info;
 
+/* Nonlinear problem of Section 7 (anomalous diffusion in porous media):
+ *   D_t^alpha u = (D(u) u_x)_x + c u_x + f on (0, 1) x (0, T],
+ * zero initial and Dirichlet values, D(u) = 1 + q u^2 (the paper: q = 1,
+ * c = 1, f = 1).  Discretised by the L1 scheme in time, the diffusion term
+ * with half-point coefficients (D(u_{n+-1}) + D(u_n)) / 2 and the convection
+ * term upwinded (forward difference: c >= 0).  Solved by the waveform
+ * relaxation FAS method (Section 7): V(nu1, nu2) cycles, red-black nonlinear
+ * Gauss-Seidel smoothing (each point's time line solved with its neighbours
+ * fixed, level by level by Newton's method), full weighting of residual and
+ * solution, linear interpolation of the correction; colour 0 = even n,
+ * first_colour relaxed first (1 reproduces Table 5), starting from u = 0,
+ * until the max-norm residual is reduced by tol or maxit cycles are done.
+ * N = 2^k - 1, 1 <= M <= 4096; f, u: DEVICE [M][N] FP64 (u is overwritten with the iterate;
+ * the caller owns both); stream: a hipStream_t or NULL.  The call allocates
+ * its hierarchy on the device, frees it before returning and synchronises
+ * the stream.  Returns MGWR_OK, MGWR_NOT_CONVERGED, or a negative code
+ * (MGWR_EINVAL for bad arguments, MGWR_ENONFINITE for a NaN/Inf residual);
+ * info (host, may be NULL) receives iterations and residual history. */
+int mgwr_fas_solve(int N, int M, double alpha, double T, double c, double q, int nu1, int nu2,
+                   int first_colour, const double *f, double *u, double tol, int maxit, void *stream,
+                   mgwr_info *info);
+
 /* Fill *o with the defaults listed above.  Host only; never fails. */
 int mgwr_default_options(mgwr_options *o);
 

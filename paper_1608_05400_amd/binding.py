@@ -32,7 +32,7 @@ EXPORTED = [
     "mgwr_profile_enable", "mgwr_profile_count", "mgwr_profile_get", "mgwr_kernel_name",
     "mgwr_last_error", "mgwr_autotune", "mgwr_get_tuning", "mgwr_batch_autotune",
     "mgwr_batch_get_tuning", "mgwr_batch_profile_enable", "mgwr_batch_profile_count",
-    "mgwr_batch_profile_get",
+    "mgwr_batch_profile_get", "mgwr_fas_solve",
 ]
 
 
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
     lib.mgwr_batch_profile_enable.argtypes = [h, I]
     lib.mgwr_batch_profile_count.argtypes = [h]
     lib.mgwr_batch_profile_get.argtypes = [h, I, P(KernelRecord)]
+    lib.mgwr_fas_solve.argtypes = [I, I, D, D, D, D, I, I, I, VP, VP, D, I, VP, P(Info)]
     lib.mgwr_kernel_name.argtypes = [I]
     lib.mgwr_kernel_name.restype = ctypes.c_char_p
     lib.mgwr_last_error.restype = ctypes.c_char_p
@@ -184,6 +185,23 @@ def l1_weights(M: int, alpha: float, T: float = 1.0):
     _check(load().mgwr_l1_weights(M, alpha, T, ctypes.byref(c),
                                   r.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), False)
     return c.value, r
+
+
+def fas_solve(f, u, alpha: float, c: float = 1.0, q: float = 1.0, nu1: int = 0, nu2: int = 1,
+              first_colour: int = 1, tol: float = 1e-10, maxit: int = 60, T: float = 1.0,
+              raise_on_error: bool = True):
+    """Waveform relaxation FAS for the nonlinear problem of Section 7
+    (mgwr_fas_solve); f, u: device FP64 [M, N] tensors, u receives the
+    solution.  Returns the info dict with the return code under "rc"."""
+    M, N = u.shape
+    info = Info()
+    rc = load().mgwr_fas_solve(N, M, alpha, T, c, q, nu1, nu2, first_colour, _ptr(f, "f", (M, N)),
+                               _ptr(u, "u", (M, N)), tol, maxit, _stream(), ctypes.byref(info))
+    if rc < 0 and raise_on_error:
+        raise MgwrError(rc, last_error())
+    d = info.as_dict()
+    d["rc"] = rc
+    return d
 
 
 def kernel_name(kernel: int) -> str:

@@ -67,6 +67,13 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+}  // namespace
+
+// Error reporting for the other translation units (mgwr_last_error).
+int mgwr::set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+namespace {
+
 #define HIPCHK(expr)                                                                            \
     do {                                                                                        \
         hipError_t e_ = (expr);                                                                 \

@@ -1,0 +1,306 @@
+// Waveform relaxation FAS for the nonlinear problem of Section 7:
+//   D_t^alpha u = (D(u) u_x)_x + c u_x + f on (0, 1), zero initial and
+//   boundary values, D(u) = 1 + q u^2 (q = 1 in the paper).
+// Discretisation: the L1 scheme in time (lower-triangular Toeplitz T_M with
+// first column r); diffusion with the half-point coefficients
+// a_{n+-1/2} = (D(u_{n+-1}) + D(u_n)) / 2; the convection term upwinded
+// (c >= 0 carries information from the right: forward difference).
+// Solver: FAS V(nu1, nu2) cycles over the space hierarchy N_l = 2^(l+1) - 1;
+// smoother: red-black nonlinear Gauss-Seidel in which a point's whole time
+// line is solved with its neighbours fixed, level by level (T_M is lower
+// triangular) by Newton's method; full weighting restricts the residual and
+// the solution, linear interpolation carries the coarse correction.
+//
+// Points are numbered n = 1..N in space (array index n - 1), rows m = 0..M-1
+// hold t_{m+1}; colour 0 is even n, colour 1 odd n (the coarse points are
+// the even ones).  The smoother gives one wave to each point of a colour:
+// the time lines are sequential, the points of a colour independent.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "mgwr.h"
+#include "mgwr_internal.h"
+
+namespace {
+
+constexpr int kNlThreads = 256;
+constexpr int kNlMaxM = 4096;   // 2 M doubles of LDS per smoother block
+
+__device__ inline double nl_D(double q, double v) { return 1.0 + q * v * v; }
+
+// Value of point n (1-based) of a row, zero outside 1..N (Dirichlet).
+__device__ inline double nl_at(const double *row, int N, int n) { return (n >= 1 && n <= N) ? row[n - 1] : 0.0; }
+
+// Half-sweep of one colour: the wave (one 64-lane block) of point n solves,
+// for m = 0..M-1,
+//   r_1 v + sum_{j<m} r_{m-j+1} u_{n,j} - [a+(v)(u_{n+1} - v) - a-(v)(v - u_{n-1})] / h^2
+//     - c (u_{n+1} - v) / h = f_{n,m}
+// for v = u_{n,m} by Newton's method from the current value.  The lanes
+// split each history sum; the point's new time line and the coefficients
+// are kept in LDS (2 M doubles), so the sum reads no global memory.
+__global__ __launch_bounds__(64) void k_nl_sweep(int N, int M, double h, double c, double q, const double *r,
+                                                 int colour, const double *f, double *u)
+{
+    extern __shared__ double lds[];
+    double *rs = lds, *tl = lds + M;
+    const int lane = threadIdx.x;
+    const int n = (colour == 0 ? 2 : 1) + 2 * (int)blockIdx.x;   // the grid holds the colour's points only
+    for (int j = lane; j < M; j += 64) rs[j] = r[j];
+    __syncthreads();
+    const double ih2 = 1.0 / (h * h);
+    for (int m = 0; m < M; ++m) {
+        double part = 0.0;
+        for (int j = lane; j < m; j += 64) part += rs[m - j] * tl[j];
+        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+        const double hist = part;
+        const double *row = u + (size_t)m * N;
+        const double ul = nl_at(row, N, n - 1), ur = nl_at(row, N, n + 1), fm = f[(size_t)m * N + (n - 1)];
+        double v = row[n - 1];
+        for (int it = 0; it < 50; ++it) {
+            const double ap = 0.5 * (nl_D(q, ur) + nl_D(q, v)), am = 0.5 * (nl_D(q, ul) + nl_D(q, v));
+            const double g = rs[0] * v + hist - (ap * (ur - v) - am * (v - ul)) * ih2 - c * (ur - v) / h - fm;
+            const double dg = rs[0] + (ap + am - q * v * (ur - v) + q * v * (v - ul)) * ih2 + c / h;
+            const double dv = g / dg;
+            v -= dv;
+            if (!(fabs(dv) > 1e-15 * (1.0 + fabs(v)))) break;   // converged (or not finite)
+        }
+        if (lane == 0) {
+            tl[m] = v;
+            u[(size_t)m * N + (n - 1)] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// out = sf f + sn N(u) + add (f, add may be null): sf = 1, sn = -1 is the
+// residual; sf = 0, sn = 1, add = restricted residual the coarse FAS
+// right-hand side.
+__global__ void k_nl_apply(int N, int M, double h, double c, double q, const double *r, const double *u,
+                           const double *f, double sf, double sn, const double *add, double *out)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)M * N) return;
+    const int m = (int)(e / N), n = (int)(e - (long)m * N) + 1;
+    double s = 0.0;
+    for (int j = 0; j <= m; ++j) s += r[m - j] * u[(size_t)j * N + (n - 1)];
+    const double *row = u + (size_t)m * N;
+    const double uc = row[n - 1], ul = nl_at(row, N, n - 1), ur = nl_at(row, N, n + 1);
+    const double ap = 0.5 * (nl_D(q, ur) + nl_D(q, uc)), am = 0.5 * (nl_D(q, ul) + nl_D(q, uc));
+    s -= (ap * (ur - uc) - am * (uc - ul)) / (h * h);
+    s -= c * (ur - uc) / h;
+    double v = sn * s;
+    if (f) v += sf * f[e];
+    if (add) v += add[e];
+    out[e] = v;
+}
+
+// Full weighting [1 2 1] / 4 to the coarse grid (coarse J on fine 2J).
+__global__ void k_nl_restrict(int Nf, int M, const double *src, double *dst)
+{
+    const int Nc = (Nf - 1) / 2;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)M * Nc) return;
+    const int m = (int)(e / Nc), J = (int)(e - (long)m * Nc) + 1;
+    const double *row = src + (size_t)m * Nf;
+    dst[e] = 0.25 * (nl_at(row, Nf, 2 * J - 1) + 2.0 * nl_at(row, Nf, 2 * J) + nl_at(row, Nf, 2 * J + 1));
+}
+
+// uf += linear interpolation of (uc - uc0), zero coarse boundary values.
+__global__ void k_nl_prolong_diff(int Nc, int M, const double *uc, const double *uc0, double *uf)
+{
+    const int Nf = 2 * Nc + 1;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)M * Nf) return;
+    const int m = (int)(e / Nf), n = (int)(e - (long)m * Nf) + 1;
+    const double *a = uc + (size_t)m * Nc, *b = uc0 + (size_t)m * Nc;
+    auto d = [&](int J) { return (J >= 1 && J <= Nc) ? a[J - 1] - b[J - 1] : 0.0; };
+    uf[e] += (n % 2 == 0) ? d(n / 2) : 0.5 * (d((n - 1) / 2) + d((n + 1) / 2));
+}
+
+// out[0] = max |x_i| over n values (a NaN anywhere makes it NaN); one block.
+__global__ void k_nl_maxabs(long n, const double *x, double *out)
+{
+    __shared__ double s[kNlThreads];
+    double a = 0.0;
+    for (long i = threadIdx.x; i < n; i += kNlThreads) {
+        const double v = fabs(x[i]);
+        if (v > a || v != v) a = v;
+    }
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = kNlThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = s[threadIdx.x + w];
+            if (o > s[threadIdx.x] || o != o) s[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0];
+}
+
+struct NlLevel {
+    int N = 0;
+    double h = 0.0;
+    double *u = nullptr, *f = nullptr, *res = nullptr, *uc0 = nullptr;
+};
+
+struct NlSolver {
+    int M = 0, nu1 = 0, nu2 = 1, first = 1;
+    double c = 1.0, q = 1.0;
+    const double *r = nullptr;   // device, M coefficients
+    std::vector<NlLevel> lv;
+    hipStream_t s = nullptr;
+
+    static unsigned blocks(long n) { return (unsigned)((n + kNlThreads - 1) / kNlThreads); }
+
+    hipError_t sweep(const NlLevel &L, int colour)
+    {
+        const int pts = (colour == 0) ? L.N / 2 : (L.N + 1) / 2;
+        if (pts <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_nl_sweep, dim3((unsigned)pts), dim3(64), sizeof(double) * 2 * M, s, L.N, M, L.h, c, q,
+                           r, colour, (const double *)L.f, L.u);
+        return hipGetLastError();
+    }
+    hipError_t apply(const NlLevel &L, const double *u, const double *f, double sf, double sn, const double *add,
+                     double *out)
+    {
+        hipLaunchKernelGGL(k_nl_apply, dim3(blocks((long)M * L.N)), dim3(kNlThreads), 0, s, L.N, M, L.h, c, q, r,
+                           u, f, sf, sn, add, out);
+        return hipGetLastError();
+    }
+    hipError_t cycle(int l)
+    {
+        NlLevel &L = lv[l];
+        if (l == 0) return sweep(L, 1);   // one point (n = 1): its exact time-line solve
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < nu1 && e == hipSuccess; ++i) {
+            e = sweep(L, first);
+            if (e == hipSuccess) e = sweep(L, 1 - first);
+        }
+        if (e != hipSuccess) return e;
+        NlLevel &C = lv[l - 1];
+        const long nc = (long)M * C.N;
+        if ((e = apply(L, L.u, L.f, 1.0, -1.0, nullptr, L.res)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_nl_restrict, dim3(blocks(nc)), dim3(kNlThreads), 0, s, L.N, M, (const double *)L.res,
+                           C.res);
+        hipLaunchKernelGGL(k_nl_restrict, dim3(blocks(nc)), dim3(kNlThreads), 0, s, L.N, M, (const double *)L.u,
+                           C.uc0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // coarse right-hand side N_c(R u) + R (f - N(u)); coarse start R u
+        if ((e = apply(C, C.uc0, nullptr, 0.0, 1.0, C.res, C.f)) != hipSuccess) return e;
+        if ((e = hipMemcpyAsync(C.u, C.uc0, sizeof(double) * nc, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+        if ((e = cycle(l - 1)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_nl_prolong_diff, dim3(blocks((long)M * L.N)), dim3(kNlThreads), 0, s, C.N, M,
+                           (const double *)C.u, (const double *)C.uc0, L.u);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (int i = 0; i < nu2 && e == hipSuccess; ++i) {
+            e = sweep(L, first);
+            if (e == hipSuccess) e = sweep(L, 1 - first);
+        }
+        return e;
+    }
+};
+
+int nl_fail(int code, const char *msg) { return mgwr::set_error(code, msg); }
+
+}  // namespace
+
+extern "C" int mgwr_fas_solve(int N, int M, double alpha, double T, double c, double q, int nu1, int nu2,
+                              int first_colour, const double *f, double *u, double tol, int maxit, void *stream,
+                              mgwr_info *info)
+{
+    int k = 0;
+    while (((1 << (k + 1)) - 1) < N && k < 30) ++k;
+    if (N < 1 || ((1 << (k + 1)) - 1) != N) return nl_fail(MGWR_EINVAL, "N must be 2^k - 1");
+    if (M < 1 || M > kNlMaxM) return nl_fail(MGWR_EINVAL, "M must be in 1..4096 (the smoother keeps a time line in LDS)");
+    if ((long)M * N > (1L << 30)) return nl_fail(MGWR_EINVAL, "M N too large");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return nl_fail(MGWR_EINVAL, "alpha must be in (0, 1]");
+    if (!(T > 0.0) || !std::isfinite(T)) return nl_fail(MGWR_EINVAL, "T must be positive");
+    if (!(c >= 0.0) || !std::isfinite(c)) return nl_fail(MGWR_EINVAL, "c must be >= 0 (upwind direction)");
+    if (!(q >= 0.0) || !std::isfinite(q)) return nl_fail(MGWR_EINVAL, "q must be >= 0 (D(u) = 1 + q u^2 > 0)");
+    if (nu1 < 0 || nu2 < 0 || nu1 + nu2 < 1) return nl_fail(MGWR_EINVAL, "nu1, nu2 >= 0 with nu1 + nu2 >= 1");
+    if (first_colour != 0 && first_colour != 1) return nl_fail(MGWR_EINVAL, "first_colour must be 0 or 1");
+    if (!(tol > 0.0) || maxit < 0) return nl_fail(MGWR_EINVAL, "tol must be > 0 and maxit >= 0");
+    if (!f || !u) return nl_fail(MGWR_EINVAL, "f and u must not be NULL");
+
+    std::vector<double> rh(M);
+    double cc = 0.0;
+    int rc = mgwr_l1_weights(M, alpha, T, &cc, rh.data());
+    if (rc < 0) return rc;
+
+    NlSolver S;
+    S.M = M; S.nu1 = nu1; S.nu2 = nu2; S.first = first_colour; S.c = c; S.q = q;
+    S.s = (hipStream_t)stream;
+    std::vector<void *> mem;
+    auto alloc = [&](double **p, long n) -> bool {
+        if (hipMalloc((void **)p, sizeof(double) * (size_t)std::max(n, 1L)) != hipSuccess) return false;
+        mem.push_back(*p);
+        return true;
+    };
+    auto release = [&]() {
+        for (void *p : mem) (void)hipFree(p);
+    };
+    bool ok = alloc((double **)&S.r, M);
+    S.lv.resize(k + 1);
+    for (int l = 0; l <= k && ok; ++l) {
+        NlLevel &L = S.lv[l];
+        L.N = (1 << (l + 1)) - 1;
+        L.h = 1.0 / (L.N + 1);
+        const long n = (long)M * L.N;
+        ok = alloc(&L.res, n);
+        if (ok && l < k) ok = alloc(&L.u, n) && alloc(&L.f, n) && alloc(&L.uc0, n);
+    }
+    double *dmax = nullptr;
+    if (ok) ok = alloc(&dmax, 1);
+    if (!ok) {
+        (void)hipStreamSynchronize(S.s);
+        release();
+        return nl_fail(MGWR_ENOMEM, "device allocation failed");
+    }
+    NlLevel &top = S.lv[k];
+    top.u = u;
+    top.f = (double *)f;
+    const long ntop = (long)M * N;
+
+    hipError_t e = hipMemcpyAsync((void *)S.r, rh.data(), sizeof(double) * M, hipMemcpyHostToDevice, S.s);
+    if (e == hipSuccess) e = hipMemsetAsync(u, 0, sizeof(double) * ntop, S.s);
+    mgwr_info inf{};
+    int status = MGWR_OK, it = 0;
+    double r0 = 0.0, rn = 0.0;
+    while (e == hipSuccess) {
+        e = S.apply(top, top.u, top.f, 1.0, -1.0, nullptr, top.res);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_nl_maxabs, dim3(1), dim3(kNlThreads), 0, S.s, ntop, (const double *)top.res, dmax);
+        if ((e = hipGetLastError()) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(&rn, dmax, sizeof(double), hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
+        if ((e = hipStreamSynchronize(S.s)) != hipSuccess) break;
+        if (!std::isfinite(rn)) {
+            status = MGWR_ENONFINITE;
+            break;
+        }
+        if (it < 128) inf.hist[it] = rn;
+        if (it == 0) r0 = rn;
+        if (rn <= tol * r0) break;
+        if (it >= maxit) {
+            status = MGWR_NOT_CONVERGED;
+            break;
+        }
+        e = S.cycle(k);
+        ++it;
+    }
+    (void)hipStreamSynchronize(S.s);   // nothing may still use the temporaries
+    release();
+    if (e != hipSuccess) return nl_fail(MGWR_EDEVICE, hipGetErrorString(e));
+    if (status == MGWR_ENONFINITE) return nl_fail(MGWR_ENONFINITE, "the residual is not finite");
+    inf.iters = it;
+    inf.status = status;
+    inf.r0 = r0;
+    inf.rk = rn;
+    inf.relres = r0 > 0.0 ? rn / r0 : 0.0;
+    inf.mean_factor = (it > 0 && r0 > 0.0) ? std::pow(rn / r0, 1.0 / it) : 0.0;
+    if (info) *info = inf;
+    return status;
+}

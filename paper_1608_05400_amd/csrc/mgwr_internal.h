@@ -19,6 +19,10 @@
 
 namespace mgwr {
 
+// Records msg for mgwr_last_error and returns code.
+int set_error(int code, const char *msg);
+
+
 // Arithmetic of a causal Toeplitz product (history GEMM).
 enum GemmMode { GM_F64 = 0, GM_F32 = 1, GM_BF16X3 = 2 };
 

@@ -1,0 +1,104 @@
+"""GPU parity of the waveform relaxation FAS solver for the nonlinear problem
+of Section 7 (mgwr_fas_solve, through the C ABI) against the oracle's FAS
+iteration, and the paper's Table 5 through the GPU path.
+
+Both sides run the same iteration in FP64 (Newton solves of each time level
+to 1e-15), so a fixed number of cycles agrees to rounding (1e-12 of the
+solution size); converged solves agree to the tolerance's effect on the
+iterate (1e-9).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import load_golden
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1608_05400_amd import binding
+    binding.load()
+    return binding
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("N,M,alpha", [(1, 8, 0.5), (7, 1, 0.3), (31, 32, 0.4), (63, 40, 0.7), (127, 64, 0.1)])
+@pytest.mark.parametrize("cycles", [1, 3])
+@pytest.mark.parametrize("nu", [(0, 1), (1, 1)])
+def test_fas_cycles_match_oracle(B, N, M, alpha, cycles, nu):
+    """A fixed number of FAS cycles from zero, f = 1 + a random part."""
+    rng = np.random.default_rng(N + M)
+    f = 1.0 + 0.5 * rng.standard_normal((M, N))
+    ref, _ = oracle.nl_solve(N, M, alpha, f, nu1=nu[0], nu2=nu[1], tol=1e-300, maxit=cycles)
+    U = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    info = B.fas_solve(dev(f), U, alpha, nu1=nu[0], nu2=nu[1], tol=1e-300, maxit=cycles)
+    assert info["iters"] == cycles, info
+    assert np.abs(host(U) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("row", load_golden("table5_fas_1d.txt"))
+def test_table5_fas_iterations_on_gpu(B, row):
+    """Section 7, Table 5 on the GPU: D(u) = 1 + u^2, c = 1, f = 1, V(0,1),
+    the odd points first; iterations within one of the paper's and the same
+    solution as the oracle's FAS."""
+    alpha, S, its_paper, fac_paper = row
+    S = int(S)
+    N, M = S - 1, S
+    f = np.ones((M, N))
+    U = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    import time
+    t = time.perf_counter()
+    info = B.fas_solve(dev(f), U, alpha)
+    ms = 1e3 * (time.perf_counter() - t)
+    print(f"alpha {alpha} S {S}: {info['iters']} cycles, factor {info['mean_factor']:.3f} "
+          f"(paper {int(its_paper)}, {fac_paper}); {ms:.1f} ms")
+    assert info["rc"] == 0, info
+    assert abs(info["iters"] - its_paper) <= 1
+    assert info["mean_factor"] <= fac_paper + 0.035
+    ref, hist = oracle.nl_solve(N, M, alpha, f)
+    assert info["iters"] == len(hist) - 1
+    assert np.abs(host(U) - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_fas_linear_case_is_the_direct_solution(B):
+    N, M, alpha = 63, 48, 0.45
+    f = np.random.default_rng(4).standard_normal((M, N))
+    U = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    info = B.fas_solve(dev(f), U, alpha, c=0.0, q=0.0, tol=1e-13)
+    assert info["rc"] == 0, info
+    ref = oracle.direct_solve(1, N, M, alpha, f)
+    assert np.abs(host(U) - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_fas_errors(B):
+    U = torch.zeros((8, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.MgwrError):      # N = 4 is not 2^k - 1
+        B.fas_solve(torch.ones_like(U), U, 0.5)
+    U = torch.zeros((8, 7), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.MgwrError):      # negative convection speed
+        B.fas_solve(torch.ones_like(U), U, 0.5, c=-1.0)
+    f = torch.ones_like(U)
+    f[3, 2] = float("nan")
+    with pytest.raises(B.MgwrError):      # a NaN right-hand side gives a NaN residual
+        B.fas_solve(f, U, 0.5)
+
+
+def test_fas_time_levels_limit(B):
+    U = torch.zeros((4097, 7), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.MgwrError):      # the smoother's LDS time line holds at most 4096 levels
+        B.fas_solve(torch.ones_like(U), U, 0.5)
