@@ -349,6 +349,49 @@ def kernel_table(records, steps):
     return rows
 
 
+def bench_fas(B, args):
+    """The nonlinear problem of Section 7 on Table 5's largest grid (N = 255,
+    M = 256, D(u) = 1 + u^2, c = 1, f = 1, V(0,1) FAS to a 1e-10 max-norm
+    reduction) for the four fractional orders of the table: one step solves
+    all four.  The oracle's FAS iteration on the same problems is the CPU
+    baseline.  Prints one JSON line."""
+    import torch
+    import oracle
+    N, M, alphas = 255, 256, (0.1, 0.4, 0.7, 1.0)
+    f = torch.ones((M, N), dtype=torch.float64, device="cuda")
+    us = [torch.zeros((M, N), dtype=torch.float64, device="cuda") for _ in alphas]
+
+    def step():
+        return [B.fas_solve(f, u, a, tol=args.tol) for u, a in zip(us, alphas)]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    unknowns = len(alphas) * M * N
+    err = max(float(np.abs(u.cpu().numpy() - oracle.nl_solve(N, M, a, np.ones((M, N)), tol=args.tol)[0]).max())
+              for u, a in zip(us, alphas)) if not args.no_check else None
+    line = {"metric": "space-time unknowns/sec to 1e-10 rel residual, nonlinear FAS (Section 7, Table 5 grid)",
+            "value": unknowns / (ms * 1e-3), "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "fas_1d_N255_M256_alpha0.1,0.4,0.7,1.0", "cycle": "V(0,1)", "tol": args.tol},
+            "iters": [i["iters"] for i in infos], "max_diff_vs_oracle": err}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        for a in alphas:
+            oracle.nl_solve(N, M, a, np.ones((M, N)), tol=args.tol)
+        s_cpu = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": unknowns / s_cpu, "unit": "unknowns/s", "cores": 1, "kind": "oracle",
+                                "sample": f"the oracle's FAS solves of the same four problems: {s_cpu:.2f} s"}
+    log(f"fas: {line['value']:.4g} unknowns/s, {ms:.1f} ms per step of four solves, iters {line['iters']}")
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(w, seconds):
     """The oracle's direct time-stepping solve on a bounded sample: the first
     Ms time levels of the full problem; its cost is dominated by the O(N M^2)
@@ -389,7 +432,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="1d", choices=["1d", "2d", "2dns", "small", "batch"])
+    ap.add_argument("--workload", default="1d", choices=["1d", "2d", "2dns", "small", "batch", "fas"])
     ap.add_argument("--smoother", default="inverse", choices=["inverse", "dc", "auto"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -414,6 +457,8 @@ def main():
         return
     from paper_1608_05400_amd import binding as B
     B.load()
+    if args.workload == "fas":
+        return bench_fas(B, args)
     wls, wname = make_workloads(args.workload)
     fs = [w.forcing_torch("cuda").contiguous() for w in wls]
     torch.cuda.synchronize()
