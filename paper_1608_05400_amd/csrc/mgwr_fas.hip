@@ -51,14 +51,25 @@ __global__ __launch_bounds__(64) void k_nl_sweep(int N, int M, double h, double 
     for (int j = lane; j < M; j += 64) rs[j] = r[j];
     __syncthreads();
     const double ih2 = 1.0 / (h * h);
+    // the neighbours, f and the old value of level m are read for 64 levels
+    // at a time (lane L holds level m0 + L) and handed round by lane shuffles,
+    // so no global load waits inside the chain along time
+    double cul = 0.0, cur = 0.0, cfm = 0.0, cv = 0.0;
     for (int m = 0; m < M; ++m) {
+        const int k = m & 63;
+        if (k == 0 && m + lane < M) {
+            const double *row = u + (size_t)(m + lane) * N;
+            cul = nl_at(row, N, n - 1);
+            cur = nl_at(row, N, n + 1);
+            cfm = f[(size_t)(m + lane) * N + (n - 1)];
+            cv = row[n - 1];
+        }
         double part = 0.0;
         for (int j = lane; j < m; j += 64) part += rs[m - j] * tl[j];
         for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
         const double hist = part;
-        const double *row = u + (size_t)m * N;
-        const double ul = nl_at(row, N, n - 1), ur = nl_at(row, N, n + 1), fm = f[(size_t)m * N + (n - 1)];
-        double v = row[n - 1];
+        const double ul = __shfl(cul, k), ur = __shfl(cur, k), fm = __shfl(cfm, k);
+        double v = __shfl(cv, k);
         for (int it = 0; it < 50; ++it) {
             const double ap = 0.5 * (nl_D(q, ur) + nl_D(q, v)), am = 0.5 * (nl_D(q, ul) + nl_D(q, v));
             const double g = rs[0] * v + hist - (ap * (ur - v) - am * (v - ul)) * ih2 - c * (ur - v) / h - fm;
