@@ -85,3 +85,47 @@ def test_random_mixed_solve_reaches_direct_solution(B, seed):
         U = host(U)
     assert info["rc"] in (0, 2), info
     assert np.abs(U - ref).max() <= 1e-8 * np.abs(ref).max(), info
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_random_batch_solve_reaches_direct_solutions(B, seed):
+    """A batch of uneven problems under one drawn set of options."""
+    c = draw(200 + seed)
+    rng = c["rng"]
+    dims = c["dims"]
+    count = int(rng.integers(2, 7))
+    Ns = [int(rng.choice([7, 15, 31, 63] if dims == 1 else [7, 15])) for _ in range(count)]
+    Ms = [int(rng.integers(2, 400 if dims == 1 else 150)) for _ in range(count)]
+    als = [float(rng.uniform(0.05, 1.0)) for _ in range(count)]
+    fs = [rng.standard_normal((M, N) if dims == 1 else (M, N, N)) for N, M in zip(Ns, Ms)]
+    print({k: v for k, v in c.items() if k != "rng"}, Ns, Ms, flush=True)
+    refs = [oracle.direct_solve(dims, N, M, a, f) for N, M, a, f in zip(Ns, Ms, als, fs)]
+    b = B.Batch(Ns, Ms, als, dims=dims, nu1=c["nu1"], nu2=c["nu2"], gamma=c["gamma"], first_colour=c["first"],
+                fft=c["fft"], smoother=c["smoother"], dc_block=c["dc_block"], precision=c["prec"], maxit=200)
+    us = [torch.zeros(f.shape, dtype=torch.float64, device="cuda") for f in fs]
+    rc, infos = b.solve([dev(f) for f in fs], us, tol=1e-12)
+    b.close()
+    for u, ref, inf in zip(us, refs, infos):
+        assert np.abs(host(u) - ref).max() <= 1e-8 * np.abs(ref).max(), inf
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_random_fas_cycles_match_oracle(B, seed):
+    """The nonlinear FAS solver under drawn sizes, coefficients and cycles."""
+    rng = np.random.default_rng(3000 + seed)
+    N = int(rng.choice([1, 3, 7, 15, 31, 63]))
+    M = int(rng.integers(1, 300))
+    alpha = float(rng.uniform(0.05, 1.0))
+    cc, q = float(rng.uniform(0.0, 2.0)), float(rng.uniform(0.0, 2.0))
+    nu1, nu2 = [int(v) for v in rng.integers(0, 3, size=2)]
+    if nu1 + nu2 == 0:
+        nu1 = 1
+    first = int(rng.integers(0, 2))
+    cycles = int(rng.integers(1, 3))
+    f = rng.standard_normal((M, N))
+    print(dict(N=N, M=M, alpha=alpha, c=cc, q=q, nu1=nu1, nu2=nu2, first=first, cycles=cycles), flush=True)
+    ref, _ = oracle.nl_solve(N, M, alpha, f, c=cc, q=q, nu1=nu1, nu2=nu2, first=first, tol=1e-300, maxit=cycles)
+    U = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    info = B.fas_solve(dev(f), U, alpha, c=cc, q=q, nu1=nu1, nu2=nu2, first_colour=first, tol=1e-300, maxit=cycles)
+    assert info["iters"] == cycles, info
+    assert np.abs(host(U) - ref).max() <= 1e-11 * max(1.0, np.abs(ref).max())
