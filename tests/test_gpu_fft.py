@@ -258,3 +258,24 @@ def test_fft_refinement_cycle_shapes(B, dims, N, M, alpha, cyc):
         U = host(U)
     assert info["rc"] in (0, 2), info
     assert relmax(U, ref) <= 1e-8, (info, relmax(U, ref))
+
+
+@pytest.mark.parametrize("M", [40000, 70000])
+@pytest.mark.parametrize("P", [2, 5])
+def test_fft_product_long_time_lines(B, M, P):
+    """Transform lengths beyond the benchmark's (L = 131072: a radix-2 first
+    pass, the fused middle kernel with a radix-2 inverse stage); reference by
+    a library FFT convolution of the oracle's coefficients, accurate normwise
+    like the path itself."""
+    from scipy import signal
+    alpha = 0.35
+    rng = np.random.default_rng(M + P)
+    X = rng.standard_normal((M, P))
+    c, d, r = oracle.l1_coeffs(M, alpha)
+    ref = np.stack([signal.fftconvolve(r, X[:, p])[:M] for p in range(P)], axis=1)
+    scale = np.abs(r).sum() * np.abs(X).max()
+    with B.Solver(7, M, alpha, fft=2) as s:
+        C = host(s.toeplitz_apply(dev(X), which=-1, precision="fp64"))
+        C32 = host(s.toeplitz_apply(dev(X), which=-1, precision="fp32"))
+    assert relmax(C, ref, scale) <= 1e-12
+    assert relmax(C32, ref, scale) <= 1e-6
