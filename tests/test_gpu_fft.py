@@ -279,3 +279,24 @@ def test_fft_product_long_time_lines(B, M, P):
         C32 = host(s.toeplitz_apply(dev(X), which=-1, precision="fp32"))
     assert relmax(C, ref, scale) <= 1e-12
     assert relmax(C32, ref, scale) <= 1e-6
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64r", 1e-10), ("bf16x3", 1e-8)])
+def test_fft_solve_long_time_line(B, prec, tol):
+    """A solve at M = 40000 (transform length 131072) with three sine modes
+    of forcing, against the oracle's modal solution (one forward substitution
+    per mode)."""
+    N, M, alpha = 63, 40000, 0.6
+    t = np.arange(1, M + 1) / M
+    kx = np.array([1, 4, 9], dtype=np.int32)
+    s = np.stack([t ** 1.5, -0.5 * t ** 0.8, 0.25 * np.ones(M)])
+    x = np.arange(1, N + 1) / (N + 1)
+    f = s.T @ np.sin(np.pi * np.outer(kx, x))
+    v = oracle.modal_solve(1, N, M, alpha, kx, s)
+    ref = v.T @ np.sin(np.pi * np.outer(kx, x))
+    with B.Solver(N, M, alpha, precision=prec, fft=2) as sv:
+        U = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+        info = sv.solve(dev(f), U, tol=1e-12)
+        U = host(U)
+    assert info["rc"] in (0, 2), info
+    assert relmax(U, ref) <= tol, (info, relmax(U, ref))
