@@ -353,7 +353,7 @@ def bench_fas(B, args):
     """The nonlinear problem of Section 7 on Table 5's largest grid (N = 255,
     M = 256, D(u) = 1 + u^2, c = 1, f = 1, V(0,1) FAS to a 1e-10 max-norm
     reduction) for the four fractional orders of the table: one step solves
-    all four.  The oracle's FAS iteration on the same problems is the CPU
+    all four as one batch (mgwr_fas_solve_batch).  The oracle's FAS iteration on the same problems is the CPU
     baseline.  Prints one JSON line."""
     import torch
     import oracle
@@ -361,8 +361,8 @@ def bench_fas(B, args):
     f = torch.ones((M, N), dtype=torch.float64, device="cuda")
     us = [torch.zeros((M, N), dtype=torch.float64, device="cuda") for _ in alphas]
 
-    def step():
-        return [B.fas_solve(f, u, a, tol=args.tol) for u, a in zip(us, alphas)]
+    def step():   # the four problems as one batch: their kernels overlap
+        return B.fas_solve_batch([f] * len(alphas), us, alphas, tol=args.tol)[1]
 
     for _ in range(args.warmup):
         step()

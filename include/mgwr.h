@@ -143,6 +143,18 @@ int mgwr_fas_solve(int N, int M, double alpha, double T, double c, double q, int
                    int first_colour, const double *f, double *u, double tol, int maxit, void *stream,
                    mgwr_info *info);
 
+/* count problems of the nonlinear problem above with the same N, M, T, c, q
+ * and cycle, each with its own alpha[i], f[i] and u[i] (host arrays of count
+ * values / device pointers): each runs on a stream of its own, created by the
+ * call and ordered after the work already on stream, so that the problems'
+ * kernels overlap; every problem stops by its own test.  infos (host, may be
+ * NULL) receives count records.  Returns MGWR_ENONFINITE if any problem's
+ * residual is not finite, else MGWR_NOT_CONVERGED if any did not converge,
+ * else MGWR_OK; MGWR_EINVAL for bad arguments (nothing written). */
+int mgwr_fas_solve_batch(int count, int N, int M, const double *alpha, double T, double c, double q,
+                         int nu1, int nu2, int first_colour, const double *const *f, double *const *u,
+                         double tol, int maxit, void *stream, mgwr_info *infos);
+
 /* Fill *o with the defaults listed above.  Host only; never fails. */
 int mgwr_default_options(mgwr_options *o);
 

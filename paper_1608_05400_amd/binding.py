@@ -32,7 +32,7 @@ EXPORTED = [
     "mgwr_profile_enable", "mgwr_profile_count", "mgwr_profile_get", "mgwr_kernel_name",
     "mgwr_last_error", "mgwr_autotune", "mgwr_get_tuning", "mgwr_batch_autotune",
     "mgwr_batch_get_tuning", "mgwr_batch_profile_enable", "mgwr_batch_profile_count",
-    "mgwr_batch_profile_get", "mgwr_fas_solve",
+    "mgwr_batch_profile_get", "mgwr_fas_solve", "mgwr_fas_solve_batch",
 ]
 
 
@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH):
     lib.mgwr_batch_profile_count.argtypes = [h]
     lib.mgwr_batch_profile_get.argtypes = [h, I, P(KernelRecord)]
     lib.mgwr_fas_solve.argtypes = [I, I, D, D, D, D, I, I, I, VP, VP, D, I, VP, P(Info)]
+    lib.mgwr_fas_solve_batch.argtypes = [I, I, I, P(D), D, D, D, I, I, I, P(VP), P(VP), D, I, VP, P(Info)]
     lib.mgwr_kernel_name.argtypes = [I]
     lib.mgwr_kernel_name.restype = ctypes.c_char_p
     lib.mgwr_last_error.restype = ctypes.c_char_p
@@ -202,6 +203,23 @@ def fas_solve(f, u, alpha: float, c: float = 1.0, q: float = 1.0, nu1: int = 0, 
     d = info.as_dict()
     d["rc"] = rc
     return d
+
+
+def fas_solve_batch(fs, us, alphas, c: float = 1.0, q: float = 1.0, nu1: int = 0, nu2: int = 1,
+                    first_colour: int = 1, tol: float = 1e-10, maxit: int = 60, T: float = 1.0,
+                    raise_on_error: bool = True):
+    """Several problems of the nonlinear problem of Section 7 with the same
+    shape (mgwr_fas_solve_batch); returns (rc, [info dicts])."""
+    n = len(us)
+    M, N = us[0].shape
+    fp = (ctypes.c_void_p * n)(*[_ptr(f, "f", (M, N)) for f in fs])
+    up = (ctypes.c_void_p * n)(*[_ptr(u, "u", (M, N)) for u in us])
+    infos = (Info * n)()
+    rc = load().mgwr_fas_solve_batch(n, N, M, (ctypes.c_double * n)(*alphas), T, c, q, nu1, nu2, first_colour,
+                                     fp, up, tol, maxit, _stream(), infos)
+    if rc < 0 and raise_on_error:
+        raise MgwrError(rc, last_error())
+    return rc, [i.as_dict() for i in infos]
 
 
 def kernel_name(kernel: int) -> str:

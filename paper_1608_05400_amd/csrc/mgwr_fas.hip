@@ -217,101 +217,184 @@ struct NlSolver {
 
 int nl_fail(int code, const char *msg) { return mgwr::set_error(code, msg); }
 
-}  // namespace
+// One problem of a FAS solve: its hierarchy, coefficients, stream and state.
+struct NlProblem {
+    NlSolver S;
+    double *dmax = nullptr;
+    mgwr_info inf{};
+    int it = 0, status = MGWR_OK;
+    double r0 = 0.0, rn = 0.0;
+    bool done = false;
+};
 
-extern "C" int mgwr_fas_solve(int N, int M, double alpha, double T, double c, double q, int nu1, int nu2,
-                              int first_colour, const double *f, double *u, double tol, int maxit, void *stream,
-                              mgwr_info *info)
+// count problems of the same N and M (alpha, f, u per problem): each on its
+// own stream, their cycles issued together and their residual norms read
+// once per iteration, so the problems' kernels overlap on the GPU.
+int fas_solve(int count, int N, int M, const double *alphas, double T, double c, double q, int nu1, int nu2,
+              int first_colour, const double *const *f, double *const *u, double tol, int maxit, void *stream,
+              mgwr_info *infos)
 {
     int k = 0;
     while (((1 << (k + 1)) - 1) < N && k < 30) ++k;
+    if (count < 1) return nl_fail(MGWR_EINVAL, "count must be >= 1");
     if (N < 1 || ((1 << (k + 1)) - 1) != N) return nl_fail(MGWR_EINVAL, "N must be 2^k - 1");
     if (M < 1 || M > kNlMaxM) return nl_fail(MGWR_EINVAL, "M must be in 1..4096 (the smoother keeps a time line in LDS)");
     if ((long)M * N > (1L << 30)) return nl_fail(MGWR_EINVAL, "M N too large");
-    if (!(alpha > 0.0 && alpha <= 1.0)) return nl_fail(MGWR_EINVAL, "alpha must be in (0, 1]");
+    if (!alphas || !f || !u) return nl_fail(MGWR_EINVAL, "alpha, f and u must not be NULL");
+    for (int i = 0; i < count; ++i) {
+        if (!(alphas[i] > 0.0 && alphas[i] <= 1.0)) return nl_fail(MGWR_EINVAL, "alpha must be in (0, 1]");
+        if (!f[i] || !u[i]) return nl_fail(MGWR_EINVAL, "f and u must not be NULL");
+    }
     if (!(T > 0.0) || !std::isfinite(T)) return nl_fail(MGWR_EINVAL, "T must be positive");
     if (!(c >= 0.0) || !std::isfinite(c)) return nl_fail(MGWR_EINVAL, "c must be >= 0 (upwind direction)");
     if (!(q >= 0.0) || !std::isfinite(q)) return nl_fail(MGWR_EINVAL, "q must be >= 0 (D(u) = 1 + q u^2 > 0)");
     if (nu1 < 0 || nu2 < 0 || nu1 + nu2 < 1) return nl_fail(MGWR_EINVAL, "nu1, nu2 >= 0 with nu1 + nu2 >= 1");
     if (first_colour != 0 && first_colour != 1) return nl_fail(MGWR_EINVAL, "first_colour must be 0 or 1");
     if (!(tol > 0.0) || maxit < 0) return nl_fail(MGWR_EINVAL, "tol must be > 0 and maxit >= 0");
-    if (!f || !u) return nl_fail(MGWR_EINVAL, "f and u must not be NULL");
 
-    std::vector<double> rh(M);
-    double cc = 0.0;
-    int rc = mgwr_l1_weights(M, alpha, T, &cc, rh.data());
-    if (rc < 0) return rc;
+    std::vector<std::vector<double>> rh(count, std::vector<double>(M));
+    for (int i = 0; i < count; ++i) {
+        double cc = 0.0;
+        int rc = mgwr_l1_weights(M, alphas[i], T, &cc, rh[i].data());
+        if (rc < 0) return rc;
+    }
 
-    NlSolver S;
-    S.M = M; S.nu1 = nu1; S.nu2 = nu2; S.first = first_colour; S.c = c; S.q = q;
-    S.s = (hipStream_t)stream;
+    const hipStream_t caller = (hipStream_t)stream;
+    std::vector<NlProblem> P(count);
     std::vector<void *> mem;
+    std::vector<hipStream_t> own;
+    hipEvent_t start = nullptr;
+    double *hnorm = nullptr;   // pinned: the problems' residual norms
     auto alloc = [&](double **p, long n) -> bool {
         if (hipMalloc((void **)p, sizeof(double) * (size_t)std::max(n, 1L)) != hipSuccess) return false;
         mem.push_back(*p);
         return true;
     };
     auto release = [&]() {
+        for (const NlProblem &pb : P) (void)hipStreamSynchronize(pb.S.s);   // nothing may still use them
         for (void *p : mem) (void)hipFree(p);
+        for (hipStream_t st : own) (void)hipStreamDestroy(st);
+        if (start) (void)hipEventDestroy(start);
+        if (hnorm) (void)hipHostFree(hnorm);
     };
-    bool ok = alloc((double **)&S.r, M);
-    S.lv.resize(k + 1);
-    for (int l = 0; l <= k && ok; ++l) {
-        NlLevel &L = S.lv[l];
-        L.N = (1 << (l + 1)) - 1;
-        L.h = 1.0 / (L.N + 1);
-        const long n = (long)M * L.N;
-        ok = alloc(&L.res, n);
-        if (ok && l < k) ok = alloc(&L.u, n) && alloc(&L.f, n) && alloc(&L.uc0, n);
+    bool ok = hipHostMalloc((void **)&hnorm, sizeof(double) * count) == hipSuccess;
+    if (!ok) hnorm = nullptr;
+    if (ok && count > 1) ok = hipEventCreateWithFlags(&start, hipEventDisableTiming) == hipSuccess &&
+                             hipEventRecord(start, caller) == hipSuccess;
+    for (int i = 0; i < count && ok; ++i) {
+        NlSolver &S = P[i].S;
+        S.M = M; S.nu1 = nu1; S.nu2 = nu2; S.first = first_colour; S.c = c; S.q = q;
+        if (count == 1) {
+            S.s = caller;
+        } else {   // default priority; ordered after the caller's earlier work
+            ok = hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) == hipSuccess;
+            if (!ok) break;
+            own.push_back(S.s);
+            ok = hipStreamWaitEvent(S.s, start, 0) == hipSuccess;
+        }
+        ok = ok && alloc((double **)&S.r, M) && alloc(&P[i].dmax, 1);
+        S.lv.resize(k + 1);
+        for (int l = 0; l <= k && ok; ++l) {
+            NlLevel &L = S.lv[l];
+            L.N = (1 << (l + 1)) - 1;
+            L.h = 1.0 / (L.N + 1);
+            const long n = (long)M * L.N;
+            ok = alloc(&L.res, n);
+            if (ok && l < k) ok = alloc(&L.u, n) && alloc(&L.f, n) && alloc(&L.uc0, n);
+        }
+        if (ok) {
+            S.lv[k].u = u[i];
+            S.lv[k].f = (double *)f[i];
+        }
     }
-    double *dmax = nullptr;
-    if (ok) ok = alloc(&dmax, 1);
     if (!ok) {
-        (void)hipStreamSynchronize(S.s);
         release();
-        return nl_fail(MGWR_ENOMEM, "device allocation failed");
+        return nl_fail(MGWR_ENOMEM, "allocation of the FAS hierarchy or its streams failed");
     }
-    NlLevel &top = S.lv[k];
-    top.u = u;
-    top.f = (double *)f;
     const long ntop = (long)M * N;
-
-    hipError_t e = hipMemcpyAsync((void *)S.r, rh.data(), sizeof(double) * M, hipMemcpyHostToDevice, S.s);
-    if (e == hipSuccess) e = hipMemsetAsync(u, 0, sizeof(double) * ntop, S.s);
-    mgwr_info inf{};
-    int status = MGWR_OK, it = 0;
-    double r0 = 0.0, rn = 0.0;
-    while (e == hipSuccess) {
-        e = S.apply(top, top.u, top.f, 1.0, -1.0, nullptr, top.res);
-        if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_nl_maxabs, dim3(1), dim3(kNlThreads), 0, S.s, ntop, (const double *)top.res, dmax);
-        if ((e = hipGetLastError()) != hipSuccess) break;
-        if ((e = hipMemcpyAsync(&rn, dmax, sizeof(double), hipMemcpyDeviceToHost, S.s)) != hipSuccess) break;
-        if ((e = hipStreamSynchronize(S.s)) != hipSuccess) break;
-        if (!std::isfinite(rn)) {
-            status = MGWR_ENONFINITE;
-            break;
-        }
-        if (it < 128) inf.hist[it] = rn;
-        if (it == 0) r0 = rn;
-        if (rn <= tol * r0) break;
-        if (it >= maxit) {
-            status = MGWR_NOT_CONVERGED;
-            break;
-        }
-        e = S.cycle(k);
-        ++it;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < count && e == hipSuccess; ++i) {
+        NlSolver &S = P[i].S;
+        e = hipMemcpyAsync((void *)S.r, rh[i].data(), sizeof(double) * M, hipMemcpyHostToDevice, S.s);
+        if (e == hipSuccess) e = hipMemsetAsync(u[i], 0, sizeof(double) * ntop, S.s);
     }
-    (void)hipStreamSynchronize(S.s);   // nothing may still use the temporaries
+    int left = count;
+    while (e == hipSuccess && left > 0) {
+        // residual norms of the problems still iterating
+        for (int i = 0; i < count && e == hipSuccess; ++i) {
+            if (P[i].done) continue;
+            NlSolver &S = P[i].S;
+            NlLevel &top = S.lv[k];
+            e = S.apply(top, top.u, top.f, 1.0, -1.0, nullptr, top.res);
+            if (e != hipSuccess) break;
+            hipLaunchKernelGGL(k_nl_maxabs, dim3(1), dim3(kNlThreads), 0, S.s, ntop, (const double *)top.res,
+                               P[i].dmax);
+            if ((e = hipGetLastError()) != hipSuccess) break;
+            e = hipMemcpyAsync(&hnorm[i], P[i].dmax, sizeof(double), hipMemcpyDeviceToHost, S.s);
+        }
+        for (int i = 0; i < count && e == hipSuccess; ++i)
+            if (!P[i].done) e = hipStreamSynchronize(P[i].S.s);
+        if (e != hipSuccess) break;
+        // stopping tests, then one cycle of each problem still iterating
+        for (int i = 0; i < count; ++i) {
+            NlProblem &pb = P[i];
+            if (pb.done) continue;
+            pb.rn = hnorm[i];
+            bool stop = false;
+            if (!std::isfinite(pb.rn)) {
+                pb.status = MGWR_ENONFINITE;
+                stop = true;
+            } else {
+                if (pb.it < 128) pb.inf.hist[pb.it] = pb.rn;
+                if (pb.it == 0) pb.r0 = pb.rn;
+                if (pb.rn <= tol * pb.r0) stop = true;
+                else if (pb.it >= maxit) {
+                    pb.status = MGWR_NOT_CONVERGED;
+                    stop = true;
+                }
+            }
+            if (stop) {
+                pb.done = true;
+                --left;
+            }
+        }
+        for (int i = 0; i < count && e == hipSuccess; ++i) {
+            if (P[i].done) continue;
+            e = P[i].S.cycle(k);
+            ++P[i].it;
+        }
+    }
     release();
     if (e != hipSuccess) return nl_fail(MGWR_EDEVICE, hipGetErrorString(e));
-    if (status == MGWR_ENONFINITE) return nl_fail(MGWR_ENONFINITE, "the residual is not finite");
-    inf.iters = it;
-    inf.status = status;
-    inf.r0 = r0;
-    inf.rk = rn;
-    inf.relres = r0 > 0.0 ? rn / r0 : 0.0;
-    inf.mean_factor = (it > 0 && r0 > 0.0) ? std::pow(rn / r0, 1.0 / it) : 0.0;
-    if (info) *info = inf;
-    return status;
+    int worst = MGWR_OK;
+    for (int i = 0; i < count; ++i) {
+        NlProblem &pb = P[i];
+        pb.inf.iters = pb.it;
+        pb.inf.status = pb.status;
+        pb.inf.r0 = pb.r0;
+        pb.inf.rk = pb.rn;
+        pb.inf.relres = pb.r0 > 0.0 ? pb.rn / pb.r0 : 0.0;
+        pb.inf.mean_factor = (pb.it > 0 && pb.r0 > 0.0) ? std::pow(pb.rn / pb.r0, 1.0 / pb.it) : 0.0;
+        if (infos) infos[i] = pb.inf;
+        if (pb.status == MGWR_ENONFINITE) worst = MGWR_ENONFINITE;
+        else if (pb.status == MGWR_NOT_CONVERGED && worst == MGWR_OK) worst = MGWR_NOT_CONVERGED;
+    }
+    if (worst == MGWR_ENONFINITE) return nl_fail(MGWR_ENONFINITE, "the residual is not finite");
+    return worst;
+}
+
+}  // namespace
+
+extern "C" int mgwr_fas_solve(int N, int M, double alpha, double T, double c, double q, int nu1, int nu2,
+                              int first_colour, const double *f, double *u, double tol, int maxit, void *stream,
+                              mgwr_info *info)
+{
+    return fas_solve(1, N, M, &alpha, T, c, q, nu1, nu2, first_colour, &f, &u, tol, maxit, stream, info);
+}
+
+extern "C" int mgwr_fas_solve_batch(int count, int N, int M, const double *alpha, double T, double c, double q,
+                                    int nu1, int nu2, int first_colour, const double *const *f, double *const *u,
+                                    double tol, int maxit, void *stream, mgwr_info *infos)
+{
+    return fas_solve(count, N, M, alpha, T, c, q, nu1, nu2, first_colour, f, u, tol, maxit, stream, infos);
 }

@@ -102,3 +102,23 @@ def test_fas_time_levels_limit(B):
     U = torch.zeros((4097, 7), dtype=torch.float64, device="cuda")
     with pytest.raises(B.MgwrError):      # the smoother's LDS time line holds at most 4096 levels
         B.fas_solve(torch.ones_like(U), U, 0.5)
+
+
+def test_fas_batch_matches_single_solves(B):
+    """Several problems at once (own streams, overlapping kernels) give each
+    problem's single-solve result and iteration count."""
+    N, M = 63, 48
+    alphas = [0.1, 0.45, 0.8, 1.0]
+    rng = np.random.default_rng(12)
+    fs = [dev(1.0 + 0.3 * rng.standard_normal((M, N))) for _ in alphas]
+    singles = []
+    for f, a in zip(fs, alphas):
+        U = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+        info = B.fas_solve(f, U, a)
+        singles.append((host(U), info["iters"]))
+    us = [torch.zeros((M, N), dtype=torch.float64, device="cuda") for _ in alphas]
+    rc, infos = B.fas_solve_batch(fs, us, alphas)
+    assert rc == 0
+    for u, inf, (ref, its) in zip(us, infos, singles):
+        assert inf["iters"] == its
+        assert np.abs(host(u) - ref).max() == 0.0   # the same kernels in the same order per problem
