@@ -122,3 +122,16 @@ def test_fas_batch_matches_single_solves(B):
     for u, inf, (ref, its) in zip(us, infos, singles):
         assert inf["iters"] == its
         assert np.abs(host(u) - ref).max() == 0.0   # the same kernels in the same order per problem
+
+
+def test_fas_batch_reports_a_nonfinite_problem(B):
+    """A NaN in one problem's right-hand side ends that problem only; the
+    call reports MGWR_ENONFINITE and the others converge."""
+    N, M = 31, 24
+    fs = [torch.ones((M, N), dtype=torch.float64, device="cuda") for _ in range(3)]
+    fs[1][5, 7] = float("nan")
+    us = [torch.zeros((M, N), dtype=torch.float64, device="cuda") for _ in range(3)]
+    rc, infos = B.fas_solve_batch(fs, us, [0.3, 0.5, 0.9], raise_on_error=False)
+    assert rc == -4   # MGWR_ENONFINITE
+    assert infos[0]["status"] == "ok" and infos[2]["status"] == "ok" and infos[1]["status"] == "enonfinite", infos
+    assert infos[0]["relres"] <= 1e-10 and infos[2]["relres"] <= 1e-10
