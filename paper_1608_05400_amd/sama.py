@@ -67,6 +67,21 @@ def two_grid_symbol(theta: float, Tm: np.ndarray, nu1: int = 1, nu2: int = 0) ->
     return np.linalg.matrix_power(S, nu2) @ C @ np.linalg.matrix_power(S, nu1)
 
 
+def smoothing_factor(alpha: float, lam: float, M: int, ntheta: int = 64, exact: bool = False) -> float:
+    """Smoothing factor of the Jacobi-type waveform relaxation (M_h = 2/h^2,
+    the diagonal of A_h): the largest eigenvalue modulus of
+    (T_M + M_h)^-1 N_h(theta) over the high frequencies theta h in [pi/2, pi]
+    (Section 4.1, smoothing analysis)."""
+    Tm = time_matrix(M, alpha, lam)
+    Mt = Tm + 2.0 * np.eye(M)
+    best = 0.0
+    for t in np.linspace(math.pi / 2, math.pi, ntheta):
+        S = linalg.solve_triangular(Mt, 2.0 * math.cos(t) * np.eye(M), lower=True)
+        v = abs(S[0, 0]) if exact else float(max(abs(np.linalg.eigvals(S))))
+        best = max(best, v)
+    return best
+
+
 def _radius(T: np.ndarray, exact: bool) -> float:
     if exact:   # block lower triangular in time: the first time level's 2 x 2 block
         M = T.shape[0] // 2

@@ -199,3 +199,20 @@ def test_2d_factors_bounded():
     # depend on the fractional order
     for l2 in (-8, -4, 0, 4, 8):
         assert max(abs(rho[(a, l2)] - rho[(0.5, l2)]) for a in (0.1, 0.9)) <= 0.01
+
+
+def test_jacobi_smoothing_factor_closed_form():
+    """Section 4.1: (T_M + 2)^-1 N(theta) is lower triangular with diagonal
+    2 cos(theta) / (r_1 + 2), r_1 = 1/lambda for h = 1, so the exact factor
+    over the high frequencies is 2 / (1/lambda + 2) (at theta h = pi)."""
+    for lam in (0.25, 1.0, 16.0):
+        mu = sama.smoothing_factor(0.4, lam, 16, exact=True)
+        assert abs(mu - 2.0 / (1.0 / lam + 2.0)) <= 1e-13, (lam, mu)
+
+
+def test_steady_limits():
+    """Section 6 remark: as lambda grows the problem tends to the steady one,
+    where red-black two-grid with full weighting and linear interpolation is
+    exact in 1D and has the factor 1/4 in 2D (one smoothing step)."""
+    assert sama.two_grid_factor(0.5, 2.0 ** 20, 4, exact=True) <= 1e-4
+    assert abs(sama.two_grid_factor_2d(0.5, 2.0 ** 20, 2, ntheta=24, exact=True) - 0.25) <= 0.01
