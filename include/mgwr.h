@@ -242,6 +242,12 @@ typedef struct {
 } mgwr_tuning;
 int mgwr_autotune(mgwr_t h);
 int mgwr_get_tuning(mgwr_t h, mgwr_tuning *t);
+/* Apply a tuning obtained from mgwr_get_tuning on a handle of the same shape
+ * and options (for instance saved by an earlier process), instead of running
+ * the autotuner.  MGWR_EINVAL if the level count differs or a field is out of
+ * range (variant -1..1, split_target >= 0, dc_block 0 or a multiple of 128,
+ * fft 0 or 1); the handle is then unchanged. */
+int mgwr_set_tuning(mgwr_t h, const mgwr_tuning *t);
 
 /* ---- batches of independent 1D or 2D problems (uneven N, M, alpha) ----
  * count problems; N[i], M[i], alpha[i], T[i] as for mgwr_create; all share

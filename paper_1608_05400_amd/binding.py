@@ -32,7 +32,7 @@ EXPORTED = [
     "mgwr_profile_enable", "mgwr_profile_count", "mgwr_profile_get", "mgwr_kernel_name",
     "mgwr_last_error", "mgwr_autotune", "mgwr_get_tuning", "mgwr_batch_autotune",
     "mgwr_batch_get_tuning", "mgwr_batch_profile_enable", "mgwr_batch_profile_count",
-    "mgwr_batch_profile_get", "mgwr_fas_solve", "mgwr_fas_solve_batch",
+    "mgwr_batch_profile_get", "mgwr_fas_solve", "mgwr_fas_solve_batch", "mgwr_set_tuning",
 ]
 
 
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH):
     lib.mgwr_profile_get.argtypes = [h, I, P(KernelRecord)]
     lib.mgwr_autotune.argtypes = [h]
     lib.mgwr_get_tuning.argtypes = [h, P(Tuning)]
+    lib.mgwr_set_tuning.argtypes = [h, P(Tuning)]
     lib.mgwr_batch_autotune.argtypes = [h]
     lib.mgwr_batch_get_tuning.argtypes = [h, I, P(Tuning)]
     lib.mgwr_batch_profile_enable.argtypes = [h, I]
@@ -309,6 +310,34 @@ class Solver:
         t = Tuning()
         _check(self._lib.mgwr_get_tuning(self._h, ctypes.byref(t)), False)
         return t.as_dict()
+
+    def set_tuning(self, d):
+        """Apply a tuning dict from tuning() (mgwr_set_tuning)."""
+        t = Tuning()
+        t.tuned = 1
+        t.variant[:] = list(d["variant"])
+        t.split_target[:] = list(d["split_target"])
+        t.levels = len(d["fft"])
+        if len(d["dc_block"]) != t.levels or t.levels > 32:
+            raise ValueError("dc_block and fft must have one entry per level")
+        for l in range(t.levels):
+            t.dc_block[l] = int(d["dc_block"][l])
+            t.fft[l] = int(d["fft"][l])
+        t.ms_default = float(d.get("ms_default", 0.0))
+        t.ms_tuned = float(d.get("ms_tuned", 0.0))
+        _check(self._lib.mgwr_set_tuning(self._h, ctypes.byref(t)), False)
+
+    def save_tuning(self, path):
+        """Write the handle's tuning as JSON (to reuse in a later process)."""
+        import json
+        with open(path, "w") as fh:
+            json.dump(self.tuning(), fh)
+
+    def load_tuning(self, path):
+        """Apply a tuning written by save_tuning for a handle of the same shape."""
+        import json
+        with open(path) as fh:
+            self.set_tuning(json.load(fh))
 
     def levels(self) -> int:
         return _check(self._lib.mgwr_levels(self._h))

@@ -1949,6 +1949,34 @@ int mgwr_get_tuning(mgwr_t h, mgwr_tuning *t)
     return MGWR_OK;
 }
 
+int mgwr_set_tuning(mgwr_t h, const mgwr_tuning *t)
+{
+    if (!h || !t) return fail(MGWR_EINVAL, "NULL argument");
+    if (t->levels != (int)h->lv.size()) return fail(MGWR_EINVAL, "the tuning has %d levels, the handle %d", t->levels,
+                                                    (int)h->lv.size());
+    for (int m = 0; m < 2; ++m)
+        if (t->variant[m] < -1 || t->variant[m] > 1) return fail(MGWR_EINVAL, "variant must be -1, 0 or 1");
+    for (int m = 0; m < 3; ++m)
+        if (t->split_target[m] < 0) return fail(MGWR_EINVAL, "split_target must be >= 0");
+    for (int l = 0; l < t->levels; ++l) {
+        if (t->dc_block[l] < 0 || t->dc_block[l] % 128 != 0)
+            return fail(MGWR_EINVAL, "dc_block must be 0 or a multiple of 128");
+        if (t->fft[l] != 0 && t->fft[l] != 1) return fail(MGWR_EINVAL, "fft must be 0 or 1");
+    }
+    h->tune.kn[GM_F64].variant = t->variant[0];
+    h->tune.kn[GM_F32].variant = t->variant[1];
+    for (int m = 0; m < 3; ++m) h->tune.kn[m].split_target = t->split_target[m];
+    for (int l = 0; l < t->levels; ++l) {
+        h->lv[l].dc_tuned = t->dc_block[l];
+        h->lv[l].fft_tuned = t->fft[l];
+    }
+    h->tune.ms_default = t->ms_default;
+    h->tune.ms_tuned = t->ms_tuned;
+    h->tune.tuned = true;
+    clear_programs(h->run);   // recorded programs follow the old choices
+    return MGWR_OK;
+}
+
 int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int ldb, int P, double *C,
                         int ldc)
 {

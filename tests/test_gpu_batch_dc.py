@@ -279,3 +279,30 @@ def test_batch_profiled_with_fft_and_dense_products(B, prec, tol):
     for i, (u, ref, inf) in enumerate(zip(us, refs, infos)):
         assert inf["status"] in ("ok", "stagnated"), (i, inf)
         assert relmax(host(u), ref) <= tol, (i, inf, relmax(host(u), ref))
+
+
+def test_tuning_saved_and_applied_to_a_new_handle(B, tmp_path):
+    """mgwr_set_tuning: a tuning saved as JSON by one handle, applied to a new
+    handle of the same shape, gives the same choices and a bitwise equal solve."""
+    w = W.random_modes_1d(255, 1500, 0.45, seed=31)
+    f = dev(w.forcing())
+    path = tmp_path / "tuning.json"
+    with B.Solver(w.N, w.M, w.alpha, precision="bf16x3", smoother="auto") as s:
+        s.autotune()
+        s.save_tuning(str(path))
+        t0 = s.tuning()
+        U0 = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        s.solve(f, U0, tol=1e-10)
+    with B.Solver(w.N, w.M, w.alpha, precision="bf16x3", smoother="auto") as s:
+        s.load_tuning(str(path))
+        t1 = s.tuning()
+        U1 = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+        s.solve(f, U1, tol=1e-10)
+        bad = dict(t1, fft=t1["fft"][:-1], dc_block=t1["dc_block"][:-1])
+        with pytest.raises(B.MgwrError):   # level count differs
+            s.set_tuning(bad)
+        with pytest.raises(B.MgwrError):   # not a multiple of 128
+            s.set_tuning(dict(t1, dc_block=[100] + t1["dc_block"][1:]))
+    for k in ("tuned", "variant", "split_target", "dc_block", "fft"):
+        assert t0[k] == t1[k], k
+    assert torch.equal(U0, U1)
