@@ -20,7 +20,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mgwr_oracle.c")
-_LIB = os.path.join(_HERE, "libmgwr_oracle.so")
+# MGWR_ORACLE_LIB selects another build of the same source (the sanitizer
+# test loads one built with AddressSanitizer and UBSan)
+_LIB = os.environ.get("MGWR_ORACLE_LIB") or os.path.join(_HERE, "libmgwr_oracle.so")
 _lib = None
 
 _D = ctypes.POINTER(ctypes.c_double)
