@@ -43,6 +43,8 @@
 #include <thread>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "mgwr.h"
 #include "mgwr_internal.h"
 
@@ -55,6 +57,16 @@ int product_kernel_kind(int mode, int M, int P, const TileKnobs &kn);
 namespace {
 
 thread_local std::string g_err;
+
+// A named range on the host timeline (roctx): a tracer such as
+// rocprofv3 --marker-trace shows the solve, each outer iteration and the
+// autotuner; without a tracer the calls do nothing.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 int fail(int code, const char *fmt, ...)
 {
@@ -1287,6 +1299,7 @@ void update_state(SolveState &S, const mgwr_options &o, const double nrm[2], dou
 int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *const *f, const double *const *g,
                 double *const *u, double tol, mgwr_info *infos)
 {
+    TraceRange tr("mgwr solve");
     const int n = (int)hs.size();
     for (mgwr_ctx *h : hs) CHK(alloc_inner(h, h->opt.precision, uses_dc(h)));
     std::vector<Hier> Hp(n), Hi(n);
@@ -1369,7 +1382,10 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
             HIPCHK(launch_dd_update(upd, ex.st, ex.s));
             return fine_residuals(ex, res);
         };
-        CHK(run_program(R, prog_key("iter", act, ptrs), step));
+        {
+            TraceRange tr("mgwr outer iteration");
+            CHK(run_program(R, prog_key("iter", act, ptrs), step));
+        }
         CHK(read_norms(R));
         for (int i : act) {
             ++S[i].it;
@@ -1459,6 +1475,7 @@ int time_cycle(Runner &R, const std::vector<mgwr_ctx *> &hs, int prec, int reps,
 
 int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
 {
+    TraceRange tr("mgwr autotune");
     mgwr_ctx *h0 = hs[0];
     const std::string key = tune_key(h0);
     {
