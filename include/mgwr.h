@@ -226,8 +226,10 @@ int mgwr_levels(mgwr_t h);
  * level (options.fft = 1), and, when options.smoother is MGWR_SMOOTH_DC with
  * dc_block = 0 or MGWR_SMOOTH_AUTO, candidate D&C base blocks per level, and
  * keeps the fastest.  Handles of the same shape and options created later in
- * the process reuse the result.  Synchronous; the choice is reported by
- * mgwr_get_tuning. */
+ * the process reuse the result; if the environment variable MGWR_TUNE_CACHE
+ * names a file, results are also appended to it and read from it by later
+ * processes (single handles; a malformed or unreadable file is ignored).
+ * Synchronous; the choice is reported by mgwr_get_tuning. */
 typedef struct {
     int tuned;            /* 1 once mgwr_autotune has run                                */
     int variant[2];       /* FP64 / FP32 product tile: -1 by size, 0 = 128x64, 1 = 256x64 */

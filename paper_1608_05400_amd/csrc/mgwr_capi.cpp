@@ -34,6 +34,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <list>
@@ -1473,9 +1474,71 @@ int time_cycle(Runner &R, const std::vector<mgwr_ctx *> &hs, int prec, int reps,
     return rc;
 }
 
+// Tuning cache file named by MGWR_TUNE_CACHE (optional): one line per key,
+//   key TAB v0 s0 v1 s1 v2 s2 levels dc[levels] fft[levels] ms_default ms_tuned
+// (tile variant and split target per product mode); a later line for the
+// same key wins.  Unreadable or malformed lines are skipped.
+bool tune_file_load(const std::string &key, size_t levels, TuneResult &out)
+{
+    const char *path = getenv("MGWR_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE *fp = fopen(path, "r");
+    if (!fp) return false;
+    std::vector<char> line(1 << 16);
+    bool found = false;
+    while (fgets(line.data(), (int)line.size(), fp)) {
+        const char *tab = strchr(line.data(), '\t');
+        if (!tab || std::string(line.data(), tab - line.data()) != key) continue;
+        TuneResult t;
+        int v[6], nl = 0, used = 0;
+        const char *p = tab + 1;
+        if (sscanf(p, "%d %d %d %d %d %d %d%n", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &nl, &used) != 7) continue;
+        if (nl != (int)levels) continue;
+        p += used;
+        bool ok = true;
+        for (int m = 0; m < 3; ++m) {
+            t.kn[m].variant = v[2 * m];
+            t.kn[m].split_target = v[2 * m + 1];
+            ok = ok && v[2 * m] >= -1 && v[2 * m] <= 1 && v[2 * m + 1] >= 0;
+        }
+        t.dc.resize(nl);
+        t.fft.resize(nl);
+        for (int l = 0; l < nl && ok; ++l) {
+            ok = sscanf(p, "%d%n", &t.dc[l], &used) == 1 && t.dc[l] >= 0 && t.dc[l] % 128 == 0;
+            p += used;
+        }
+        for (int l = 0; l < nl && ok; ++l) {
+            ok = sscanf(p, "%d%n", &t.fft[l], &used) == 1 && t.fft[l] >= -1 && t.fft[l] <= 1;
+            p += used;
+        }
+        ok = ok && sscanf(p, "%lf %lf", &t.ms_default, &t.ms_tuned) == 2;
+        if (ok) {
+            out = t;
+            found = true;
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+void tune_file_store(const std::string &key, const TuneResult &t)
+{
+    const char *path = getenv("MGWR_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *fp = fopen(path, "a");
+    if (!fp) return;
+    fprintf(fp, "%s\t", key.c_str());
+    for (int m = 0; m < 3; ++m) fprintf(fp, "%d %d ", t.kn[m].variant, t.kn[m].split_target);
+    fprintf(fp, "%zu", t.dc.size());
+    for (int d : t.dc) fprintf(fp, " %d", d);
+    for (int x : t.fft) fprintf(fp, " %d", x);
+    fprintf(fp, " %.17g %.17g\n", t.ms_default, t.ms_tuned);
+    fclose(fp);
+}
+
 int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
 {
-    TraceRange tr("mgwr autotune");
+    TraceRange range("mgwr autotune");
     mgwr_ctx *h0 = hs[0];
     const std::string key = tune_key(h0);
     {
@@ -1489,6 +1552,20 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
             }
             h0->tune.ms_default = it->second.ms_default;
             h0->tune.ms_tuned = it->second.ms_tuned;
+            h0->tune.tuned = true;
+            clear_programs(R);
+            return MGWR_OK;
+        }
+        TuneResult ft;   // a tuning saved by an earlier process
+        if (hs.size() == 1 && tune_file_load(key, h0->lv.size(), ft)) {
+            g_tune_cache[key] = ft;
+            for (int m = 0; m < 3; ++m) h0->tune.kn[m] = ft.kn[m];
+            for (size_t l = 0; l < h0->lv.size(); ++l) {
+                h0->lv[l].dc_tuned = ft.dc[l];
+                h0->lv[l].fft_tuned = ft.fft[l];
+            }
+            h0->tune.ms_default = ft.ms_default;
+            h0->tune.ms_tuned = ft.ms_tuned;
             h0->tune.tuned = true;
             clear_programs(R);
             return MGWR_OK;
@@ -1653,6 +1730,7 @@ int autotune_group(Runner &R, const std::vector<mgwr_ctx *> &hs)
         tr.ms_tuned = best;
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = tr;
+        tune_file_store(key, tr);
     }
     return MGWR_OK;
 }

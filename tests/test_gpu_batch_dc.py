@@ -306,3 +306,29 @@ def test_tuning_saved_and_applied_to_a_new_handle(B, tmp_path):
     for k in ("tuned", "variant", "split_target", "dc_block", "fft"):
         assert t0[k] == t1[k], k
     assert torch.equal(U0, U1)
+
+
+def test_tune_cache_file_is_read_by_a_later_process(B, tmp_path):
+    """MGWR_TUNE_CACHE: a tuning written by one process is read back by the
+    next one (the same choices and the same recorded timings, not a new
+    tuning run)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = str(tmp_path / "tune.cache")
+    script = (
+        "import json, torch\n"
+        "from paper_1608_05400_amd import binding as B\n"
+        "B.load()\n"
+        "with B.Solver(255, 1500, 0.45, precision='bf16x3') as s:\n"
+        "    print(json.dumps(s.autotune()))\n")
+    env = dict(os.environ, MGWR_TUNE_CACHE=cache, PYTHONPATH=root)
+    outs = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True, env=env, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    assert os.path.exists(cache) and len(open(cache).read().splitlines()) == 1
+    assert outs[0] == outs[1]   # including ms_default / ms_tuned: read, not re-timed
