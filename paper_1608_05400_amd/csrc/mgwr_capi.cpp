@@ -1003,6 +1003,23 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
 // One cycle of Algorithm 1 for every task (each on its own level): the tasks
 // at their coarsest level do the exact one-point solve while the others
 // pre-smooth, then the others recurse together.
+// A level that starts a cycle from zero needs no zero fill when every point
+// is written before it is read: pre-smoothing comes first and the first
+// half-sweep takes the FFT route, whose products then read their right-hand
+// sides from F (no initial-condition term) and write the colour's points
+// without reading them; the second half-sweep reads only those.  (A dense or
+// D&C first half-sweep builds its right-hand sides from the iterate.)
+bool skip_zero_fill(const Hier &H, int lev)
+{
+    const mgwr_ctx *h = H.h;
+    if (h->opt.nu1 < 1 || dc_block_of(h, lev) > 0) return false;
+    if (lev == (int)h->lv.size() - 1 && H.g) return false;
+    const int Pc = h->lv[lev].Pc[h->opt.first_colour];
+    if (Pc == 0) return false;
+    const int mode = level_mode(H, Pc);
+    return mode == GM_F64 ? fft_for(h, lev) : fft_for(h, lev, mode);
+}
+
 int cycle(Exec &ex, const std::vector<Task> &ts)
 {
     if (ts.empty()) return MGWR_OK;
@@ -1037,7 +1054,8 @@ int cycle(Exec &ex, const std::vector<Task> &ts)
         if (!restricted_residual(t))
             rs.push_back(XferArgs{0, h->dims, h->lv[t.lev].n, h->M, t.H->rscratch, t.H->f[t.lev - 1],
                                   colour_residual(t) ? 1 - h->opt.first_colour : -1});
-        zs.push_back(FillArgs{h->M, h->lv[t.lev - 1].P, nullptr, nullptr, t.H->u[t.lev - 1], 0});
+        if (!skip_zero_fill(*t.H, t.lev - 1))
+            zs.push_back(FillArgs{h->M, h->lv[t.lev - 1].P, nullptr, nullptr, t.H->u[t.lev - 1], 0});
         pr.push_back(XferArgs{1, h->dims, h->lv[t.lev - 1].n, h->M, t.H->u[t.lev - 1], t.H->u[t.lev]});
     }
     HIPCHK(launch_xfer(rs, ex.st, ex.s));
@@ -1361,7 +1379,7 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
                 } else {
                     Level &L = h->lv.back();
                     inner.push_back(Task{&Hi[i], top, true});
-                    zero.push_back(FillArgs{h->M, L.P, nullptr, nullptr, L.e, 0});
+                    if (!skip_zero_fill(Hi[i], top)) zero.push_back(FillArgs{h->M, L.P, nullptr, nullptr, L.e, 0});
                     upd.push_back(DDArgs{(long)h->M * L.P, L.e, u[i], h->ulo});
                 }
                 res.push_back(fine_res(i, false));
@@ -1445,7 +1463,8 @@ int time_cycle(Runner &R, const std::vector<mgwr_ctx *> &hs, int prec, int reps,
         for (size_t i = 0; i < hs.size(); ++i) {
             Level &L = hs[i]->lv.back();
             ts.push_back(Task{&H[i], (int)hs[i]->lv.size() - 1, true});
-            zero.push_back(FillArgs{hs[i]->M, L.P, nullptr, nullptr, L.e, 0});
+            if (!skip_zero_fill(H[i], (int)hs[i]->lv.size() - 1))
+                zero.push_back(FillArgs{hs[i]->M, L.P, nullptr, nullptr, L.e, 0});
         }
         HIPCHK(launch_fill(zero, ex.st, ex.s));
         return cycle(ex, ts);
