@@ -38,9 +38,23 @@ __device__ inline double nl_at(const double *row, int N, int n) { return (n >= 1
 // for m = 0..M-1,
 //   r_1 v + sum_{j<m} r_{m-j+1} u_{n,j} - [a+(v)(u_{n+1} - v) - a-(v)(v - u_{n-1})] / h^2
 //     - c (u_{n+1} - v) / h = f_{n,m}
-// for v = u_{n,m} by Newton's method from the current value.  The lanes
-// split each history sum; the point's new time line and the coefficients
-// are kept in LDS (2 M doubles), so the sum reads no global memory.
+// for v = u_{n,m} by Newton's method from the current value.  The time line
+// is taken 64 levels at a time, lane L holding level m0 + L: its neighbours,
+// f, its old value and its history sum.  At a block's start each lane sums
+// the history of the levels before the block; every level solved inside the
+// block is then added into the sums of the later lanes, so each level's
+// history is complete in its own lane when its turn comes (the same terms in
+// the same order as the plain sum over j) and the chain along time holds no
+// reduction, only reads of lane k's registers.  The new time line and the
+// coefficients are kept in LDS (2 M doubles).
+__device__ inline double nl_lane(double x, int k)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, k);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), k);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __global__ __launch_bounds__(64) void k_nl_sweep(int N, int M, double h, double c, double q, const double *r,
                                                  int colour, const double *f, double *u)
 {
@@ -51,38 +65,41 @@ __global__ __launch_bounds__(64) void k_nl_sweep(int N, int M, double h, double 
     for (int j = lane; j < M; j += 64) rs[j] = r[j];
     __syncthreads();
     const double ih2 = 1.0 / (h * h);
-    // the neighbours, f and the old value of level m are read for 64 levels
-    // at a time (lane L holds level m0 + L) and handed round by lane shuffles,
-    // so no global load waits inside the chain along time
-    double cul = 0.0, cur = 0.0, cfm = 0.0, cv = 0.0;
-    for (int m = 0; m < M; ++m) {
-        const int k = m & 63;
-        if (k == 0 && m + lane < M) {
-            const double *row = u + (size_t)(m + lane) * N;
+    for (int m0 = 0; m0 < M; m0 += 64) {
+        const int mine = m0 + lane;
+        const bool live = mine < M;
+        double cul = 0.0, cur = 0.0, cfm = 0.0, cv = 0.0, acc = 0.0;
+        if (live) {
+            const double *row = u + (size_t)mine * N;
             cul = nl_at(row, N, n - 1);
             cur = nl_at(row, N, n + 1);
-            cfm = f[(size_t)(m + lane) * N + (n - 1)];
+            cfm = f[(size_t)mine * N + (n - 1)];
             cv = row[n - 1];
+            for (int j = 0; j < m0; ++j) acc += rs[mine - j] * tl[j];   // mine - j in 1..M-1
         }
-        double part = 0.0;
-        for (int j = lane; j < m; j += 64) part += rs[m - j] * tl[j];
-        for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-        const double hist = part;
-        const double ul = __shfl(cul, k), ur = __shfl(cur, k), fm = __shfl(cfm, k);
-        double v = __shfl(cv, k);
-        for (int it = 0; it < 50; ++it) {
-            const double ap = 0.5 * (nl_D(q, ur) + nl_D(q, v)), am = 0.5 * (nl_D(q, ul) + nl_D(q, v));
-            const double g = rs[0] * v + hist - (ap * (ur - v) - am * (v - ul)) * ih2 - c * (ur - v) / h - fm;
-            const double dg = rs[0] + (ap + am - q * v * (ur - v) + q * v * (v - ul)) * ih2 + c / h;
-            const double dv = g / dg;
-            v -= dv;
-            if (!(fabs(dv) > 1e-15 * (1.0 + fabs(v)))) break;   // converged (or not finite)
+        const int kend = min(64, M - m0);
+        double vmine = cv;
+        for (int k = 0; k < kend; ++k) {
+            const int d = lane - k;
+            const double w = (d > 0 && live) ? rs[d] : 0.0;   // d <= mine < M
+            const double hist = nl_lane(acc, k), ul = nl_lane(cul, k), ur = nl_lane(cur, k), fm = nl_lane(cfm, k);
+            double v = nl_lane(cv, k);
+            for (int it = 0; it < 50; ++it) {
+                const double ap = 0.5 * (nl_D(q, ur) + nl_D(q, v)), am = 0.5 * (nl_D(q, ul) + nl_D(q, v));
+                const double g = rs[0] * v + hist - (ap * (ur - v) - am * (v - ul)) * ih2 - c * (ur - v) / h - fm;
+                const double dg = rs[0] + (ap + am - q * v * (ur - v) + q * v * (v - ul)) * ih2 + c / h;
+                const double dv = g / dg;
+                v -= dv;
+                if (!(fabs(dv) > 1e-15 * (1.0 + fabs(v)))) break;   // converged (or not finite)
+            }
+            if (lane == k) vmine = v;
+            if (d > 0) acc += w * v;
         }
-        if (lane == 0) {
-            tl[m] = v;
-            u[(size_t)m * N + (n - 1)] = v;
+        if (live) {
+            tl[mine] = vmine;
+            u[(size_t)mine * N + (n - 1)] = vmine;
         }
-        __syncthreads();
+        __syncthreads();   // the block's levels are in tl before the next block's history sums
     }
 }
 
@@ -95,8 +112,22 @@ __global__ void k_nl_apply(int N, int M, double h, double c, double q, const dou
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)M * N) return;
     const int m = (int)(e / N), n = (int)(e - (long)m * N) + 1;
+    // the history sum in order of j, its loads issued eight at a time so
+    // that they are in flight together rather than one after another
+    const double *col = u + (n - 1);
     double s = 0.0;
-    for (int j = 0; j <= m; ++j) s += r[m - j] * u[(size_t)j * N + (n - 1)];
+    int j = 0;
+    for (; j + 8 <= m + 1; j += 8) {
+        double x[8], w[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            x[t] = col[(size_t)(j + t) * N];
+            w[t] = r[m - j - t];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += w[t] * x[t];
+    }
+    for (; j <= m; ++j) s += r[m - j] * col[(size_t)j * N];
     const double *row = u + (size_t)m * N;
     const double uc = row[n - 1], ul = nl_at(row, N, n - 1), ur = nl_at(row, N, n + 1);
     const double ap = 0.5 * (nl_D(q, ur) + nl_D(q, uc)), am = 0.5 * (nl_D(q, ul) + nl_D(q, uc));
