@@ -64,7 +64,7 @@ __global__ __launch_bounds__(64) void k_nl_sweep(int N, int M, double h, double 
     const int n = (colour == 0 ? 2 : 1) + 2 * (int)blockIdx.x;   // the grid holds the colour's points only
     for (int j = lane; j < M; j += 64) rs[j] = r[j];
     __syncthreads();
-    const double ih2 = 1.0 / (h * h);
+    const double ih2 = 1.0 / (h * h), ch = c / h, r0 = rs[0];
     for (int m0 = 0; m0 < M; m0 += 64) {
         const int mine = m0 + lane;
         const bool live = mine < M;
@@ -86,8 +86,8 @@ __global__ __launch_bounds__(64) void k_nl_sweep(int N, int M, double h, double 
             double v = nl_lane(cv, k);
             for (int it = 0; it < 50; ++it) {
                 const double ap = 0.5 * (nl_D(q, ur) + nl_D(q, v)), am = 0.5 * (nl_D(q, ul) + nl_D(q, v));
-                const double g = rs[0] * v + hist - (ap * (ur - v) - am * (v - ul)) * ih2 - c * (ur - v) / h - fm;
-                const double dg = rs[0] + (ap + am - q * v * (ur - v) + q * v * (v - ul)) * ih2 + c / h;
+                const double g = r0 * v + hist - (ap * (ur - v) - am * (v - ul)) * ih2 - ch * (ur - v) - fm;
+                const double dg = r0 + (ap + am - q * v * (ur - v) + q * v * (v - ul)) * ih2 + ch;
                 const double dv = g / dg;
                 v -= dv;
                 if (!(fabs(dv) > 1e-15 * (1.0 + fabs(v)))) break;   // converged (or not finite)
