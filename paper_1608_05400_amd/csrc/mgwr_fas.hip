@@ -139,15 +139,18 @@ __global__ void k_nl_apply(int N, int M, double h, double c, double q, const dou
     out[e] = v;
 }
 
-// Full weighting [1 2 1] / 4 to the coarse grid (coarse J on fine 2J).
-__global__ void k_nl_restrict(int Nf, int M, const double *src, double *dst)
+// Full weighting [1 2 1] / 4 to the coarse grid (coarse J on fine 2J), into
+// dst and, when dst2 is not null, into dst2 as well.
+__global__ void k_nl_restrict(int Nf, int M, const double *src, double *dst, double *dst2)
 {
     const int Nc = (Nf - 1) / 2;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)M * Nc) return;
     const int m = (int)(e / Nc), J = (int)(e - (long)m * Nc) + 1;
     const double *row = src + (size_t)m * Nf;
-    dst[e] = 0.25 * (nl_at(row, Nf, 2 * J - 1) + 2.0 * nl_at(row, Nf, 2 * J) + nl_at(row, Nf, 2 * J + 1));
+    const double v = 0.25 * (nl_at(row, Nf, 2 * J - 1) + 2.0 * nl_at(row, Nf, 2 * J) + nl_at(row, Nf, 2 * J + 1));
+    dst[e] = v;
+    if (dst2) dst2[e] = v;
 }
 
 // uf += linear interpolation of (uc - uc0), zero coarse boundary values.
@@ -162,18 +165,35 @@ __global__ void k_nl_prolong_diff(int Nc, int M, const double *uc, const double 
     uf[e] += (n % 2 == 0) ? d(n / 2) : 0.5 * (d((n - 1) / 2) + d((n + 1) / 2));
 }
 
-// out[0] = max |x_i| over n values (a NaN anywhere makes it NaN); one block.
-__global__ void k_nl_maxabs(long n, const double *x, double *out)
+// out[0] = max |x_i| over n values (a NaN anywhere makes it NaN); one block
+// of kNlMaxThreads threads.
+constexpr int kNlMaxThreads = 1024;
+
+__device__ inline double nl_absmax(double a, double v)
 {
-    __shared__ double s[kNlThreads];
+    v = fabs(v);
+    return (v > a || v != v) ? v : a;
+}
+
+__global__ __launch_bounds__(kNlMaxThreads) void k_nl_maxabs(long n, const double *x, double *out)
+{
+    __shared__ double s[kNlMaxThreads];
     double a = 0.0;
-    for (long i = threadIdx.x; i < n; i += kNlThreads) {
-        const double v = fabs(x[i]);
-        if (v > a || v != v) a = v;
+    // whole chunks of eight loads per thread, issued together (the maximum
+    // does not depend on the order), then the tail one load at a time
+    constexpr long chunk = 8L * kNlMaxThreads;
+    long i0 = 0;
+    for (; i0 + chunk <= n; i0 += chunk) {
+        double v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = x[i0 + (long)t * kNlMaxThreads + threadIdx.x];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a = nl_absmax(a, v[t]);
     }
+    for (long i = i0 + threadIdx.x; i < n; i += kNlMaxThreads) a = nl_absmax(a, x[i]);
     s[threadIdx.x] = a;
     __syncthreads();
-    for (int w = kNlThreads / 2; w > 0; w >>= 1) {
+    for (int w = kNlMaxThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             const double o = s[threadIdx.x + w];
             if (o > s[threadIdx.x] || o != o) s[threadIdx.x] = o;
@@ -227,13 +247,13 @@ struct NlSolver {
         const long nc = (long)M * C.N;
         if ((e = apply(L, L.u, L.f, 1.0, -1.0, nullptr, L.res)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_nl_restrict, dim3(blocks(nc)), dim3(kNlThreads), 0, s, L.N, M, (const double *)L.res,
-                           C.res);
+                           C.res, (double *)nullptr);
+        // coarse start R u, kept in uc0 for the correction
         hipLaunchKernelGGL(k_nl_restrict, dim3(blocks(nc)), dim3(kNlThreads), 0, s, L.N, M, (const double *)L.u,
-                           C.uc0);
+                           C.uc0, C.u);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // coarse right-hand side N_c(R u) + R (f - N(u)); coarse start R u
+        // coarse right-hand side N_c(R u) + R (f - N(u))
         if ((e = apply(C, C.uc0, nullptr, 0.0, 1.0, C.res, C.f)) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(C.u, C.uc0, sizeof(double) * nc, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
         if ((e = cycle(l - 1)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_nl_prolong_diff, dim3(blocks((long)M * L.N)), dim3(kNlThreads), 0, s, C.N, M,
                            (const double *)C.u, (const double *)C.uc0, L.u);
@@ -358,7 +378,7 @@ int fas_solve(int count, int N, int M, const double *alphas, double T, double c,
             NlLevel &top = S.lv[k];
             e = S.apply(top, top.u, top.f, 1.0, -1.0, nullptr, top.res);
             if (e != hipSuccess) break;
-            hipLaunchKernelGGL(k_nl_maxabs, dim3(1), dim3(kNlThreads), 0, S.s, ntop, (const double *)top.res,
+            hipLaunchKernelGGL(k_nl_maxabs, dim3(1), dim3(kNlMaxThreads), 0, S.s, ntop, (const double *)top.res,
                                P[i].dmax);
             if ((e = hipGetLastError()) != hipSuccess) break;
             e = hipMemcpyAsync(&hnorm[i], P[i].dmax, sizeof(double), hipMemcpyDeviceToHost, S.s);
