@@ -75,6 +75,22 @@ def test_table5_fas_iterations_on_gpu(B, row):
     assert np.abs(host(U) - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("M", [63, 64, 65, 127, 128, 129, 200, 4096])
+def test_fas_time_blocks_match_oracle(B, M):
+    """The smoother takes a time line 64 levels at a time (each level's
+    history summed in its own lane, later levels of the block added as they
+    are solved): full, partial and single-level last blocks, and the largest
+    M, against the oracle's plain sums, two cycles from zero."""
+    N = 7 if M > 1000 else 31
+    rng = np.random.default_rng(M)
+    f = 1.0 + 0.5 * rng.standard_normal((M, N))
+    ref, _ = oracle.nl_solve(N, M, 0.6, f, nu1=1, nu2=1, tol=1e-300, maxit=2)
+    U = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    info = B.fas_solve(dev(f), U, 0.6, nu1=1, nu2=1, tol=1e-300, maxit=2)
+    assert info["iters"] == 2, info
+    assert np.abs(host(U) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
 def test_fas_linear_case_is_the_direct_solution(B):
     N, M, alpha = 63, 48, 0.45
     f = np.random.default_rng(4).standard_normal((M, N))
