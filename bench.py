@@ -244,10 +244,13 @@ def fft_pass_bytes(r):
     insz = 4 if epi == 2 else 8                       # an FP32 panel, else FP64 input
     Q = (P + 1) // 2
     # the last pass writes the product; scatter-add reads the old values,
-    # scatter-diag reads the right-hand sides, the residual epilogue reads
-    # the right-hand side and the iterate (and its low part: epilogue 7; at
-    # one colour's points: epilogues 8, 9)
-    epi_bytes = 8.0 * M * P * (4 if epi == 7 else 3 if epi in (6, 8, 9) else 2 if epi in (2, 3, 4, 5) else 1)
+    # scatter-diag reads the right-hand sides (also into the colour panel:
+    # epilogue 10), the residual epilogue reads the right-hand side and the
+    # iterate (and its low part: epilogue 7; at one colour's points:
+    # epilogues 8, 9); the merge (11) reads the right-hand sides and the
+    # other colour's panel and writes both colours' points
+    epi_bytes = 8.0 * M * P * (4 if epi in (7, 11) else 3 if epi in (6, 8, 9) else
+                               2 if epi in (2, 3, 4, 5, 10) else 1)
     # from L = 512 on, the last forward pass, the spectrum and the first
     # inverse pass are one kernel: one read and one write of the array less
     work = (4 * n - 4) if L >= 512 else (4 * n - 2)

@@ -60,10 +60,18 @@ enum EpiKind {
     EPI_RESID_C = 8,     // EPI_RESID at the points of one colour: product column p is
                          //   point colour_point(p) (the other colour's residual is zero
                          //   after a red-black sweep and is neither computed nor written)
-    EPI_RESID_R = 9      // 1D, colour 0: EPI_RESID_C restricted on the fly: colour 0's
+    EPI_RESID_R = 9,     // 1D, colour 0: EPI_RESID_C restricted on the fly: colour 0's
                          //   points are the coarse points and the other colour's
                          //   residual is zero, so out[i][p] = 0.25 (2 r) is the coarse
                          //   right-hand side (full weighting)
+    EPI_STORE_DIAG = 10, // out[i][p] = diag b[i][p] + acc: EPI_SCATTER_DIAG into a
+                         //   panel of the colour's points, contiguous (1D, first
+                         //   half-sweep; the second one merges the panel into U)
+    EPI_MERGE_DIAG = 11  // 1D: EPI_SCATTER_DIAG, and beside each point of the colour
+                         //   the other colour's point paired with it (pt + 1 for
+                         //   colour 1, pt - 1 for colour 0, and n - 1 from colour 0's
+                         //   last point) from that colour's panel x, so that whole
+                         //   rows of U are written
 };
 
 struct EpiArgs {
@@ -81,6 +89,9 @@ struct EpiArgs {
     const double *F = nullptr, *U = nullptr, *lo = nullptr, *cd = nullptr, *g = nullptr;
     double ih2 = 0.0;
     long ldu = 0;              // EPI_RESID*: row length of F, U, lo (the level's points)
+    const double *x = nullptr; // EPI_MERGE_DIAG: the other colour's panel [M][ldx]
+    long ldx = 0;
+    int px = 0;                // its points per row
 };
 
 // Tile choices of the product kernels (set by the autotuner).
@@ -180,6 +191,11 @@ struct RhsArgs {
     double ih2, lam0;
     void *panel, *panel_lo;
     long ldp;
+    // 1D, fmt 0: the neighbours (the other colour's points) are read from
+    // that colour's panel X [M][ldx] of px points per row instead of U
+    const double *X = nullptr;
+    long ldx = 0;
+    int px = 0;
 };
 // Residual from a Toeplitz product already in out (the history part, or all
 // of T_M U when diag = 0): out = (F + cd g - diag U - A_h U) - out, with A_h

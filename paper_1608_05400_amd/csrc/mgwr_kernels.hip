@@ -129,7 +129,7 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
         return out[(long)i * e.ldo + p];
     } else if constexpr (EPI == EPI_SCATTER_ADD) {
         return out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)];
-    } else if constexpr (EPI == EPI_SCATTER_DIAG) {
+    } else if constexpr (EPI == EPI_SCATTER_DIAG || EPI == EPI_STORE_DIAG || EPI == EPI_MERGE_DIAG) {
         const int pb = e.b_colour < 0 ? p : colour_point(e.dims, e.n, e.b_colour, p);
         return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + pb];
     } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C || EPI == EPI_RESID_R) {
@@ -156,6 +156,21 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
     }
 }
 
+// EPI_MERGE_DIAG store of column j (1D) of row i: the colour's point pt gets
+// val; the other colour's point paired with it (pt + 1 for colour 1, while
+// inside the grid; pt - 1 for colour 0), whose index in that colour's panel
+// is j, gets xv; colour 0's last point also writes point n - 1, the other
+// colour's last one.  Every point of the row is written once.
+__device__ inline void merge_put(const EpiArgs &e, int i, int j, double val, double xv)
+{
+    GLOBAL double *row = gview_rw<double>(e.out) + (long)i * e.ldo;
+    const int pt = colour_point(1, e.n, e.colour, j);
+    const int q = e.colour == 1 ? pt + 1 : pt - 1;
+    row[pt] = val;
+    if (q < e.n) row[q] = xv;
+    if (e.colour == 0 && pt == e.n - 2) row[e.n - 1] = gview<double>(e.x)[(long)i * e.ldx + e.px - 1];
+}
+
 template <int EPI>
 __device__ inline void epi_put(const EpiArgs &e, int i, int p, double pre, double acc)
 {
@@ -170,6 +185,11 @@ __device__ inline void epi_put(const EpiArgs &e, int i, int p, double pre, doubl
         out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = acc;
     } else if constexpr (EPI == EPI_SCATTER_ADD || EPI == EPI_SCATTER_DIAG) {
         out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = pre + acc;
+    } else if constexpr (EPI == EPI_MERGE_DIAG) {
+        // (the radix-256 last pass loads the panel values ahead instead)
+        merge_put(e, i, p, pre + acc, gview<double>(e.x)[(long)i * e.ldx + min(p, e.px - 1)]);
+    } else if constexpr (EPI == EPI_STORE_DIAG) {
+        out[(long)i * e.ldo + p] = pre + acc;
     } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
         out[(long)i * e.ldo + p] = pre - acc;
     } else if constexpr (EPI == EPI_RESID_C) {
@@ -1337,7 +1357,8 @@ __global__ __launch_bounds__(256) void k_fft_pass(Grp<FftPass> grp)
 // per thread.
 template <typename T, int EPI = -1> constexpr int fft_lds_cols()
 {
-    return (sizeof(T) == 4 && EPI != EPI_SCATTER && EPI != EPI_SCATTER_ADD && EPI != EPI_SCATTER_DIAG) ? 32 : 16;
+    return (sizeof(T) == 4 && EPI != EPI_SCATTER && EPI != EPI_SCATTER_ADD && EPI != EPI_SCATTER_DIAG &&
+            EPI != EPI_MERGE_DIAG) ? 32 : 16;
 }
 template <typename T, int EPI = -1> constexpr int fft_lds_threads() { return 16 * fft_lds_cols<T, EPI>(); }
 
@@ -1445,6 +1466,34 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
                     }
                     continue;
                 }
+            }
+            if constexpr (EPI == EPI_MERGE_DIAG) {
+                // the other colour's values beside the two columns, loaded
+                // with the right-hand sides ahead of the stores (clamped:
+                // colour 1's last column has no partner)
+                const int j0 = min(cc, a.P - 1), j1 = min(cc + 1, a.P - 1), xl = a.ea.px - 1;
+#pragma unroll
+                for (int k0 = 0; k0 < R2; k0 += CH) {
+                    double pre[CH][2], xv[CH][2];
+#pragma unroll
+                    for (int k = 0; k < CH; ++k) {
+                        const int tau = min(base + (k1 + R1 * (k0 + k)) * a.Ns, a.M - 1);
+                        const GLOBAL double *xr = gview<double>(a.ea.x) + (long)tau * a.ea.ldx;
+                        pre[k][0] = epi_pre<EPI>(a.ea, tau, j0);
+                        pre[k][1] = epi_pre<EPI>(a.ea, tau, j1);
+                        xv[k][0] = xr[min(j0, xl)];
+                        xv[k][1] = xr[min(j1, xl)];
+                    }
+#pragma unroll
+                    for (int k = 0; k < CH; ++k) {
+                        const int tau = base + (k1 + R1 * (k0 + k)) * a.Ns;
+                        if (tau >= a.M) continue;
+                        if (cc < a.P) merge_put(a.ea, tau, cc, pre[k][0] + (double)v[k0 + k].x * a.scale, xv[k][0]);
+                        if (cc + 1 < a.P)
+                            merge_put(a.ea, tau, cc + 1, pre[k][1] + (double)v[k0 + k].y * a.scale, xv[k][1]);
+                    }
+                }
+                continue;
             }
 #pragma unroll
             for (int k0 = 0; k0 < R2; k0 += CH) {
@@ -1787,6 +1836,8 @@ static hipError_t fft_group(const std::vector<const GemmArgs *> &as, const std::
             case EPI_RESID_DD: RET_IF((launch_fft_last<T, EPI_RESID_DD>(plan[i], ps, st, s))); break;
             case EPI_RESID_C: RET_IF((launch_fft_last<T, EPI_RESID_C>(plan[i], ps, st, s))); break;
             case EPI_RESID_R: RET_IF((launch_fft_last<T, EPI_RESID_R>(plan[i], ps, st, s))); break;
+            case EPI_STORE_DIAG: RET_IF((launch_fft_last<T, EPI_STORE_DIAG>(plan[i], ps, st, s))); break;
+            case EPI_MERGE_DIAG: RET_IF((launch_fft_last<T, EPI_MERGE_DIAG>(plan[i], ps, st, s))); break;
             default: return hipErrorInvalidValue;
             }
         }
@@ -1860,7 +1911,15 @@ template <typename S> struct OpRhsPanel {
             int k = (int)(e / Pc), j = (int)(e - (long)k * Pc);
             int pt = colour_point(a.dims, a.n, a.colour, j);
             GLOBAL double *Uk = U + (long)k * P;
-            double b = F[(long)k * P + pt] + nbr_sum(Uk, a.dims, a.n, pt) * a.ih2;
+            double ns;
+            if (a.X) {   // 1D: the neighbours pt -+ 1 are the other colour's points jl, jr of X
+                const GLOBAL double *Xk = gview<double>(a.X) + (long)k * a.ldx;
+                const int jl = a.colour == 1 ? j - 1 : j, jr = a.colour == 1 ? j : j + 1;
+                ns = (jl >= 0 ? Xk[jl] : 0.0) + (jr < a.px ? Xk[jr] : 0.0);
+            } else {
+                ns = nbr_sum(Uk, a.dims, a.n, pt);
+            }
+            double b = F[(long)k * P + pt] + ns * a.ih2;
             if (a.g) b += cd[k] * g[pt];
             panel[(long)k * a.ldp + j] = (S)b;
             if (a.lam0 != 0.0) Uk[pt] = a.lam0 * b;

@@ -108,6 +108,27 @@ def test_fft_solve_matches_direct_solve(B, prec, tol):
     assert relmax(U, ref) <= tol, (info, relmax(U, ref))
 
 
+@pytest.mark.parametrize("M", [40, 83, 255, 256, 300, 1100])
+@pytest.mark.parametrize("first", [0, 1])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fft32_colour_panels_solve(B, M, first, prec):
+    """1D mixed cycles on the FFT route: the first half-sweep writes its
+    colour's points into a panel and the second merges it into U with its
+    own (register passes below L = 512, radix-256 passes from 512 on; either
+    colour first, so that each colour is the one with the extra point)."""
+    N = 63
+    f = np.random.default_rng(M + 7 * first).standard_normal((M, N))
+    ref = oracle.direct_solve(1, N, M, 0.55, f)
+    for nu in ((1, 1), (0, 1)):
+        with B.Solver(N, M, 0.55, precision=prec, fft=2, first_colour=first, nu1=nu[0], nu2=nu[1],
+                      maxit=200) as s:
+            U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
+            info = s.solve(dev(f), U, tol=1e-12)
+            U = host(U)
+        assert info["rc"] in (0, 2), info
+        assert relmax(U, ref) <= 1e-8, (nu, info, relmax(U, ref))
+
+
 def test_fft_and_dense_routes_agree(B):
     """Same cycles, products by the two routes: the iterates agree to
     rounding and the iteration counts are the same."""
