@@ -9,11 +9,15 @@ field (paper_1608_05400_amd.workloads.config2).  One step solves both alpha
 problems from u = 0 with a V(1,1) cycle until the FP64 residual is reduced by
 --tol in the max norm.  Inputs are resident in HBM before the timed region.
 
-Modes: "bf16x3" (split-BF16 inner cycle, FP64 double-double refinement; the
-reported value), "fp64" (Algorithm 1 in FP64 on u; on the default workload it
-stops at its rounding floor above the tolerance, flagged in the JSON line),
-"fp32" (FP32 inner cycle), "fp64r" (FP64 inner cycle with double-double
-refinement: the FP64 method that reaches the tolerance).
+Modes: "fp32" (FP32 history products in the cycle on the error equation,
+FP64 double-double refinement; the reported value on this workload), "fp64"
+(Algorithm 1 in FP64 on u; on the default workload it stops at its rounding
+floor above the tolerance, flagged in the JSON line), "bf16x3" (split-BF16
+matrix-core history products where the autotuner finds them faster, else
+FP32), "fp64r" (FP64 cycle on the error with double-double refinement: the
+FP64 method that reaches the tolerance).  Each mode's `dtype` lists the
+arithmetic its Toeplitz products actually ran in, from the library's
+per-launch records, and `products_ms_per_step` their time by arithmetic.
 
 Before the timed steps each handle is autotuned (FFT or dense route per
 level, tile shapes of the dense product kernels, and D&C base blocks with
@@ -22,9 +26,13 @@ like handle creation.  The timed steps issue the products one by one between
 HIP events (the roofline's launch times); one more step replays the recorded
 HIP graphs and is reported beside them.
 
---workload batch solves 256 independent 1D problems of uneven size (N in
-{127..2047}, M in {256..8192}, alpha in (0.1, 0.9), seeded) as one batch:
-every stage of their cycles is one launch over all problems still iterating.
+The default run also measures, as `extra_workloads`, the 2D problem
+(N = 511 per dimension, M = 2048, alpha = 0.4, u = t^2 sin(pi x) sin(pi y))
+and the batch of 256 independent 1D problems of uneven size (N in
+{127..2047}, M in {256..8192}, alpha in (0.1, 0.9), seeded; every stage of
+their cycles is one launch over all problems still iterating), each in the
+split-BF16 mode and in plain FP64.  `cpu_baseline` is the oracle's direct
+solve of the first problem, all of it, timed on the host's cores.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -41,7 +49,6 @@ import numpy as np
 
 METRIC = "space-time unknowns/sec to 1e-10 rel residual, mixed vs FP64 MGWR, 1 GPU"
 PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0}   # MI355X dense: FP64, FP32, BF16 MFMA
-MODE_DTYPE = {0: "f64", 1: "f32", 2: "bf16"}
 
 
 def log(*a):
@@ -135,6 +142,8 @@ class _SingleRunner:
 
 def run_mode(mode, wls, fs, steps, warmup, tol, check, profile, batch=False, autotune=True,
              smoother="inverse", graph_step=True):
+    """Autotune, warm up, then time `steps` solves of every problem of the
+    workload in one precision mode; returns (results, product records)."""
     import torch
     from paper_1608_05400_amd import binding as B
     runner = (_BatchRunner if batch else _SingleRunner)(B, wls, mode, smoother)
@@ -179,6 +188,8 @@ def run_mode(mode, wls, fs, steps, warmup, tol, check, profile, batch=False, aut
     unknowns = sum(w.unknowns for w in wls)
     res = {
         "mode": mode,
+        "dtype": dtype_label(records),
+        "products_ms_per_step": products_by_dtype(records, steps),
         "value": unknowns * steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
         "iters": summ([i["iters"] for i in infos]),
@@ -226,42 +237,35 @@ def measured_traffic(kernel_name):
 HBM_PEAK_GBS = 8000.0
 
 
-def fft_pass_bytes(r):
-    """Bytes the FFT route of one product must move: its first forward pass
-    reads the K x P input once and writes the L x ceil(P/2) complex work
-    array; each other pass reads and writes that array; the last inverse pass
-    reads it and writes the M x P FP64 product (and reads it first when the
-    epilogue reads).  n passes per direction: ceil(log2(L) / 8) from
-    L = 512 on (radix-256 passes), ceil(log2(L) / 5) below."""
-    M, P, K, kid = r["M"], r["P"], r["K"], r["kernel"]
-    mode, epi = (kid >> 4) & 15, kid & 15
-    L = 64
-    while L < 2 * M:
-        L *= 2
-    lg = L.bit_length() - 1
-    n = (lg + 7) // 8 if L >= 512 else (lg + 4) // 5
-    c = 16 if mode == 0 else 8                        # complex FP64 / FP32
-    insz = 4 if epi == 2 else 8                       # an FP32 panel, else FP64 input
-    Q = (P + 1) // 2
-    # the last pass writes the product; scatter-add reads the old values,
-    # scatter-diag reads the right-hand sides (also into the colour panel:
-    # epilogue 10), the residual epilogue reads the right-hand side and the
-    # iterate (and its low part: epilogue 7; at one colour's points:
-    # epilogues 8, 9); the merge (11) reads the right-hand sides and the
-    # other colour's panel and writes both colours' points
-    epi_bytes = 8.0 * M * P * (4 if epi in (7, 11) else 3 if epi in (6, 8, 9) else
-                               2 if epi in (2, 3, 4, 5, 10) else 1)
-    # from L = 512 on, the last forward pass, the spectrum and the first
-    # inverse pass are one kernel: one read and one write of the array less
-    work = (4 * n - 4) if L >= 512 else (4 * n - 2)
-    return K * P * insz + work * L * Q * c + epi_bytes
+DTYPE_OF_MODE = {0: "f64", 1: "f32", 2: "bf16x3"}
 
 
-def roofline_of(records, steps):
-    """Dominant Toeplitz-product kernel (largest total time) and its achieved
-    rate from the per-launch HIP events: algorithmic FLOP/s against the matrix
-    cores for the dense kernels, bytes/s against HBM for the FFT route (its
-    finest-level launches)."""
+def products_by_dtype(records, steps):
+    """Milliseconds per step of the Toeplitz products by the arithmetic they
+    ran in (kernel id bits 4..7), from the per-launch records."""
+    out = {}
+    for r in records:
+        k = DTYPE_OF_MODE[(r["kernel"] >> 4) & 15]
+        out[k] = out.get(k, 0.0) + r["ms"]
+    return {k: round(v / max(1, steps), 3) for k, v in sorted(out.items(), key=lambda kv: -kv[1])}
+
+
+def dtype_label(records):
+    """The arithmetic the products actually ran in, FP64 first ("f64+f32")."""
+    seen = {DTYPE_OF_MODE[(r["kernel"] >> 4) & 15] for r in records}
+    order = [d for d in ("f64", "f32", "bf16x3") if d in seen]
+    return "+".join(order) if order else None
+
+
+def roofline_of(records, steps, batch=False):
+    """Dominant Toeplitz-product kernel class (largest total time) and its
+    achieved rate from the per-launch HIP events.  Dense kernels: algorithmic
+    FLOP/s against the matrix cores of their dtype.  FFT route: the products'
+    own bytes (operand read once, epilogue reads and writes, as the library
+    records them per product) per second against HBM, with the bytes of the
+    passes' work arrays added in `pass_structure`; for one problem the
+    class's finest-level launches (all its levels share the three kernels),
+    for a batch all its launches."""
     if not records:
         return None
     from paper_1608_05400_amd import binding as B
@@ -274,54 +278,67 @@ def roofline_of(records, steps):
     kid = max(by, key=lambda k: by[k]["ms"])
     d = by[kid]
     mode = (kid >> 4) & 15
+    share = round(d["ms"] / sum(v["ms"] for v in by.values()), 3)
+    rs = [r for r in records if r["kernel"] == kid]
     if (kid >> 8) == 4:
-        # the FFT route's launches of the finest level (the largest products
-        # of the class; the coarser levels' are the same kernels on fewer columns)
-        rs = [r for r in records if r["kernel"] == kid]
-        top = max(r["level"] for r in rs)
-        rs = [r for r in rs if r["level"] == top]
+        if not batch:
+            top = max(r["level"] for r in rs)
+            rs = [r for r in rs if r["level"] == top]
         ms = sum(r["ms"] for r in rs)
-        nbytes = sum(fft_pass_bytes(r) for r in rs)
+        nbytes = sum(r["bytes"] for r in rs)
+        pbytes = sum(r["bytes"] + r["pass_bytes"] for r in rs)
         achieved = nbytes / (ms * 1e-3) / 1e9
         out = {
             "bound": "hbm",
             "kernel": B.kernel_name(kid),
-            "level": top,
-            "P": sorted(set(r["P"] for r in rs)),
-            "M": rs[0]["M"],
             "dtype": "f64" if mode == 0 else "f32",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
-            "algorithmic_bytes": nbytes / len(rs),
-            "launches_per_step": len(rs) // max(1, steps),
+            "bytes_per_launch": nbytes / len(rs),
+            "bytes_definition": "the product's own bytes: operand read once + epilogue reads and writes",
+            "pass_structure": {
+                "bytes_per_launch": pbytes / len(rs),
+                "achieved": round(pbytes / (ms * 1e-3) / 1e9, 1),
+                "frac": round(pbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "definition": "own bytes + the complex work arrays written and read between the passes",
+            },
+            "launches": len(rs),
+            "launches_per_step": round(len(rs) / max(1, steps), 2),
             "avg_launch_ms": round(ms / len(rs), 4),
-            "dense_equivalent_tflops": round(sum(r["flops"] for r in rs) / (ms * 1e-3) / 1e12, 1),
-            "share_of_product_time": round(d["ms"] / sum(v["ms"] for v in by.values()), 3),
+            "share_of_product_time": share,
         }
-        tr = measured_traffic(out["kernel"])
-        if tr and tr.get("level") == top and tr.get("P") == out["P"]:
-            out["traffic"] = tr["bytes_per_launch"]
-            out["traffic_unit"] = "bytes/launch (FETCH_SIZE x %g + WRITE_SIZE x %g)" % (tr["fetch_factor"],
-                                                                                       tr["write_factor"])
+        if not batch:
+            out["level"] = top
+            out["P"] = sorted(set(r["P"] for r in rs))
+            out["M"] = rs[0]["M"]
+            tr = measured_traffic(out["kernel"])
+            if tr and tr.get("level") == top and tr.get("P") == out["P"]:
+                out["traffic"] = tr["bytes_per_launch"]
+                out["traffic_unit"] = "bytes/launch (FETCH_SIZE x %g + WRITE_SIZE x %g)" % (tr["fetch_factor"],
+                                                                                           tr["write_factor"])
         return out
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[mode]
+    nbytes = sum(r["bytes"] for r in rs)
     out = {
         "bound": "mfma",
         "kernel": B.kernel_name(kid),
-        "dtype": MODE_DTYPE[mode],
+        "dtype": DTYPE_OF_MODE[mode],
         "achieved": round(achieved, 2),
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": None,
-        "launches_per_step": d["n"] // max(1, steps),
+        "bytes_per_launch": nbytes / len(rs),
+        "hbm_gbs_of_own_bytes": round(nbytes / (d["ms"] * 1e-3) / 1e9, 1),
+        "launches": d["n"],
+        "launches_per_step": round(d["n"] / max(1, steps), 2),
         "avg_launch_ms": round(d["ms"] / d["n"], 4),
         "avg_launch_gflop": round(d["flops"] / d["n"] / 1e9, 3),
-        "share_of_product_time": round(d["ms"] / sum(v["ms"] for v in by.values()), 3),
+        "share_of_product_time": share,
     }
     if mode == 2:
         out["issued_frac"] = round(3 * achieved / peak, 4)   # three BF16 passes per product
@@ -330,9 +347,6 @@ def roofline_of(records, steps):
         out["traffic"] = tr["bytes_per_launch"]
         out["traffic_unit"] = "bytes/launch (FETCH_SIZE x %g + WRITE_SIZE x %g)" % (tr["fetch_factor"],
                                                                                    tr["write_factor"])
-        # operand read once and product written once, FP64 (8 bytes each)
-        rs = [r for r in records if r["kernel"] == kid]
-        out["algorithmic_bytes"] = sum(16.0 * r["M"] * r["P"] for r in rs) / len(rs)
     return out
 
 
@@ -395,26 +409,33 @@ def bench_fas(B, args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(w, seconds):
-    """The oracle's direct time-stepping solve on a bounded sample: the first
-    Ms time levels of the full problem; its cost is dominated by the O(N M^2)
-    history sum, so the full-problem time is scaled by (M / Ms)^2."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, levels=0):
+    """The oracle's direct time-stepping solve of one problem of the workload
+    (all M time levels unless `levels` > 0), timed on the host's cores; the
+    rate is the unknowns it solved per second, without extrapolation."""
     import oracle
     f = w.forcing()
-    oracle.direct_solve(w.dims, w.N, w.M, w.alpha, f, Mstop=64)   # load, page in
-    ms0 = min(w.M, 512)
-    t = time.perf_counter()
-    oracle.direct_solve(w.dims, w.N, w.M, w.alpha, f, Mstop=ms0)
-    t0 = time.perf_counter() - t
-    Ms = int(min(w.M, max(ms0, ms0 * math.sqrt(seconds / max(t0, 1e-3)))))
+    oracle.direct_solve(w.dims, w.N, w.M, w.alpha, f, Mstop=16)   # load, page in
+    Ms = w.M if levels <= 0 else min(levels, w.M)
     t = time.perf_counter()
     oracle.direct_solve(w.dims, w.N, w.M, w.alpha, f, Mstop=Ms)
     ts = time.perf_counter() - t
-    t_full = ts * (w.M / Ms) ** 2
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-    return {"value": w.unknowns / t_full, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
-            "sample": (f"direct time-stepping solve of {w.name}: first {Ms} of {w.M} time levels "
-                       f"took {ts:.2f} s; full-solve time scaled by (M/Ms)^2 = {t_full:.1f} s")}
+    unknowns = w.unknowns * Ms // w.M
+    what = "all" if Ms == w.M else f"the first {Ms} of the {w.M}"
+    return {"value": unknowns / ts, "unit": "unknowns/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "cpu": cpu_model(), "seconds": round(ts, 2),
+            "sample": (f"the oracle's direct time-stepping solve (Thomas per level, O(N M^2) history sum) "
+                       f"of {w.name}, {what} time levels: {unknowns} unknowns in {ts:.2f} s")}
 
 
 def calibrate_copy(mib=512, reps=3):
@@ -430,6 +451,62 @@ def calibrate_copy(mib=512, reps=3):
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": reps}), flush=True)
 
 
+# Precision modes per workload, the first one reported as `value`: the mixed
+# mode whose products actually differ from the others there.  On the 1D
+# N = 4095, M = 16384 problems every mixed product takes the FP32 FFT route
+# (split-BF16 products lose to it by 3-4x at M = 16384, so the split-BF16
+# mode runs the same FP32 products); on the 2D and batch workloads the
+# split-BF16 matrix-core products are chosen per level where they are faster.
+DEFAULT_MODES = {"1d": "fp32,fp64,bf16x3,fp64r", "2d": "bf16x3,fp64,fp32,fp64r",
+                 "2dns": "bf16x3,fp64,fp32,fp64r", "small": "fp32,fp64,bf16x3,fp64r",
+                 "batch": "bf16x3,fp64,fp32,fp64r"}
+# Workloads measured after the default one and reported beside it (mixed
+# mode and plain FP64, fewer steps).
+EXTRA = {"2d": "bf16x3,fp64", "batch": "bf16x3,fp64"}
+
+
+def log_kernels(mode, res, recs, steps):
+    for row in kernel_table(recs, steps)[:14]:
+        log(f"  {row['kernel']:22s} lvl {row['level']:2d} P {row['P']:6d}: "
+            f"{row['launches_per_step']:5.1f}/step {row['ms_per_step']:8.2f} ms/step "
+            f"avg {row['avg_ms']:7.3f} ms {row['tflops']:7.1f} TFLOP/s")
+    log(f"{mode}: {res['value']:.4g} unknowns/s, {res['ms_per_step']:.1f} ms/step, dtype {res['dtype']}, "
+        f"iters {res['iters']}, relres {res['relres']}, err {res.get('err_vs_oracle')}")
+
+
+def compare_fp64(line, results, primary):
+    """Speedup of the primary mode over the FP64 modes; a mode that stops
+    short of the tolerance (plain FP64 stagnates at its rounding floor on
+    the 1D workload) is flagged: its rate is not to the same accuracy."""
+    p = results[primary]
+    for m in ("fp64", "fp64r"):
+        if m in results and primary != m:
+            line["speedup_vs_" + m] = p["value"] / results[m]["value"]
+            st = results[m]["status"]   # per problem, or counts per status
+            line[m + "_reaches_tol"] = all(x == "ok" for x in st) if isinstance(st, list) else set(st) == {"ok"}
+
+
+def run_workload(name, modes, args, steps, warmup, all_steps=True):
+    """Every mode of one workload; returns (results, rooflines, name)."""
+    import torch
+    wls, wname = make_workloads(name)
+    fs = [w.forcing_torch("cuda").contiguous() for w in wls]
+    torch.cuda.synchronize()
+    log(f"workload {wname}: {sum(w.unknowns for w in wls)} unknowns per step")
+    results, rooflines = {}, {}
+    for i, mode in enumerate(modes):
+        k = steps if (i < 2 or all_steps is False) else 1
+        res, recs = run_mode(mode, wls, fs, k, warmup if i < 2 else 0, args.tol, not args.no_check,
+                             profile=not args.no_profile, batch=name == "batch",
+                             autotune=not args.no_autotune, smoother=args.smoother, graph_step=i < 2 and all_steps)
+        results[mode] = res
+        rooflines[mode] = roofline_of(recs, k, batch=name == "batch")
+        log_kernels(mode, res, recs, k)
+    del fs
+    torch.cuda.empty_cache()
+    return results, rooflines, wname
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,11 +518,13 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 512 MiB device copy three times (profiler counter calibration)")
-    ap.add_argument("--modes", default="bf16x3,fp64,fp32,fp64r")
+    ap.add_argument("--modes", default=None, help="comma-separated precision modes, the first one reported")
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-levels", type=int, default=0,
+                    help="time the oracle on the first K time levels only (default: the whole solve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 2D and batch workloads of the default run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU (one problem or one batch per GPU); --gpus must be 1",
@@ -462,28 +541,8 @@ def main():
     B.load()
     if args.workload == "fas":
         return bench_fas(B, args)
-    wls, wname = make_workloads(args.workload)
-    fs = [w.forcing_torch("cuda").contiguous() for w in wls]
-    torch.cuda.synchronize()
-    log(f"workload {wname}: {sum(w.unknowns for w in wls)} unknowns per step")
-
-    modes = [m.strip() for m in args.modes.split(",") if m.strip()]
-    results = {}
-    rooflines = {}
-    for i, mode in enumerate(modes):
-        steps = args.steps if i < 2 else max(1, min(args.steps, 1))
-        res, recs = run_mode(mode, wls, fs, steps, args.warmup if i < 2 else 0, args.tol,
-                             not args.no_check, profile=not args.no_profile, batch=args.workload == "batch",
-                             autotune=not args.no_autotune, smoother=args.smoother, graph_step=i < 2)
-        results[mode] = res
-        rooflines[mode] = roofline_of(recs, steps)
-        for row in kernel_table(recs, steps)[:14]:
-            log(f"  {row['kernel']:22s} lvl {row['level']:2d} P {row['P']:6d}: "
-                f"{row['launches_per_step']:5.1f}/step {row['ms_per_step']:8.2f} ms/step "
-                f"avg {row['avg_ms']:7.3f} ms {row['tflops']:7.1f} TFLOP/s")
-        log(f"{mode}: {res['value']:.4g} unknowns/s, {res['ms_per_step']:.1f} ms/step, "
-            f"iters {res['iters']}, relres {res['relres']}, err {res.get('err_vs_oracle')}")
-
+    modes = [m.strip() for m in (args.modes or DEFAULT_MODES[args.workload]).split(",") if m.strip()]
+    results, rooflines, wname = run_workload(args.workload, modes, args, args.steps, args.warmup)
     primary = modes[0]
     p = results[primary]
     line = {
@@ -497,7 +556,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+bf16x3" if primary == "bf16x3" else ("f64+f32" if primary == "fp32" else "f64"),
+        "dtype": p["dtype"] or "f64",
         "data": "synthetic",
         "config": {"workload": wname, "mode": primary, "cycle": "V(1,1)", "tol": args.tol,
                    "norm": "max", "smoother": args.smoother, "autotuned": not args.no_autotune},
@@ -505,18 +564,23 @@ def main():
         "modes": results,
         "rooflines": rooflines,
     }
-    # FP64 modes compared with the primary one; a mode that stops short of
-    # the tolerance (plain FP64 stagnates at its rounding floor) is flagged:
-    # its rate is not to the same accuracy
-    for m in ("fp64", "fp64r"):
-        if m in results and primary != m:
-            line["speedup_vs_" + m] = p["value"] / results[m]["value"]
-            st = results[m]["status"]   # per problem, or counts per status
-            line[m + "_reaches_tol"] = all(x == "ok" for x in st) if isinstance(st, list) else set(st) == {"ok"}
+    compare_fp64(line, results, primary)
+    if args.workload == "1d" and not args.no_extra and not args.modes:
+        extra = {}
+        for name, ms in EXTRA.items():
+            em = ms.split(",")
+            r, rl, en = run_workload(name, em, args, min(args.steps, 2), 1, all_steps=False)
+            e = {"workload": en, "mode": em[0], "value": r[em[0]]["value"], "unit": "unknowns/s",
+                 "ms_per_step": r[em[0]]["ms_per_step"], "dtype": r[em[0]]["dtype"],
+                 "roofline": rl[em[0]], "modes": r}
+            compare_fp64(e, r, em[0])
+            extra[name] = e
+        line["extra_workloads"] = extra
     if not args.no_cpu_baseline:
+        wls, _ = make_workloads(args.workload)
         log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
-        log(f"cpu baseline: {line['cpu_baseline']['value']:.4g} unknowns/s")
+        line["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_levels)
+        log(f"cpu baseline: {line['cpu_baseline']['value']:.4g} unknowns/s in {line['cpu_baseline']['seconds']} s")
     print(json.dumps(line), flush=True)
 
 

@@ -184,9 +184,18 @@ int mgwr_get_options(mgwr_t h, mgwr_options *opts);
 int mgwr_set_stream(mgwr_t h, void *hip_stream);
 
 /* `sweeps` red-black waveform-relaxation steps (Section 3, eq. red-black;
- * Section 6, eq. red-black_2d) on the finest level, in place on u, in FP64:
- * for each colour in turn, every point p of that colour gets the solution x
- * of (T_M + sigma I) x = f_p + c d g_p + (sum of neighbours of p)/h^2. */
+ * Section 6, eq. red-black_2d) on the finest level, in place on u: for each
+ * colour in turn, every point p of that colour gets the solution x of
+ * (T_M + sigma I) x = f_p + c d g_p + (sum of neighbours of p)/h^2.
+ * Arithmetic of options.precision, as in the cycles of mgwr_solve:
+ * MGWR_FP64 and MGWR_FP64_REFINED entirely in FP64; MGWR_MIXED_FP32 and
+ * MGWR_MIXED_BF16X3 with the history part of each line solve (the product
+ * with the inverse column without its first entry) in FP32 or split BF16
+ * (levels with fewer than 128 points of a colour in FP32; on the FFT route
+ * FP32 arithmetic, or FP64 where c > 0.1 sigma), its diagonal term
+ * lambda_0 b and every grid function in FP64.  This is the smoothing step of
+ * the inner cycles of the refinement, exposed so that it can be checked on
+ * its own. */
 int mgwr_smooth(mgwr_t h, const double *f, const double *g, double *u, int sweeps);
 
 /* Residual r = f + c d_m g - T_M u - A_h u of the discrete problem (Section 2,
@@ -195,7 +204,13 @@ int mgwr_smooth(mgwr_t h, const double *f, const double *g, double *u, int sweep
 int mgwr_residual(mgwr_t h, const double *f, const double *g, const double *u, double *r,
                   double *norms);
 
-/* One cycle of Algorithm 1 (V or W per options.gamma) on u in place, FP64. */
+/* One cycle of Algorithm 1 (V or W per options.gamma) on u in place, in the
+ * arithmetic of options.precision (as mgwr_smooth; the residuals of the
+ * levels below the finest as well).  In the refinement precisions the
+ * residual before restriction is computed at the first colour's points only
+ * on the FFT route (after a red-black sweep the other colour's residual is
+ * zero up to the rounding of its line solves), as in the inner cycles of
+ * mgwr_solve; MGWR_FP64 computes it everywhere. */
 int mgwr_vcycle(mgwr_t h, const double *f, const double *g, double *u);
 
 /* Iterate until ||r_k|| <= tol ||r_0|| (norm per options; Section 7 uses a
@@ -288,15 +303,26 @@ int mgwr_batch_destroy(mgwr_batch_t b);
  * same for a double-double iterate, 8 = the residual at one colour's points
  * (inner cycles of the refinement after pre-smoothing), 9 = the same in 1D
  * with colour 0 first, written restricted to the coarse grid.
- * A record covers one launch, possibly over several problems: M and K are
- * those of the first, P the sum of the columns, flops the sum of the
- * multiply-adds that are not structurally zero, times 2.  ms covers the
- * product and, when its K range is split over several blocks, the reduce
- * kernel that applies its epilogue. */
+ * A record covers one launch, possibly over several products (of several
+ * problems): M and K are the largest of them, P the sum of their columns,
+ * and flops, bytes and pass_bytes sums of per-product values.  ms covers
+ * the product and, when its K range is split over several blocks, the
+ * reduce kernel that applies its epilogue. */
 typedef struct {
     int kernel, level, M, P, K;
-    double flops;  /* algorithmic flops of the launch                        */
-    double ms;     /* elapsed time between the two events                    */
+    double flops;      /* algorithmic flops: multiply-adds of the products that are
+                          not structurally zero, times 2                            */
+    double ms;         /* elapsed time between the two events                      */
+    double bytes;      /* the products' own HBM bytes: the operand read once (in the
+                          precision it is handed over: 8 bytes FP64, 4 FP32 or split
+                          BF16 hi + lo) plus, per output element, what the epilogue
+                          must read and write: 8 (store), 16 (read-modify-write, or
+                          the right-hand side read for the diagonal term and the
+                          value written), 16 / 24 (residual: F and the result, and
+                          the double-double low part / the other colour's neighbours) */
+    double pass_bytes; /* FFT route: the bytes its passes move through the complex
+                          work arrays on top of `bytes` (0 for the dense kernels)    */
+    int products;      /* Toeplitz products in the launch                          */
 } mgwr_kernel_record;
 
 /* on != 0 clears the records and starts recording; on == 0 stops. */

@@ -62,6 +62,7 @@ def _load():
         lib.orc_mittag_leffler.argtypes = [dd, ii, _D, _D]
         lib.orc_nl_solve.argtypes = [ii, ii, dd, dd, dd, dd, ii, ii, ii, dd, ii, _D, _D, _D]
         lib.orc_nl_solve.restype = ii
+        lib.orc_max_threads.restype = ii
         _lib = lib
     return _lib
 
@@ -219,3 +220,8 @@ def nl_solve(N, M, alpha, f, c=1.0, q=1.0, nu1=0, nu2=1, first=1, tol=1e-10, max
     hist = np.zeros(maxit + 1)
     its = _load().orc_nl_solve(N, M, alpha, T, c, q, nu1, nu2, first, tol, maxit, _dp(f), _dp(u), _dp(hist))
     return u, hist[:its + 1]
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().orc_max_threads())

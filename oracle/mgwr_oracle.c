@@ -634,3 +634,17 @@ int orc_nl_solve(int N, int M, double alpha, double T, double cc, double q, int 
     free(R); free(d); free(r);
     return it;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Threads the oracle's parallel loops use (for reporting its timings).     */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -68,7 +68,8 @@ class Tuning(ctypes.Structure):
 class KernelRecord(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("level", ctypes.c_int), ("M", ctypes.c_int),
                 ("P", ctypes.c_int), ("K", ctypes.c_int), ("flops", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("pass_bytes", ctypes.c_double),
+                ("products", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -175,7 +176,8 @@ def _records(count, get, handle):
     for i in range(n):
         _check(get(handle, i, ctypes.byref(rec)), False)
         out.append({"kernel": rec.kernel, "name": kernel_name(rec.kernel), "level": rec.level,
-                    "M": rec.M, "P": rec.P, "K": rec.K, "flops": rec.flops, "ms": rec.ms})
+                    "M": rec.M, "P": rec.P, "K": rec.K, "flops": rec.flops, "ms": rec.ms,
+                    "bytes": rec.bytes, "pass_bytes": rec.pass_bytes, "products": rec.products})
     return out
 
 

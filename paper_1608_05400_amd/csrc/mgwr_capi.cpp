@@ -445,6 +445,24 @@ double product_flops(const GemmArgs &a)
     return 2.0 * macs * a.P;
 }
 
+// HBM bytes a product itself must move: its operand read once, in the
+// precision it is handed over, and per output element what its epilogue
+// reads and writes (the FFT route's work arrays are counted apart).
+double product_bytes(const GemmArgs &a)
+{
+    double in = 8.0;
+    if (a.mode == GM_BF16X3) in = 4.0;                       // hi + lo
+    else if (a.mode == GM_F32) in = (a.fft_spec && a.fft_b64) ? 8.0 : 4.0;
+    double out = 8.0;
+    switch (a.epi) {
+    case EPI_STORE: case EPI_SCATTER: out = 8.0; break;
+    case EPI_RESID: out = 16.0; break;                        // F, R (U is the operand)
+    case EPI_RESID_DD: case EPI_RESID_C: case EPI_RESID_R: out = 24.0; break;
+    default: out = 16.0; break;                               // read-modify-write, b + x
+    }
+    return (double)a.K * a.P * in + (double)a.M * a.P * out;
+}
+
 // Kernel id of a product: (kind << 8) | (mode << 4) | epilogue, kind 0 =
 // narrow, 1 = wide 128 x 64, 2 = wide 256 x 64, 3 = split-BF16.
 int kernel_id(const GemmArgs &a)
@@ -487,10 +505,17 @@ int run_gemms(Exec &ex, const std::vector<GemmArgs> &as, int level)
         p.a = ex.prof->take();
         p.b = ex.prof->take();
         if (!p.a || !p.b) return fail(MGWR_EDEVICE, "hipEventCreate failed");
-        const GemmArgs &a0 = kv.second[0];
-        p.rec.kernel = kv.first; p.rec.level = level; p.rec.M = a0.M; p.rec.K = a0.K;
-        p.rec.P = 0; p.rec.flops = 0; p.rec.ms = 0;
-        for (const GemmArgs &a : kv.second) { p.rec.P += a.P; p.rec.flops += product_flops(a); }
+        p.rec = mgwr_kernel_record{};
+        p.rec.kernel = kv.first; p.rec.level = level;
+        for (const GemmArgs &a : kv.second) {
+            p.rec.M = std::max(p.rec.M, a.M);
+            p.rec.K = std::max(p.rec.K, a.K);
+            p.rec.P += a.P;
+            p.rec.flops += product_flops(a);
+            p.rec.bytes += product_bytes(a);
+            if (a.fft_spec) p.rec.pass_bytes += fft_work_bytes(a);
+            ++p.rec.products;
+        }
         HIPCHK(hipEventRecord(p.a, ex.s));
         HIPCHK(launch_toep_gemm(kv.second, ex.st, ex.s));
         HIPCHK(hipEventRecord(p.b, ex.s));
@@ -2030,6 +2055,7 @@ int mgwr_smooth(mgwr_t h, const double *f, const double *g, double *u, int sweep
     CHK(set_device(h));
     CHK(alloc_inner(h, h->opt.precision, uses_dc(h)));
     Hier H = plain_hier(h, f, g, u);
+    H.prec = h->opt.precision;   // the history products in the handle's arithmetic
     std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
     Exec ex{h->stream, nullptr, &h->run.prof};
     for (int s = 0; s < sweeps; ++s) CHK(sweep(ex, ts));
@@ -2062,6 +2088,7 @@ int mgwr_vcycle(mgwr_t h, const double *f, const double *g, double *u)
     CHK(set_device(h));
     CHK(alloc_inner(h, h->opt.precision, uses_dc(h)));
     Hier H = plain_hier(h, f, g, u);
+    H.prec = h->opt.precision;
     std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
     Exec ex{h->stream, nullptr, &h->run.prof};
     return cycle(ex, ts);

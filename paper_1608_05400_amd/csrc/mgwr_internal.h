@@ -269,6 +269,10 @@ hipError_t launch_fill(const std::vector<FillArgs> &v, Staging *st, hipStream_t 
 hipError_t launch_norms(const std::vector<NormArgs> &v, Staging *st, hipStream_t s);
 hipError_t launch_dd_update(const std::vector<DDArgs> &v, Staging *st, hipStream_t s);
 hipError_t launch_scatter(const std::vector<ScatterArgs> &v, Staging *st, hipStream_t s);
+// Bytes the FFT route's passes move through their complex work arrays for
+// one product (written by the first kernel, read and written by each middle
+// one, read by the last).
+double fft_work_bytes(const GemmArgs &a);
 // Fill one coefficient table (fp32 copy and bf16 fragment table) from d64.
 hipError_t launch_build_coef(ToepCoef &c, hipStream_t s);
 // Blocks of the norm partials of an n-element array.

@@ -1714,6 +1714,16 @@ static std::vector<int> fft_plan(int L)
     return r;
 }
 
+double fft_work_bytes(const GemmArgs &a)
+{
+    const std::vector<int> plan = fft_plan(a.fft_L);
+    // kernels per product: one per pass, the last forward and the first
+    // inverse pass fused when the plan ends in radix 256
+    const int kernels = 2 * (int)plan.size() - (plan.back() == 256 ? 1 : 0);
+    const double array = (double)a.fft_L * ((a.P + 1) / 2) * (a.mode == GM_F64 ? 16.0 : 8.0);
+    return 2.0 * (kernels - 1) * array;
+}
+
 template <typename T, typename TIN, int R1, int R2, int SIGN, int SRC, int DST, int EPI>
 static hipError_t launch_fft_lds(const std::vector<FftPass> &ps, Staging *st, hipStream_t s)
 {

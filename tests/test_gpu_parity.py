@@ -335,9 +335,10 @@ def test_config2_plain_fp64_reaches_its_floor(B):
     assert err <= 1e-10, err
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-8), ("fp64", 1e-10)])
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-8), ("fp32", 1e-8), ("fp64", 1e-10)])
 def test_config3_2d_full_size(B, prec, tol):
-    """2D, N = 511, M = 2048, alpha = 0.4, u = t^2 sin(pi x) sin(pi y)."""
+    """2D, N = 511, M = 2048, alpha = 0.4, u = t^2 sin(pi x) sin(pi y): every
+    precision reaches the 1e-10 relative FP64 residual of the benchmark."""
     w = W.manufactured_2d(511, 2048, 0.4)
     f = w.forcing_torch("cuda").contiguous()
     with B.Solver(w.N, w.M, w.alpha, dims=2, precision=prec) as s:
@@ -345,7 +346,8 @@ def test_config3_2d_full_size(B, prec, tol):
         info = s.solve(f, U, tol=1e-10)
         torch.cuda.synchronize()
         err = _sampled_modal_error(w, U)
-    assert info["status"] in ("ok", "stagnated") and info["relres"] <= 1e-9, info
+    print(prec, info["iters"], info["relres"], info["hist"], err)
+    assert info["status"] == "ok" and info["relres"] <= 1e-10, info
     assert err <= tol, err
 
 

@@ -294,6 +294,33 @@ def test_full_weighting_is_half_transpose_of_linear_interpolation_1d():
     assert np.allclose(Rm, 0.5 * Pm.T, atol=1e-15)
 
 
+def _transfer_matrices(dims, Nc):
+    """The oracle's restriction and interpolation assembled column by column
+    (one time level), point index l N + n (x fastest) in 2D."""
+    Nf = 2 * Nc + 1
+    nf, nc = (Nf, Nc) if dims == 1 else (Nf * Nf, Nc * Nc)
+    shf, shc = ((1, Nf), (1, Nc)) if dims == 1 else ((1, Nf, Nf), (1, Nc, Nc))
+    Rm = np.stack([oracle.restrict(dims, Nf, 1, np.eye(nf)[i].reshape(shf)).ravel() for i in range(nf)], axis=1)
+    Pm = np.stack([oracle.prolong_add(dims, Nc, 1, np.eye(nc)[j].reshape(shc), np.zeros(shf)).ravel()
+                   for j in range(nc)], axis=1)
+    return Rm, Pm
+
+
+def test_full_weighting_is_quarter_transpose_of_bilinear_interpolation_2d():
+    """Section 6 names 2D full weighting and bilinear interpolation: both are
+    tensor products of their 1D stencils, so R_2D = R_1D (x) R_1D,
+    P_2D = P_1D (x) P_1D and, from R_1D = P_1D^T / 2, R_2D = P_2D^T / 4.  A wrong
+    weight anywhere in the 9-point stencil or the interpolation breaks the
+    Kronecker structure against the pinned 1D operators."""
+    Nc = 7
+    R1, P1 = _transfer_matrices(1, Nc)
+    R2, P2 = _transfer_matrices(2, Nc)
+    assert np.allclose(R1, 0.5 * P1.T, atol=1e-15)
+    assert np.allclose(R2, np.kron(R1, R1), atol=1e-15)
+    assert np.allclose(P2, np.kron(P1, P1), atol=1e-15)
+    assert np.allclose(R2, 0.25 * P2.T, atol=1e-15)
+
+
 @pytest.mark.parametrize("dims", [1, 2])
 def test_transfers_exact_on_piecewise_linear_and_constants(dims):
     Nc, M = 15, 2
