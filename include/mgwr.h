@@ -227,6 +227,30 @@ int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol
 int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int ldb, int P,
                         double *C, int ldc);
 
+/* Bytes of the device scratch of mgwr_toeplitz_apply_static (one static
+ * array per GPU, held from library load until the process ends). */
+#define MGWR_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* mgwr_toeplitz_apply without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same products on the same kernels,
+ * with everything beyond B and C (the low-precision copy of the operand, the
+ * split-K partial sums, the FFT route's work arrays) in a static device
+ * array of MGWR_STATIC_SCRATCH_BYTES per GPU instead of the handle's
+ * buffers or temporaries.  It calls no hipMalloc, hipFree or stream
+ * synchronisation; the work is queued on the handle's stream.  Rejected with
+ * MGWR_EINVAL (nothing launched): FP32 operands of more than
+ * MGWR_STATIC_SCRATCH_BYTES (4 M P bytes), split-BF16 operands of more than
+ * that (4 Mpad ldp bytes, Mpad = M rounded up to 128, ldp = P rounded up to
+ * 128), and FFT-route products whose one column pair does not fit half of
+ * it (16 L bytes in FP64, 8 L in FP32, L the transform length >= 2M); larger
+ * FFT-route products run in chunks of columns.  Every call on one GPU uses
+ * that GPU's one array and leaves its contents behind (nothing in it needs
+ * to start at zero): calls that overlap in time on one GPU, on any streams or
+ * handles, race and give wrong results; order them on one stream. */
+int mgwr_toeplitz_apply_static(mgwr_t h, int which, int precision, const double *B, int ldb, int P,
+                               double *C, int ldc);
+
 /* Host copy of the first column (M doubles) of T_M (which = -1) or of the
  * inverse of T_M + sigma_l I on level `which`. */
 int mgwr_get_column(mgwr_t h, int which, double *out);

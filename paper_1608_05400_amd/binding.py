@@ -33,6 +33,7 @@ EXPORTED = [
     "mgwr_last_error", "mgwr_autotune", "mgwr_get_tuning", "mgwr_batch_autotune",
     "mgwr_batch_get_tuning", "mgwr_batch_profile_enable", "mgwr_batch_profile_count",
     "mgwr_batch_profile_get", "mgwr_fas_solve", "mgwr_fas_solve_batch", "mgwr_set_tuning",
+    "mgwr_toeplitz_apply_static",
 ]
 
 
@@ -111,6 +112,7 @@ def load(path: str = LIB_PATH):
     lib.mgwr_vcycle.argtypes = [h, VP, VP, VP]
     lib.mgwr_solve.argtypes = [h, VP, VP, VP, D, P(Info)]
     lib.mgwr_toeplitz_apply.argtypes = [h, I, I, VP, I, I, VP, I]
+    lib.mgwr_toeplitz_apply_static.argtypes = [h, I, I, VP, I, I, VP, I]
     lib.mgwr_get_column.argtypes = [h, I, P(D)]
     lib.mgwr_levels.argtypes = [h]
     lib.mgwr_batch_create.argtypes = [I, P(I), P(I), P(D), P(D), I, P(Options), P(h)]
@@ -397,6 +399,23 @@ class Solver:
         P = B.shape[1]
         _check(self._lib.mgwr_toeplitz_apply(self._h, which, precision, _ptr(B, "B"), P, P,
                                              _ptr(C, "C"), P), False)
+        return C
+
+    def toeplitz_apply_static(self, B, which=-1, precision=FP64, C=None):
+        """toeplitz_apply through the allocation-free entry point
+        (mgwr_toeplitz_apply_static; C must be given by callers that cannot
+        allocate)."""
+        import torch
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        if B.dim() != 2 or B.shape[0] != self.M:
+            raise ValueError("B must be [M, P]")
+        if C is None:
+            C = torch.empty_like(B)
+        self._bind_stream()
+        P = B.shape[1]
+        _check(self._lib.mgwr_toeplitz_apply_static(self._h, which, precision, _ptr(B, "B"), P, P,
+                                                    _ptr(C, "C"), P), False)
         return C
 
     def profile(self, on=True):

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmgwr.so")
-SOURCES = ["mgwr_kernels.hip", "mgwr_capi.cpp", "mgwr_fas.hip"]
+SOURCES = ["mgwr_kernels.hip", "mgwr_capi.cpp", "mgwr_fas.hip", "mgwr_scratch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

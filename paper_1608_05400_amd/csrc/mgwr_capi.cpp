@@ -391,6 +391,7 @@ struct mgwr_ctx {
     size_t fft_buf_cap = 0;
     Tuning tune;
     Runner run;
+    void *scratch = nullptr;         // this device's static scratch (mgwr_toeplitz_apply_static)
     int inner_prec = -1;             // precision the inner buffers exist for
     int inner_dc = 0;                // D&C buffers of the inner precision exist
     std::vector<void *> inner_alloc; // buffers owned by the inner hierarchy
@@ -1902,6 +1903,7 @@ int mgwr_create_ex(int N, int M, double alpha, double T, int dims, const mgwr_op
         return fail(MGWR_EDEVICE, "no HIP device available");
     }
     int rc = [&]() -> int {
+        CHK(static_scratch(h->device, &h->scratch));
         l1_weights(M, alpha, T, h->c, h->r_host, h->d_host);
         h->Mpad = (M + 127) / 128 * 128;
         // levels: finest n = N, then (n - 1) / 2 down to 1
@@ -2205,6 +2207,70 @@ int mgwr_toeplitz_apply(mgwr_t h, int which, int precision, const double *B, int
     free_list(tmp);
     if (rc >= 0 && se != hipSuccess) return fail(MGWR_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(se));
     return rc;
+}
+
+int mgwr_toeplitz_apply_static(mgwr_t h, int which, int precision, const double *B, int ldb, int P, double *C,
+                               int ldc)
+{
+    if (!h) return fail(MGWR_EINVAL, "NULL handle");
+    CHK(check_ptr(B, "B"));
+    CHK(check_ptr(C, "C"));
+    if (which < -1 || which >= (int)h->lv.size()) return fail(MGWR_EINVAL, "bad level %d", which);
+    if (P < 1 || ldb < P || ldc < P) return fail(MGWR_EINVAL, "need 1 <= P <= ldb, ldc");
+    if (precision < MGWR_FP64 || precision > MGWR_FP64_REFINED) return fail(MGWR_EINVAL, "bad precision");
+    CHK(set_device(h));
+    if (!h->scratch) CHK(static_scratch(h->device, &h->scratch));
+    char *S = (char *)h->scratch;
+    const size_t cap = MGWR_STATIC_SCRATCH_BYTES;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const ToepCoef *coef = which < 0 ? &h->tm : &h->lv[which].inv;
+    const int lev = which < 0 ? (int)h->lv.size() - 1 : which;
+    const int mode = (precision == MGWR_MIXED_FP32) ? GM_F32 : (precision == MGWR_MIXED_BF16X3) ? GM_BF16X3 : GM_F64;
+    const long M = h->M;
+    GemmArgs a = gemm_base(h, mode);
+    a.M = h->M; a.P = P; a.K = h->M; a.off = 0; a.coef = coef; a.epi = EPI_STORE;
+    a.ea.out = C; a.ea.ldo = ldc;
+    a.part = nullptr; a.part_cap = 0;
+    if (mode == GM_F64 ? fft_for(h, lev) : fft_for(h, lev, mode)) {
+        // the two work arrays in the two halves; columns beyond what they
+        // hold are transformed in chunks
+        const size_t half = cap / 2 / 256 * 256, csz = (mode == GM_F64) ? 16 : 8;
+        if ((size_t)h->fft_L * csz > half)
+            return fail(MGWR_EINVAL, "FFT route: one column pair needs %zu bytes of work array, more than half of "
+                        "the %zu-byte static scratch", (size_t)h->fft_L * csz, cap);
+        a.B = B; a.ldb = ldb;
+        if (mode == GM_F64) set_fft(h, a, which < 0 ? h->spec_tm : h->lv[which].spec_inv);
+        else set_fft32(h, a, which < 0 ? h->spec32_tm : h->lv[which].spec32_inv, true);
+        a.fft_buf0 = S; a.fft_buf1 = S + half; a.fft_buf_cap = half;
+    } else {
+        size_t used = 0;
+        if (mode == GM_F64) {
+            a.B = B; a.ldb = ldb;
+        } else if (mode == GM_F32) {
+            used = up(sizeof(float) * (size_t)M * P);
+            if (used > cap)
+                return fail(MGWR_EINVAL, "FP32 operand of %zu bytes exceeds the %zu-byte static scratch", used, cap);
+            HIPCHK(launch_operand({OperandArgs{1, h->M, h->M, P, B, ldb, S, nullptr, P, nullptr, 0.0}}, nullptr,
+                                  h->stream));
+            a.B = S; a.ldb = P;
+        } else {
+            const long ldp = packed_ld(P);
+            const size_t one = up(sizeof(uint16_t) * (size_t)h->Mpad * ldp);
+            used = 2 * one;
+            if (used > cap)
+                return fail(MGWR_EINVAL, "split-BF16 operand of %zu bytes exceeds the %zu-byte static scratch", used,
+                            cap);
+            HIPCHK(launch_operand({OperandArgs{2, h->M, h->Mpad, P, B, ldb, S, S + one, ldp, nullptr, 0.0}}, nullptr,
+                                  h->stream));
+            a.Bhi = S; a.Blo = S + one; a.ldb = ldp;
+        }
+        // split-K partials in the rest (at most what the handle's own buffer
+        // holds, so that the launch geometry is the one mgwr_toeplitz_apply uses)
+        a.part_cap = std::min(h->part_cap, cap - used);
+        a.part = a.part_cap > 0 ? S + used : nullptr;
+    }
+    HIPCHK(launch_toep_gemm({a}, nullptr, h->stream));
+    return MGWR_OK;
 }
 
 int mgwr_profile_enable(mgwr_t h, int on)

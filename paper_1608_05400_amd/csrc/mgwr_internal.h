@@ -277,5 +277,8 @@ double fft_work_bytes(const GemmArgs &a);
 hipError_t launch_build_coef(ToepCoef &c, hipStream_t s);
 // Blocks of the norm partials of an n-element array.
 int norm_partial_blocks(long n);
+// Device address of this device's static scratch (MGWR_STATIC_SCRATCH_BYTES
+// bytes); `device` must be current.  Looked up once per device.
+int static_scratch(int device, void **ptr);
 
 }  // namespace mgwr
