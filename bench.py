@@ -496,7 +496,7 @@ def run_workload(name, modes, args, steps, warmup, all_steps=True):
     results, rooflines = {}, {}
     for i, mode in enumerate(modes):
         k = steps if (i < 2 or all_steps is False) else 1
-        res, recs = run_mode(mode, wls, fs, k, warmup if i < 2 else 0, args.tol, not args.no_check,
+        res, recs = run_mode(mode, wls, fs, k, warmup if i < 2 else 1, args.tol, not args.no_check,
                              profile=not args.no_profile, batch=name == "batch",
                              autotune=not args.no_autotune, smoother=args.smoother, graph_step=i < 2 and all_steps)
         results[mode] = res

@@ -18,10 +18,15 @@ Only lambda = tau^alpha Gamma(2 - alpha) / h^2 matters, so the analysis takes
 h = 1.  The predicted two-grid factor is the largest eigenvalue modulus over
 a sample of theta.  The matrices are block lower triangular in time with the
 same 2 x 2 block on the diagonal, so in exact arithmetic their spectral radius
-is that block's and does not depend on M (``exact=True``); the factors
-printed in the paper vary with M and are matched by the eigenvalues as
-computed numerically (``exact=False``, the default), which for these
-defective matrices are spread by rounding.
+is that block's and does not depend on M (``reading="exact"``).  The factors
+printed in the paper vary with M.  They are the eigenvalues as computed
+numerically (``reading="numerical"``), which for these defective matrices
+are spread by rounding, and lie where rounding can put them: in the
+eps-pseudospectrum for eps = u ||T||_2 (u = 2^-52), whose radius
+(``reading="pseudospectral"``, the default) reproduces them
+deterministically.  ``contraction`` gives the finite-k mean contraction
+||T^k||_2^(1/k) of k two-grid cycles, the quantity an experiment of k cycles
+measures.
 
 A CPU analysis tool of the method (numpy); not part of the solve path.  The
 L1 coefficients come from the library's host code.
@@ -89,12 +94,59 @@ def _radius(T: np.ndarray, exact: bool) -> float:
     return float(max(abs(np.linalg.eigvals(T))))
 
 
+def pseudospectral_radius(T: np.ndarray, eps: float, r0: float, nphi: int = 36, iters: int = 30,
+                          phi0: float = 0.0) -> float:
+    """Radius of the eps-pseudospectrum {z : sigma_min(T - z I) <= eps}
+    reached along nphi directions (starting at angle phi0), by bisection on
+    |z| from r0 (a point of the set, such as the modulus of an eigenvalue in
+    direction phi0) to ||T||_2.  Singular values are perfectly conditioned,
+    so the result does not depend on rounding details."""
+    n = T.shape[0]
+    eye = np.eye(n)
+    phis = phi0 + 2.0 * math.pi * np.arange(nphi) / nphi
+
+    def inside(r):
+        return any(linalg.svdvals(T - r * np.exp(1j * p) * eye)[-1] <= eps for p in phis)
+
+    lo, hi = r0, float(np.linalg.norm(T, 2))
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if inside(mid):
+            lo = mid
+        else:
+            hi = mid
+    return lo
+
+
 def two_grid_factor(alpha: float, lam: float, M: int, nu1: int = 1, nu2: int = 0, ntheta: int = 64,
-                    exact: bool = False) -> float:
-    """Predicted two-grid factor: max over theta h in (0, pi/2] (ntheta samples)."""
+                    exact: bool = False, reading: str = None) -> float:
+    """Predicted two-grid factor, max over theta h in (0, pi/2] (ntheta
+    samples): the exact spectral radius ("exact"), the largest modulus of the
+    numerically computed eigenvalues ("numerical"), or the eps-pseudospectral
+    radius for eps = u ||T||_2 ("pseudospectral", the default; evaluated at the
+    sample where the exact radius is largest: both decrease with theta)."""
+    reading = reading or ("exact" if exact else "pseudospectral")
     Tm = time_matrix(M, alpha, lam)
     thetas = np.linspace(math.pi / 2, 0.0, ntheta, endpoint=False)[::-1]
-    return max(_radius(two_grid_symbol(t, Tm, nu1, nu2), exact) for t in thetas)
+    if reading in ("exact", "numerical"):
+        return max(_radius(two_grid_symbol(t, Tm, nu1, nu2), reading == "exact") for t in thetas)
+    if reading != "pseudospectral":
+        raise ValueError(f"unknown reading {reading}")
+    syms = [two_grid_symbol(t, Tm, nu1, nu2) for t in thetas]
+    blocks = [np.linalg.eigvals(T[np.ix_([0, M], [0, M])]) for T in syms]
+    i = int(np.argmax([max(abs(w)) for w in blocks]))
+    mu = blocks[i][np.argmax(abs(blocks[i]))]
+    T = syms[i]
+    eps = np.finfo(float).eps * np.linalg.norm(T, 2)
+    return pseudospectral_radius(T, eps, abs(mu), phi0=float(np.angle(mu)))
+
+
+def contraction(alpha: float, lam: float, M: int, k: int, nu1: int = 1, nu2: int = 0, ntheta: int = 64) -> float:
+    """Mean contraction of k two-grid cycles, max over theta of ||T^k||_2^(1/k)."""
+    Tm = time_matrix(M, alpha, lam)
+    thetas = np.linspace(math.pi / 2, 0.0, ntheta, endpoint=False)[::-1]
+    return max(np.linalg.norm(np.linalg.matrix_power(two_grid_symbol(t, Tm, nu1, nu2), k), 2) ** (1.0 / k)
+               for t in thetas)
 
 
 # ---------------------------------------------------------------------------

@@ -15,10 +15,39 @@ from paper_1608_05400_amd import sama
 @pytest.mark.parametrize("row", load_golden("table2_wcycle_1d.txt"))
 def test_table2_predicted_two_grid_factor(row):
     """Section 4, Table 2: alpha = 0.4, one pre-smoothing step; the predicted
-    column, which the numerically computed eigenvalues of the symbol match."""
+    column, which the pseudospectral radius of the symbol at eps = u ||T||_2
+    reproduces (the region where rounding puts the eigenvalues of these
+    defective matrices; singular values do not depend on rounding details)."""
     l2lam, M, predicted, _measured = row
-    rho = sama.two_grid_factor(0.4, 2.0 ** l2lam, int(M))
+    rho = sama.two_grid_factor(0.4, 2.0 ** l2lam, int(M), reading="pseudospectral")
     assert abs(rho - predicted) <= 0.004, rho
+
+
+@pytest.mark.parametrize("row", load_golden("table2_wcycle_1d.txt"))
+def test_table2_measured_factor_is_the_finite_cycle_contraction(row):
+    """Section 4, Table 2, the bracketed factors measured with the W-cycle:
+    the two-grid contraction of M cycles, ||T^M||_2^(1/M), lies within 0.008
+    of them, while the exact spectral radius does not depend on M."""
+    l2lam, M, _predicted, measured = row
+    q = sama.contraction(0.4, 2.0 ** l2lam, int(M), int(M), ntheta=16)
+    rho = sama.two_grid_factor(0.4, 2.0 ** l2lam, int(M), reading="exact")
+    assert abs(q - measured) <= 0.008, q
+    assert rho <= q + 1e-12
+
+
+@pytest.mark.parametrize("l2lam,M", [(0, 32), (2, 64)])
+def test_numerical_eigenvalues_lie_in_the_pseudospectrum(l2lam, M):
+    """The numerical reading, as a comparison: a backward-stable eigenvalue
+    solver returns exact eigenvalues of T + E with ||E||_2 <= p(n) u ||T||_2,
+    so their moduli lie between the exact radius and the pseudospectral
+    radius at that eps (p(n) = 2n here)."""
+    Tm = sama.time_matrix(M, 0.4, 2.0 ** l2lam)
+    T = sama.two_grid_symbol(math.pi / 128, Tm)
+    mu = sama._radius(T, True)
+    num = sama._radius(T, False)
+    eps = 2 * T.shape[0] * np.finfo(float).eps * np.linalg.norm(T, 2)
+    ps = sama.pseudospectral_radius(T, eps, mu, phi0=math.pi)
+    assert mu - 1e-12 <= num <= ps + 1e-12, (mu, num, ps)
 
 
 def test_exact_radius_does_not_depend_on_M():
