@@ -195,7 +195,8 @@ int mgwr_set_stream(mgwr_t h, void *hip_stream);
  * FP32 arithmetic, or FP64 where c > 0.1 sigma), its diagonal term
  * lambda_0 b and every grid function in FP64.  This is the smoothing step of
  * the inner cycles of the refinement, exposed so that it can be checked on
- * its own. */
+ * its own: in those precisions f and u are copied into the refinement's
+ * internal hierarchy (its levels stored split by colour) and u back. */
 int mgwr_smooth(mgwr_t h, const double *f, const double *g, double *u, int sweeps);
 
 /* Residual r = f + c d_m g - T_M u - A_h u of the discrete problem (Section 2,

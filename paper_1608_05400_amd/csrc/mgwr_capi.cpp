@@ -87,12 +87,17 @@ int mgwr::set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 
 namespace {
 
+// A failed runtime call is reported through the return code; the runtime's
+// last-error state is cleared, so that a later launch check does not report
+// it again (a failed allocation is not a device fault).
 #define HIPCHK(expr)                                                                            \
     do {                                                                                        \
         hipError_t e_ = (expr);                                                                 \
-        if (e_ != hipSuccess)                                                                   \
+        if (e_ != hipSuccess) {                                                                 \
+            (void)hipGetLastError();                                                            \
             return fail(e_ == hipErrorOutOfMemory ? MGWR_ENOMEM : MGWR_EDEVICE, "%s: %s (%s:%d)", \
                         #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+        }                                                                                       \
     } while (0)
 
 #define CHK(expr)                  \
@@ -409,9 +414,11 @@ int dmalloc(std::vector<void *> &list, void **p, size_t bytes)
 {
     if (bytes == 0) bytes = 16;
     hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        (void)hipGetLastError();   // reported here; not left for a later launch check
         return fail(e == hipErrorOutOfMemory ? MGWR_ENOMEM : MGWR_EDEVICE,
                     "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+    }
     list.push_back(*p);
     return MGWR_OK;
 }
@@ -726,8 +733,14 @@ struct Hier {
     mgwr_ctx *h = nullptr;
     int prec = MGWR_FP64;         // precision of the products (enum mgwr_precision)
     std::vector<double *> u, f;   // per level
-    const double *g = nullptr;    // initial condition on the finest level (plain FP64 only)
+    const double *g = nullptr;    // initial condition on the finest level (natural order)
     double *rscratch = nullptr;   // residual scratch [M][P_fine]
+    // storage order of every level (lay_pos): the refinement's inner
+    // hierarchy keeps each level split by colour, so that the points of a
+    // half-sweep and the neighbours its right-hand sides read are contiguous;
+    // the plain FP64 hierarchy, whose finest level is the caller's array,
+    // keeps the natural order
+    int split = 0;
 };
 struct Task {
     Hier *H;
@@ -769,6 +782,7 @@ int dc_half_sweep(Exec &ex, const std::vector<DcItem> &items)
         const int Pc = L.Pc[d.colour];
         rhs.push_back(RhsArgs{0, h->dims, L.n, d.colour, h->M, h->Mpad, d.t.H->f[d.t.lev], d.t.H->u[d.t.lev],
                               h->cd, fine ? d.t.H->g : nullptr, L.ih2, 0.0, h->panel64, nullptr, Pc});
+        rhs.back().split = d.t.H->split;
         const int Mb = dc_block_of(h, d.t.lev);
         nbmax = std::max(nbmax, (h->M + Mb - 1) / Mb);
     }
@@ -831,7 +845,8 @@ int dc_half_sweep(Exec &ex, const std::vector<DcItem> &items)
     for (const DcItem &d : items) {
         mgwr_ctx *h = d.t.H->h;
         Level &L = h->lv[d.t.lev];
-        sc.push_back(ScatterArgs{h->dims, L.n, d.colour, h->M, L.Pc[d.colour], h->xpanel, d.t.H->u[d.t.lev]});
+        sc.push_back(ScatterArgs{h->dims, L.n, d.colour, h->M, L.Pc[d.colour], h->xpanel, d.t.H->u[d.t.lev],
+                                 d.t.H->split});
     }
     HIPCHK(launch_scatter(sc, ex.st, ex.s));
     return MGWR_OK;
@@ -847,7 +862,7 @@ int dc_half_sweep(Exec &ex, const std::vector<DcItem> &items)
 bool colour_panels(const Task &t)
 {
     const mgwr_ctx *h = t.H->h;
-    if (h->dims != 1 || !h->xcol || dc_block_of(h, t.lev) > 0) return false;
+    if (t.H->split || h->dims != 1 || !h->xcol || dc_block_of(h, t.lev) > 0) return false;
     const Level &L = h->lv[t.lev];
     for (int c = 0; c < 2; ++c) {
         if (L.Pc[c] == 0) return false;
@@ -882,20 +897,28 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
         const bool fine = (t.lev == (int)h->lv.size() - 1);
         const double *g = fine ? t.H->g : nullptr;
         const int mode = level_mode(*t.H, Pc);
+        const int split = t.H->split;
+        const long off = split ? lay_cpos(h->dims, L.n, 1, colour, 0) : 0;   // the colour's first point
         GemmArgs a = gemm_base(h, mode);
         a.M = h->M; a.P = Pc; a.K = h->M; a.off = 0;
         a.ea.out = t.H->u[t.lev]; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n; a.ea.colour = colour;
+        auto push_rhs = [&](RhsArgs r) {
+            r.split = split;
+            rhs.push_back(r);
+        };
         // On the FFT route, a zero iterate (first half-sweep of a level that
         // starts from zero, no initial-condition term) makes the right-hand
         // sides the colour's points of F: the products read them there and
         // no panel is built.
         const bool from_f = t.zero && !g;
         auto rhs_panel = [&]() {
-            if (from_f) {
+            if (from_f && split) {
+                a.B = t.H->f[t.lev] + off; a.ldb = L.P;
+            } else if (from_f) {
                 a.B = t.H->f[t.lev]; a.ldb = L.P; a.b_colour = colour;
             } else {
-                rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd,
-                                      g, L.ih2, 0.0, h->panel64, nullptr, Pc});
+                push_rhs(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd,
+                                 g, L.ih2, 0.0, h->panel64, nullptr, Pc});
                 a.B = h->panel64; a.ldb = Pc;
             }
         };
@@ -904,8 +927,8 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
             set_fft(h, a, L.spec_inv);
             rhs_panel();
         } else if (mode == GM_F64) {
-            rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
-                                  L.ih2, 0.0, h->panel64, nullptr, Pc});
+            push_rhs(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
+                             L.ih2, 0.0, h->panel64, nullptr, Pc});
             a.coef = &L.inv; a.epi = EPI_SCATTER; a.B = h->panel64; a.ldb = Pc;
         } else if (fft_for(h, t.lev, mode) && h->c > kFft32MaxHist * L.sigma) {
             a.mode = GM_F64; a.coef = &L.inv; a.epi = EPI_SCATTER;
@@ -930,14 +953,22 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
             }
             a.ea.b = (const double *)a.B; a.ea.ldb_diag = a.ldb; a.ea.b_colour = a.b_colour;
         } else if (mode == GM_F32) {
-            rhs.push_back(RhsArgs{1, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
-                                  L.ih2, L.lam0, h->panel32, nullptr, Pc});
+            push_rhs(RhsArgs{1, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
+                             L.ih2, L.lam0, h->panel32, nullptr, Pc});
             a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.B = h->panel32; a.ldb = Pc;
         } else {
             const long ldp = packed_ld(Pc);
-            rhs.push_back(RhsArgs{2, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
-                                  L.ih2, L.lam0, h->pk_hi, h->pk_lo, ldp});
+            push_rhs(RhsArgs{2, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
+                             L.ih2, L.lam0, h->pk_hi, h->pk_lo, ldp});
             a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+        }
+        if (split) {
+            // the colour's points are contiguous from `off`: the scatters are
+            // plain stores there
+            a.ea.out = t.H->u[t.lev] + off;
+            if (a.epi == EPI_SCATTER) a.epi = EPI_STORE;
+            else if (a.epi == EPI_SCATTER_ADD) a.epi = EPI_ADD;
+            else if (a.epi == EPI_SCATTER_DIAG) a.epi = EPI_STORE_DIAG;
         }
         prods.push_back(a);
     }
@@ -981,6 +1012,18 @@ bool colour_residual(const Task &t)
     return t.H->prec != MGWR_FP64 && t.H->h->opt.nu1 >= 1 && residual_fft(t);
 }
 
+// A level that starts the cycle from zero and is pre-smoothed by one
+// red-black sweep needs no residual product: the first half-sweep solved the
+// first colour's line systems with zero neighbours, so after the second
+// half-sweep the first colour's residual is ih2 times the neighbour sum of
+// the second colour's new values, and the second colour's residual is zero
+// (exact in exact arithmetic; its rounding is that of the line solves).  The
+// restriction computes it on the fly from the iterate.
+bool implicit_residual(const Task &t)
+{
+    return t.zero && t.H->h->opt.nu1 == 1;
+}
+
 // In 1D with colour 0 relaxed first, the colour-0 points are exactly the
 // coarse points, so full weighting of a residual that is zero at colour 1
 // is 0.25 (2 r) at each of them: the residual kernel writes the coarse
@@ -1008,9 +1051,11 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
         level = t.lev;
         const int mode = level_mode(*t.H, L.P);
         double *out = t.H->rscratch;
+        const int split = t.H->split;
         GemmArgs a = gemm_base(h, mode);
         a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.epi = EPI_STORE;
         a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
+        a.ea.lay_in = a.ea.lay_out = split;
         if (mode == GM_F64) {
             a.coef = &h->tm; a.B = t.H->u[t.lev]; a.ldb = L.P;
             if (fft_for(h, t.lev)) set_fft(h, a, h->spec_tm);
@@ -1037,7 +1082,8 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
                 const int colour = h->opt.first_colour;
                 a.epi = EPI_RESID_C;
                 a.P = L.Pc[colour];
-                a.b_colour = colour;
+                if (split) a.B = t.H->u[t.lev] + lay_cpos(h->dims, L.n, 1, colour, 0);   // contiguous
+                else a.b_colour = colour;
                 a.ea.colour = colour;
                 if (restricted_residual(t)) {
                     a.epi = EPI_RESID_R;
@@ -1050,7 +1096,7 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
         }
         prods.push_back(a);
         posts.push_back(PostArgs{h->dims, L.n, h->M, t.H->f[t.lev], t.H->u[t.lev], nullptr, h->cd,
-                                 fine ? t.H->g : nullptr, L.ih2, diag, out});
+                                 fine ? t.H->g : nullptr, L.ih2, diag, out, split, split});
     }
     HIPCHK(launch_operand(ops, ex.st, ex.s));
     CHK(run_gemms(ex, prods, level));
@@ -1104,17 +1150,33 @@ int cycle(Exec &ex, const std::vector<Task> &ts)
         CHK(sweep(ex, sel));
     }
     if (fine.empty()) return MGWR_OK;
-    CHK(level_residual(ex, fine));
+    std::vector<Task> explicit_res;
+    for (const Task &t : fine)
+        if (!implicit_residual(t)) explicit_res.push_back(t);
+    CHK(level_residual(ex, explicit_res));
     std::vector<XferArgs> rs, pr;
     std::vector<FillArgs> zs;
     for (const Task &t : fine) {
         mgwr_ctx *h = t.H->h;
-        if (!restricted_residual(t))
-            rs.push_back(XferArgs{0, h->dims, h->lv[t.lev].n, h->M, t.H->rscratch, t.H->f[t.lev - 1],
-                                  colour_residual(t) ? 1 - h->opt.first_colour : -1});
+        const Level &L = h->lv[t.lev];
+        if (implicit_residual(t)) {
+            // the residual is ih2 times the neighbour sum of the second colour
+            // at the first colour's points (zero at the second's)
+            XferArgs x{0, h->dims, L.n, h->M, t.H->u[t.lev], t.H->f[t.lev - 1], 1 - h->opt.first_colour, t.H->split};
+            x.implicit = 1;
+            x.ih2 = L.ih2;
+            rs.push_back(x);
+        } else if (!restricted_residual(t)) {
+            rs.push_back(XferArgs{0, h->dims, L.n, h->M, t.H->rscratch, t.H->f[t.lev - 1],
+                                  colour_residual(t) ? 1 - h->opt.first_colour : -1, t.H->split});
+        }
         if (!skip_zero_fill(*t.H, t.lev - 1))
             zs.push_back(FillArgs{h->M, h->lv[t.lev - 1].P, nullptr, nullptr, t.H->u[t.lev - 1], 0});
-        pr.push_back(XferArgs{1, h->dims, h->lv[t.lev - 1].n, h->M, t.H->u[t.lev - 1], t.H->u[t.lev]});
+        XferArgs x{1, h->dims, h->lv[t.lev - 1].n, h->M, t.H->u[t.lev - 1], t.H->u[t.lev], -1, t.H->split};
+        // the post-smoothing's first half-sweep recomputes the first colour
+        // from the second alone: its correction would be overwritten unread
+        if (h->opt.nu2 >= 1) x.skip_colour = h->opt.first_colour;
+        pr.push_back(x);
     }
     HIPCHK(launch_xfer(rs, ex.st, ex.s));
     HIPCHK(launch_fill(zs, ex.st, ex.s));
@@ -1149,9 +1211,29 @@ Hier plain_hier(mgwr_t h, const double *f, const double *g, double *u)
 Hier inner_hier(mgwr_t h, int prec)
 {
     Hier H;
-    H.h = h; H.prec = prec; H.g = nullptr; H.rscratch = h->rs64;
+    H.h = h; H.prec = prec; H.g = nullptr; H.rscratch = h->rs64; H.split = 1;
     for (auto &L : h->lv) { H.u.push_back(L.e); H.f.push_back(L.fe); }
     return H;
+}
+
+// The caller's f and u (natural order) into the finest level of an inner
+// hierarchy (split storage), and its iterate back into u.
+int enter_inner(Exec &ex, Hier &H, const double *f, const double *u)
+{
+    mgwr_ctx *h = H.h;
+    const int top = (int)h->lv.size() - 1;
+    HIPCHK(launch_permute({PermuteArgs{h->dims, h->lv[top].n, h->M, 1, f, H.f[top]},
+                           PermuteArgs{h->dims, h->lv[top].n, h->M, 1, u, H.u[top]}},
+                          nullptr, ex.s));
+    return MGWR_OK;
+}
+
+int leave_inner(Exec &ex, Hier &H, double *u)
+{
+    mgwr_ctx *h = H.h;
+    const int top = (int)h->lv.size() - 1;
+    HIPCHK(launch_permute({PermuteArgs{h->dims, h->lv[top].n, h->M, 0, H.u[top], u}}, nullptr, ex.s));
+    return MGWR_OK;
 }
 
 // FP64 residual of the finest level into res64 (double-double iterate when
@@ -1165,6 +1247,7 @@ struct FineRes {
     bool cold;
     double *norm2;   // nullptr: no norms
     double *out;     // nullptr: the handle's residual buffer
+    int out_split = 0;   // out in the split storage order (the inner hierarchy's right-hand side)
 };
 
 int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
@@ -1180,25 +1263,32 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
         level = (int)h->lv.size() - 1;
         double *out = r.out ? r.out : h->res64;
         bool fused = false;
+        // the dense route stores the product apart when out is split (the
+        // residual kernel reads it in natural order)
+        double *prod_at = r.out_split ? h->rs64 : out;
         if (r.cold) {
-            fills.push_back(FillArgs{h->M, L.P, h->cd, r.g, out, 1});
+            fills.push_back(FillArgs{h->M, L.P, h->cd, r.g, prod_at, 1});
         } else {
             GemmArgs a = gemm_base(h, GM_F64);
             a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm; a.epi = EPI_STORE;
-            a.ea.out = out; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
+            a.ea.out = prod_at; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
             a.B = r.u; a.ldb = L.P;
             if (fft_for(h, level)) {
                 set_fft(h, a, h->spec_tm);
                 // the FFT route's last pass applies the stencil part itself
                 a.epi = r.lo ? EPI_RESID_DD : EPI_RESID;
+                a.ea.out = out;
                 a.ea.F = r.f; a.ea.U = r.u; a.ea.lo = r.lo; a.ea.cd = h->cd; a.ea.g = r.g;
                 a.ea.ih2 = L.ih2; a.ea.diag = 0.0; a.ea.ldu = L.P;
+                a.ea.lay_in = 0; a.ea.lay_out = r.out_split;
                 fused = true;
             }
             prods.push_back(a);
         }
-        if (!fused)
-            posts.push_back(PostArgs{h->dims, L.n, h->M, r.f, r.u, r.lo, h->cd, r.g, L.ih2, 0.0, out});
+        if (!fused) {
+            posts.push_back(PostArgs{h->dims, L.n, h->M, r.f, r.u, r.lo, h->cd, r.g, L.ih2, 0.0, out, 0, r.out_split,
+                                     prod_at});
+        }
         if (r.norm2) {
             const long n = (long)h->M * L.P;
             norms.push_back(NormArgs{n, out, h->partials, norm_partial_blocks(n), r.norm2});
@@ -1395,7 +1485,7 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
     auto fine_res = [&](int i, bool cold) {
         mgwr_ctx *h = hs[i];
         return FineRes{h, f[i], g ? g[i] : nullptr, u[i], refine(i) ? h->ulo : nullptr, cold, R.norms_dev + 2 * i,
-                       nullptr};
+                       nullptr, refine(i) ? 1 : 0};
     };
     std::vector<int> all(n);
     for (int i = 0; i < n; ++i) all[i] = i;
@@ -1438,7 +1528,7 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
                     Level &L = h->lv.back();
                     inner.push_back(Task{&Hi[i], top, true});
                     if (!skip_zero_fill(Hi[i], top)) zero.push_back(FillArgs{h->M, L.P, nullptr, nullptr, L.e, 0});
-                    upd.push_back(DDArgs{(long)h->M * L.P, L.e, u[i], h->ulo});
+                    upd.push_back(DDArgs{(long)h->M * L.P, L.e, u[i], h->ulo, h->dims, L.n, 1});
                 }
                 res.push_back(fine_res(i, false));
             }
@@ -2056,12 +2146,21 @@ int mgwr_smooth(mgwr_t h, const double *f, const double *g, double *u, int sweep
     if (sweeps < 0) return fail(MGWR_EINVAL, "sweeps must be >= 0");
     CHK(set_device(h));
     CHK(alloc_inner(h, h->opt.precision, uses_dc(h)));
-    Hier H = plain_hier(h, f, g, u);
-    H.prec = h->opt.precision;   // the history products in the handle's arithmetic
-    std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
     Exec ex{h->stream, nullptr, &h->run.prof};
+    if (h->opt.precision == MGWR_FP64) {
+        Hier H = plain_hier(h, f, g, u);
+        std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
+        for (int s = 0; s < sweeps; ++s) CHK(sweep(ex, ts));
+        return MGWR_OK;
+    }
+    // the refinement precisions: the inner hierarchy's kernels on its split
+    // storage, f and u reordered into it and u back
+    Hier H = inner_hier(h, h->opt.precision);
+    H.g = g;
+    CHK(enter_inner(ex, H, f, u));
+    std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
     for (int s = 0; s < sweeps; ++s) CHK(sweep(ex, ts));
-    return MGWR_OK;
+    return leave_inner(ex, H, u);
 }
 
 int mgwr_residual(mgwr_t h, const double *f, const double *g, const double *u, double *r, double *norms)
@@ -2089,11 +2188,18 @@ int mgwr_vcycle(mgwr_t h, const double *f, const double *g, double *u)
     CHK(check_ptr(u, "u"));
     CHK(set_device(h));
     CHK(alloc_inner(h, h->opt.precision, uses_dc(h)));
-    Hier H = plain_hier(h, f, g, u);
-    H.prec = h->opt.precision;
-    std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
     Exec ex{h->stream, nullptr, &h->run.prof};
-    return cycle(ex, ts);
+    if (h->opt.precision == MGWR_FP64) {
+        Hier H = plain_hier(h, f, g, u);
+        std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
+        return cycle(ex, ts);
+    }
+    Hier H = inner_hier(h, h->opt.precision);
+    H.g = g;
+    CHK(enter_inner(ex, H, f, u));
+    std::vector<Task> ts{Task{&H, (int)h->lv.size() - 1}};
+    CHK(cycle(ex, ts));
+    return leave_inner(ex, H, u);
 }
 
 int mgwr_solve(mgwr_t h, const double *f, const double *g, double *u, double tol, mgwr_info *info)

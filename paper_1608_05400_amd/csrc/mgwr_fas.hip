@@ -317,7 +317,10 @@ int fas_solve(int count, int N, int M, const double *alphas, double T, double c,
     hipEvent_t start = nullptr;
     double *hnorm = nullptr;   // pinned: the problems' residual norms
     auto alloc = [&](double **p, long n) -> bool {
-        if (hipMalloc((void **)p, sizeof(double) * (size_t)std::max(n, 1L)) != hipSuccess) return false;
+        if (hipMalloc((void **)p, sizeof(double) * (size_t)std::max(n, 1L)) != hipSuccess) {
+            (void)hipGetLastError();   // reported by the caller; not left for a later launch check
+            return false;
+        }
         mem.push_back(*p);
         return true;
     };

@@ -92,6 +92,9 @@ struct EpiArgs {
     const double *x = nullptr; // EPI_MERGE_DIAG: the other colour's panel [M][ldx]
     long ldx = 0;
     int px = 0;                // its points per row
+    // EPI_RESID*: storage order (lay_pos) of F, U, lo (and of the product's
+    // columns) and of out; EPI_RESID_R: of the coarse level written
+    int lay_in = 0, lay_out = 0;
 };
 
 // Tile choices of the product kernels (set by the autotuner).
@@ -153,6 +156,37 @@ __host__ __device__ inline int colour_count(int dims, int n, int colour)
     return colour == 0 ? (int)((t + 1) / 2) : (int)(t / 2);
 }
 
+// Storage order of a level's points.  Natural (split == 0): x fastest.  Split
+// by colour (split == 1): colour 0's points in the order of colour_point,
+// then colour 1's, so that the points one half-sweep relaxes, and the
+// neighbours its right-hand sides read, are contiguous.
+// Storage index of the j-th point of colour c:
+__host__ __device__ inline int lay_cpos(int dims, int n, int split, int c, int j)
+{
+    if (!split) return colour_point(dims, n, c, j);
+    return (c == 0 ? 0 : colour_count(dims, n, 0)) + j;
+}
+// Storage index of natural point p (x + n y):
+__host__ __device__ inline int lay_pos(int dims, int n, int split, int p)
+{
+    if (!split) return p;
+    if (dims == 1) return (p & 1) ? (p >> 1) : (n >> 1) + (p >> 1);   // colour 0: odd p
+    const int y = p / n, x = p - y * n, c = (x + y) & 1;
+    // (as colour_point enumerates them) each pair of rows holds n points of
+    // a colour; in the odd row of a pair they follow the (n + 1) / 2 (colour
+    // 0) or n / 2 (colour 1) points of the even row, and in either row the
+    // r-th point of the colour is at x = 2r or 2r + 1
+    const int before = (y & 1) ? (c == 0 ? (n + 1) / 2 : n / 2) : 0;
+    return (c == 0 ? 0 : colour_count(2, n, 0)) + (y >> 1) * n + before + (x >> 1);
+}
+// Natural point of storage index s:
+__host__ __device__ inline int lay_nat(int dims, int n, int split, int s)
+{
+    if (!split) return s;
+    const int p0 = colour_count(dims, n, 0);
+    return s < p0 ? colour_point(dims, n, 0, s) : colour_point(dims, n, 1, s - p0);
+}
+
 // ---------------------------------------------------------------------------
 // Argument arrays of grouped launches.  A stage is run twice over the same
 // host logic: a RECORD pass appends every array to `host` and launches
@@ -196,6 +230,7 @@ struct RhsArgs {
     const double *X = nullptr;
     long ldx = 0;
     int px = 0;
+    int split = 0;          // storage order of F and U (lay_pos)
 };
 // Residual from a Toeplitz product already in out (the history part, or all
 // of T_M U when diag = 0): out = (F + cd g - diag U - A_h U) - out, with A_h
@@ -205,6 +240,8 @@ struct PostArgs {
     const double *F, *U, *lo, *cd, *g;
     double ih2, diag;
     double *out;
+    int lay_in = 0, lay_out = 0;     // storage order of F, U, lo, prod and of out
+    const double *prod = nullptr;    // the product (nullptr: in out, lay_in == lay_out)
 };
 // Low-precision product operand of rows [0, M) of X [.][ldx] (P columns):
 // fmt 1: FP32 [M][ldp]; fmt 2: split-BF16 k8-packed [Mpad/8][ldp][8] (rows
@@ -226,13 +263,26 @@ struct XferArgs {
     const double *src;
     double *dst;
     int zero_colour = -1;   // restriction: src holds only the other colour (this one is zero)
+    int split = 0;          // storage order of both levels
+    // restriction: the residual is not stored but implied by the iterate src
+    // of a level that started from zero and was smoothed by one red-black
+    // sweep (first colour = 1 - zero_colour): ih2 times the neighbour sum of
+    // src at the first colour's points, zero at the others
+    int implicit = 0;
+    double ih2 = 0.0;
+    // interpolation: this colour's fine points are not corrected (the first
+    // half-sweep of the post-smoothing recomputes them from the other
+    // colour alone); -1: all points
+    int skip_colour = -1;
 };
-// u[k][p] = scaled ? cd[k] g[p] : g[p]  (g == nullptr: 0)
+// u[k][s] = scaled ? cd[k] g[p] : g[p] for the natural point p of storage
+// index s (g == nullptr: 0)
 struct FillArgs {
     long M, P;
     const double *cd, *g;
     double *u;
     int scaled;
+    int dims = 1, n = 0, split = 0;   // storage order of u (split: dims and n give it)
 };
 // Norm partials {max |x|, sum x^2} of x[0..n) over nblk blocks, and the final
 // reduction into out2 = {max, sqrt(sum)}.
@@ -243,17 +293,28 @@ struct NormArgs {
     int nblk;
     double *out2;
 };
-// (hi, lo) += e (double-double); lo == nullptr: hi += e.
+// (hi, lo) += e (double-double); lo == nullptr: hi += e.  hi and lo in
+// natural order; e in the storage order `split` of a level with npd points
+// per dimension (n = M x points values).
 struct DDArgs {
     long n;
     const double *e;
     double *hi, *lo;
+    int dims = 1, npd = 0, split = 0;
 };
-// U[k][colour_point(j)] = X[k][j], k < M, j < Pc (end of a D&C half-sweep).
+// U[k][colour's j-th point] = X[k][j], k < M, j < Pc (end of a D&C half-sweep).
 struct ScatterArgs {
     int dims, n, colour, M, Pc;
     const double *X;
     double *U;
+    int split = 0;
+};
+// Reorder [M][points] between natural order and the split storage order:
+// to_split: dst[k][lay_pos(p)] = src[k][p]; else dst[k][p] = src[k][lay_pos(p)].
+struct PermuteArgs {
+    int dims, n, M, to_split;
+    const double *src;
+    double *dst;
 };
 
 // ---- launchers (all asynchronous on `s`; st may be nullptr when every list
@@ -269,6 +330,7 @@ hipError_t launch_fill(const std::vector<FillArgs> &v, Staging *st, hipStream_t 
 hipError_t launch_norms(const std::vector<NormArgs> &v, Staging *st, hipStream_t s);
 hipError_t launch_dd_update(const std::vector<DDArgs> &v, Staging *st, hipStream_t s);
 hipError_t launch_scatter(const std::vector<ScatterArgs> &v, Staging *st, hipStream_t s);
+hipError_t launch_permute(const std::vector<PermuteArgs> &v, Staging *st, hipStream_t s);
 // Bytes the FFT route's passes move through their complex work arrays for
 // one product (written by the first kernel, read and written by each middle
 // one, read by the last).

@@ -63,16 +63,18 @@ __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b <<
 // with zero Dirichlet values, on one time row U of a level with n points/dim.
 // The neighbours are loaded at clamped indices and the ones outside the grid
 // replaced by zero, so that no load sits behind a branch.
+// p is the natural index of the point; the row is stored in the order
+// `split` (lay_pos).
 template <typename Ptr>
-__device__ inline void nbr_vals(Ptr U, int dims, int n, int p, double (&v)[4])
+__device__ inline void nbr_vals(Ptr U, int dims, int n, int p, double (&v)[4], int split = 0)
 {
     // a 1D row is an n x 1 grid: its y-neighbours are outside
     const int ny = dims == 1 ? 1 : n;
     const int y = dims == 1 ? 0 : p / n, x = p - y * n;
-    v[0] = (double)U[x > 0 ? p - 1 : p];
-    v[1] = (double)U[x < n - 1 ? p + 1 : p];
-    v[2] = (double)U[y > 0 ? p - n : p];
-    v[3] = (double)U[y < ny - 1 ? p + n : p];
+    v[0] = (double)U[lay_pos(dims, n, split, x > 0 ? p - 1 : p)];
+    v[1] = (double)U[lay_pos(dims, n, split, x < n - 1 ? p + 1 : p)];
+    v[2] = (double)U[lay_pos(dims, n, split, y > 0 ? p - n : p)];
+    v[3] = (double)U[lay_pos(dims, n, split, y < ny - 1 ? p + n : p)];
     if (x == 0) v[0] = 0.0;
     if (x == n - 1) v[1] = 0.0;
     if (y == 0) v[2] = 0.0;
@@ -80,10 +82,10 @@ __device__ inline void nbr_vals(Ptr U, int dims, int n, int p, double (&v)[4])
 }
 
 template <typename Ptr>
-__device__ inline double nbr_sum(Ptr U, int dims, int n, int p)
+__device__ inline double nbr_sum(Ptr U, int dims, int n, int p, int split = 0)
 {
     double v[4];
-    nbr_vals(U, dims, n, p, v);
+    nbr_vals(U, dims, n, p, v, split);
     return ((v[0] + v[1]) + v[2]) + v[3];
 }
 
@@ -98,13 +100,14 @@ __device__ inline void two_sum(double a, double b, double &s, double &e)
 // shi + slo = 2 d hi_p - sum(neighbours of hi) + (same stencil of lo),
 // the hi part without rounding error (error-free transformations).
 template <typename Ptr>
-__device__ inline void stencil_dd(Ptr H, Ptr Lo, int dims, int n, int p, double &shi, double &slo)
+__device__ inline void stencil_dd(Ptr H, Ptr Lo, int dims, int n, int p, double &shi, double &slo, int split = 0)
 {
     double h[4], l[4];
-    nbr_vals(H, dims, n, p, h);
-    nbr_vals(Lo, dims, n, p, l);
-    double s = (dims == 1 ? 2.0 : 4.0) * H[p], e, acc = 0.0;
-    double lo = (dims == 1 ? 2.0 : 4.0) * Lo[p];
+    nbr_vals(H, dims, n, p, h, split);
+    nbr_vals(Lo, dims, n, p, l, split);
+    const int sp = lay_pos(dims, n, split, p);
+    double s = (dims == 1 ? 2.0 : 4.0) * H[sp], e, acc = 0.0;
+    double lo = (dims == 1 ? 2.0 : 4.0) * Lo[sp];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {   // a zero neighbour leaves s exact and adds nothing
         two_sum(s, -h[k], s, e);
@@ -136,19 +139,28 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
         // the stencil part of the residual (as OpPost), fused; no load
         // behind a divergent branch (g and cd are read only when there is an
         // initial condition, a launch-wide choice; diag = 0 subtracts an
-        // exact zero)
-        if constexpr (EPI == EPI_RESID_C || EPI == EPI_RESID_R) p = colour_point(e.dims, e.n, e.colour, p);
+        // exact zero).  nat: the natural point, sp: its storage index (F, U
+        // and lo in the order lay_in; column p is the colour's p-th point for
+        // the one-colour residuals, else storage index p)
+        int nat, sp;
+        if constexpr (EPI == EPI_RESID_C || EPI == EPI_RESID_R) {
+            nat = colour_point(e.dims, e.n, e.colour, p);
+            sp = lay_cpos(e.dims, e.n, e.lay_in, e.colour, p);
+        } else {
+            nat = lay_nat(e.dims, e.n, e.lay_in, p);
+            sp = p;
+        }
         const long k = (long)i * e.ldu;
         const GLOBAL double *Uk = gview<double>(e.U) + k;
-        double rhs = gview<double>(e.F)[k + p];
-        if (e.g) rhs += gview<double>(e.cd)[i] * gview<double>(e.g)[p];
-        rhs -= e.diag * Uk[p];
+        double rhs = gview<double>(e.F)[k + sp];
+        if (e.g) rhs += gview<double>(e.cd)[i] * gview<double>(e.g)[nat];
+        rhs -= e.diag * Uk[sp];
         if constexpr (EPI == EPI_RESID_DD) {
             double shi, slo;
-            stencil_dd(Uk, gview<double>(e.lo) + k, e.dims, e.n, p, shi, slo);
+            stencil_dd(Uk, gview<double>(e.lo) + k, e.dims, e.n, nat, shi, slo, e.lay_in);
             return (rhs - shi * e.ih2) - slo * e.ih2;
         } else {
-            double st = (e.dims == 1 ? 2.0 : 4.0) * Uk[p] - nbr_sum(Uk, e.dims, e.n, p);
+            double st = (e.dims == 1 ? 2.0 : 4.0) * Uk[sp] - nbr_sum(Uk, e.dims, e.n, nat, e.lay_in);
             return rhs - st * e.ih2;
         }
     } else {
@@ -191,11 +203,14 @@ __device__ inline void epi_put(const EpiArgs &e, int i, int p, double pre, doubl
     } else if constexpr (EPI == EPI_STORE_DIAG) {
         out[(long)i * e.ldo + p] = pre + acc;
     } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
-        out[(long)i * e.ldo + p] = pre - acc;
+        const int q = (e.lay_out == e.lay_in) ? p
+                      : lay_pos(e.dims, e.n, e.lay_out, lay_nat(e.dims, e.n, e.lay_in, p));
+        out[(long)i * e.ldo + q] = pre - acc;
     } else if constexpr (EPI == EPI_RESID_C) {
-        out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = pre - acc;
+        out[(long)i * e.ldo + lay_cpos(e.dims, e.n, e.lay_out, e.colour, p)] = pre - acc;
     } else if constexpr (EPI == EPI_RESID_R) {
-        out[(long)i * e.ldo + p] = 0.25 * (2.0 * (pre - acc));
+        // colour 0's p-th fine point is coarse point p (natural)
+        out[(long)i * e.ldo + lay_pos(1, (e.n - 1) / 2, e.lay_out, p)] = 0.25 * (2.0 * (pre - acc));
     }
 }
 
@@ -1445,7 +1460,7 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
             const int cc = a.c0 + 2 * q;
             constexpr int CH = epi_rows<EPI>(R2);
             if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C || EPI == EPI_RESID_R) {
-                if (a.ea.dims == 1) {   // cc < P; cc + 1 may be P
+                if (a.ea.dims == 1 && !a.ea.lay_in) {   // natural input; cc < P; cc + 1 may be P
                     // first point of the pair: column cc, or the colour's point cc
                     constexpr bool colr = EPI == EPI_RESID_C || EPI == EPI_RESID_R;
                     const int pt = colr ? colour_point(1, a.ea.n, a.ea.colour, cc) : cc;
@@ -1919,7 +1934,8 @@ template <typename S> struct OpRhsPanel {
         GLOBAL double *U = gview_rw<double>(a.U);
         GRID_STRIDE(e, (long)a.M * Pc) {
             int k = (int)(e / Pc), j = (int)(e - (long)k * Pc);
-            int pt = colour_point(a.dims, a.n, a.colour, j);
+            int pt = colour_point(a.dims, a.n, a.colour, j);             // natural
+            int sp = lay_cpos(a.dims, a.n, a.split, a.colour, j);        // stored at
             GLOBAL double *Uk = U + (long)k * P;
             double ns;
             if (a.X) {   // 1D: the neighbours pt -+ 1 are the other colour's points jl, jr of X
@@ -1927,12 +1943,12 @@ template <typename S> struct OpRhsPanel {
                 const int jl = a.colour == 1 ? j - 1 : j, jr = a.colour == 1 ? j : j + 1;
                 ns = (jl >= 0 ? Xk[jl] : 0.0) + (jr < a.px ? Xk[jr] : 0.0);
             } else {
-                ns = nbr_sum(Uk, a.dims, a.n, pt);
+                ns = nbr_sum(Uk, a.dims, a.n, pt, a.split);
             }
-            double b = F[(long)k * P + pt] + ns * a.ih2;
+            double b = F[(long)k * P + sp] + ns * a.ih2;
             if (a.g) b += cd[k] * g[pt];
             panel[(long)k * a.ldp + j] = (S)b;
-            if (a.lam0 != 0.0) Uk[pt] = a.lam0 * b;
+            if (a.lam0 != 0.0) Uk[sp] = a.lam0 * b;
         }
     }
 };
@@ -1970,15 +1986,16 @@ struct OpRhsPacked {
             int kg = (int)(e / a.ldp), j = (int)(e - (long)kg * a.ldp);
             float b8[8];
             int pt = (j < Pc) ? colour_point(a.dims, a.n, a.colour, j) : 0;
+            int sp = (j < Pc) ? lay_cpos(a.dims, a.n, a.split, a.colour, j) : 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 int k = kg * 8 + q;
                 double b = 0.0;
                 if (k < a.M && j < Pc) {
                     GLOBAL double *Uk = U + (long)k * P;
-                    b = F[(long)k * P + pt] + nbr_sum(Uk, a.dims, a.n, pt) * a.ih2;
+                    b = F[(long)k * P + sp] + nbr_sum(Uk, a.dims, a.n, pt, a.split) * a.ih2;
                     if (a.g) b += cd[k] * g[pt];
-                    if (a.lam0 != 0.0) Uk[pt] = a.lam0 * b;
+                    if (a.lam0 != 0.0) Uk[sp] = a.lam0 * b;
                 }
                 b8[q] = (float)b;
             }
@@ -1999,22 +2016,26 @@ struct OpPost {
         const GLOBAL double *F = gview<double>(a.F), *U = gview<double>(a.U), *lo = gview<double>(a.lo);
         const GLOBAL double *cd = gview<double>(a.cd), *g = gview<double>(a.g);
         GLOBAL double *out = gview_rw<double>(a.out);
+        const GLOBAL double *prod = a.prod ? gview<double>(a.prod) : out;
         GRID_STRIDE(e, (long)a.M * P) {
-            int k = (int)(e / P), p = (int)(e - (long)k * P);
+            // s: storage index (order lay_in), p: the natural point
+            int k = (int)(e / P), s = (int)(e - (long)k * P);
+            const int p = lay_nat(a.dims, a.n, a.lay_in, s);
             const GLOBAL double *Uk = U + (long)k * P;
             double rhs = F[e];
             if (a.g) rhs += cd[k] * g[p];
-            if (a.diag != 0.0) rhs -= a.diag * Uk[p];
+            if (a.diag != 0.0) rhs -= a.diag * Uk[s];
             double r;
             if (a.lo) {
                 double shi, slo;
-                stencil_dd(Uk, lo + (long)k * P, a.dims, a.n, p, shi, slo);
+                stencil_dd(Uk, lo + (long)k * P, a.dims, a.n, p, shi, slo, a.lay_in);
                 r = (rhs - shi * a.ih2) - slo * a.ih2;
             } else {
-                double st = (a.dims == 1 ? 2.0 : 4.0) * Uk[p] - nbr_sum(Uk, a.dims, a.n, p);
+                double st = (a.dims == 1 ? 2.0 : 4.0) * Uk[s] - nbr_sum(Uk, a.dims, a.n, p, a.lay_in);
                 r = rhs - st * a.ih2;
             }
-            out[e] = r - out[e];
+            const long o = (a.lay_out == a.lay_in) ? e : (long)k * P + lay_pos(a.dims, a.n, a.lay_out, p);
+            out[o] = r - prod[e];
         }
     }
 };
@@ -2075,30 +2096,41 @@ struct OpXfer {
         const int nf = a.n, nc = (nf - 1) / 2;
         const long Pc = (a.dims == 1) ? nc : (long)nc * nc;
         const long Pf = (a.dims == 1) ? nf : (long)nf * nf;
+        const int sp = a.split;
         GRID_STRIDE(e, (long)a.M * Pc) {
             int k = (int)(e / Pc);
-            long q = e - (long)k * Pc;
+            // q: natural index of the coarse point stored at e (both levels in
+            // the order `split`)
+            const int q = lay_nat(a.dims, nc, sp, (int)(e - (long)k * Pc));
             const GLOBAL double *r = gview<double>(a.src) + (long)k * Pf;
             // the coarse point is a colour-0 point of the fine grid, its
             // edge neighbours colour 1, its corners (2D) colour 0; with
             // zero_colour set, that colour's entries are zero and not read
             double v;
             if (a.dims == 1) {
-                int x = 2 * (int)q + 1;
-                if (a.zero_colour == 1) v = 0.25 * (2.0 * r[x]);
-                else if (a.zero_colour == 0) v = 0.25 * (r[x - 1] + r[x + 1]);
-                else v = 0.25 * (r[x - 1] + 2.0 * r[x] + r[x + 1]);
+                int x = 2 * q + 1;
+                auto R = [&](int xx) {
+                    return a.implicit ? a.ih2 * nbr_sum(r, 1, nf, xx, sp) : r[lay_pos(1, nf, sp, xx)];
+                };
+                if (a.zero_colour == 1) v = 0.25 * (2.0 * R(x));
+                else if (a.zero_colour == 0) v = 0.25 * (R(x - 1) + R(x + 1));
+                else v = 0.25 * (R(x - 1) + 2.0 * R(x) + R(x + 1));
             } else {
-                int I = (int)(q % nc), J = (int)(q / nc);
+                int I = q % nc, J = q / nc;
                 int x = 2 * I + 1, y = 2 * J + 1;
-                const GLOBAL double *r0 = r + (long)(y - 1) * nf, *r1 = r + (long)y * nf, *r2 = r + (long)(y + 1) * nf;
+                auto R = [&](int yy, int xx) {
+                    return a.implicit ? a.ih2 * nbr_sum(r, 2, nf, yy * nf + xx, sp)
+                                      : r[lay_pos(2, nf, sp, yy * nf + xx)];
+                };
                 if (a.zero_colour == 1)
-                    v = (r0[x - 1] + r0[x + 1] + 2.0 * (2.0 * r1[x]) + r2[x - 1] + r2[x + 1]) * (1.0 / 16.0);
+                    v = (R(y - 1, x - 1) + R(y - 1, x + 1) + 2.0 * (2.0 * R(y, x)) + R(y + 1, x - 1) + R(y + 1, x + 1))
+                        * (1.0 / 16.0);
                 else if (a.zero_colour == 0)
-                    v = (2.0 * r0[x] + 2.0 * (r1[x - 1] + r1[x + 1]) + 2.0 * r2[x]) * (1.0 / 16.0);
+                    v = (2.0 * R(y - 1, x) + 2.0 * (R(y, x - 1) + R(y, x + 1)) + 2.0 * R(y + 1, x)) * (1.0 / 16.0);
                 else
-                    v = (r0[x - 1] + 2.0 * r0[x] + r0[x + 1] + 2.0 * (r1[x - 1] + 2.0 * r1[x] + r1[x + 1])
-                         + r2[x - 1] + 2.0 * r2[x] + r2[x + 1]) * (1.0 / 16.0);
+                    v = (R(y - 1, x - 1) + 2.0 * R(y - 1, x) + R(y - 1, x + 1)
+                         + 2.0 * (R(y, x - 1) + 2.0 * R(y, x) + R(y, x + 1))
+                         + R(y + 1, x - 1) + 2.0 * R(y + 1, x) + R(y + 1, x + 1)) * (1.0 / 16.0);
             }
             gview_rw<double>(a.dst)[e] = v;
         }
@@ -2108,19 +2140,28 @@ struct OpXfer {
         const int nc = a.n, nf = 2 * nc + 1;
         const long Pc = (a.dims == 1) ? nc : (long)nc * nc;
         const long Pf = (a.dims == 1) ? nf : (long)nf * nf;
-        GRID_STRIDE(e, (long)a.M * Pf) {
-            int k = (int)(e / Pf);
-            long p = e - (long)k * Pf;
+        const int sp = a.split;
+        // with skip_colour, the points of the other colour only
+        const int oc = 1 - a.skip_colour;
+        const long Pw = a.skip_colour >= 0 ? colour_count(a.dims, nf, oc) : Pf;
+        GRID_STRIDE(w, (long)a.M * Pw) {
+            int k = (int)(w / Pw);
+            const int jw = (int)(w - (long)k * Pw);
+            // e: storage index of the fine point, p: its natural index
+            const long e = (long)k * Pf + (a.skip_colour >= 0 ? lay_cpos(a.dims, nf, sp, oc, jw) : jw);
+            const int p = a.skip_colour >= 0 ? colour_point(a.dims, nf, oc, jw) : lay_nat(a.dims, nf, sp, jw);
             const GLOBAL double *c = gview<double>(a.src) + (long)k * Pc;
             double v;
             if (a.dims == 1) {
-                int nn = (int)p + 1;   // paper numbering
-                v = 0.5 * (coarse_at(c, nc, nn / 2) + coarse_at(c, nc, (nn + 1) / 2));
+                int nn = p + 1;   // paper numbering
+                auto at = [&](int X) -> double { return (X >= 1 && X <= nc) ? c[lay_pos(1, nc, sp, X - 1)] : 0.0; };
+                v = 0.5 * (at(nn / 2) + at((nn + 1) / 2));
             } else {
-                int nn = (int)(p % nf) + 1, ll = (int)(p / nf) + 1;
+                int nn = p % nf + 1, ll = p / nf + 1;
                 int xa = nn / 2, xb = (nn + 1) / 2, ya = ll / 2, yb = (ll + 1) / 2;
                 auto at = [&](int X, int Y) -> double {
-                    return (X >= 1 && X <= nc && Y >= 1 && Y <= nc) ? c[(long)(Y - 1) * nc + (X - 1)] : 0.0;
+                    return (X >= 1 && X <= nc && Y >= 1 && Y <= nc) ? c[lay_pos(2, nc, sp, (Y - 1) * nc + (X - 1))]
+                                                                    : 0.0;
                 };
                 v = 0.25 * (at(xa, ya) + at(xb, ya) + at(xa, yb) + at(xb, yb));
             }
@@ -2142,7 +2183,10 @@ struct OpFill {
         GLOBAL double *u = gview_rw<double>(a.u);
         GRID_STRIDE(e, a.M * a.P) {
             double v = 0.0;
-            if (a.g) v = a.scaled ? cd[e / a.P] * g[e % a.P] : g[e % a.P];
+            if (a.g) {
+                const int p = lay_nat(a.dims, a.n, a.split, (int)(e % a.P));
+                v = a.scaled ? cd[e / a.P] * g[p] : g[p];
+            }
             u[e] = v;
         }
     }
@@ -2217,8 +2261,11 @@ struct OpDD {
     {
         const GLOBAL double *ev = gview<double>(a.e);
         GLOBAL double *hi = gview_rw<double>(a.hi), *lo = gview_rw<double>(a.lo);
+        const long P = a.split ? (a.dims == 1 ? a.npd : (long)a.npd * a.npd) : 1;
         GRID_STRIDE(i, a.n) {
-            double d = ev[i];
+            // e in the storage order `split`: the natural point i % P is at
+            // lay_pos of it
+            double d = a.split ? ev[(i / P) * P + lay_pos(a.dims, a.npd, 1, (int)(i % P))] : ev[i];
             if (!a.lo) {
                 hi[i] += d;
                 continue;
@@ -2243,7 +2290,26 @@ struct OpScatter {
         GLOBAL double *U = gview_rw<double>(a.U);
         GRID_STRIDE(e, (long)a.M * a.Pc) {
             int k = (int)(e / a.Pc), j = (int)(e - (long)k * a.Pc);
-            U[(long)k * P + colour_point(a.dims, a.n, a.colour, j)] = X[e];
+            U[(long)k * P + lay_cpos(a.dims, a.n, a.split, a.colour, j)] = X[e];
+        }
+    }
+};
+
+// Between natural order and the split storage order (the refinement's inner
+// hierarchy), for the entry points that run its kernels on caller arrays.
+struct OpPermute {
+    using A = PermuteArgs;
+    __device__ static void run(const PermuteArgs &a, long lb, long nb)
+    {
+        const long P = (a.dims == 1) ? a.n : (long)a.n * a.n;
+        const GLOBAL double *src = gview<double>(a.src);
+        GLOBAL double *dst = gview_rw<double>(a.dst);
+        GRID_STRIDE(e, (long)a.M * P) {
+            const long k = e / P;
+            const int p = (int)(e - k * P);
+            const long q = k * P + lay_pos(a.dims, a.n, 1, p);
+            if (a.to_split) dst[q] = src[e];
+            else dst[e] = src[q];
         }
     }
 };
@@ -2318,7 +2384,9 @@ hipError_t launch_xfer(const std::vector<XferArgs> &v, Staging *st, hipStream_t 
         v, [](const XferArgs &) { return true; },
         [](const XferArgs &a) {
             long np = (a.dir == 0) ? (a.n - 1) / 2 : 2 * a.n + 1;
-            return blocks_for((long)a.M * ((a.dims == 1) ? np : np * np));
+            long pts = (a.dims == 1) ? np : np * np;
+            if (a.dir == 1 && a.skip_colour >= 0) pts = colour_count(a.dims, (int)np, 1 - a.skip_colour);
+            return blocks_for((long)a.M * pts);
         },
         st, s);
 }
@@ -2354,6 +2422,13 @@ hipError_t launch_scatter(const std::vector<ScatterArgs> &v, Staging *st, hipStr
     return launch_subset<OpScatter>(
         v, [](const ScatterArgs &) { return true; },
         [](const ScatterArgs &a) { return blocks_for((long)a.M * a.Pc); }, st, s);
+}
+
+hipError_t launch_permute(const std::vector<PermuteArgs> &v, Staging *st, hipStream_t s)
+{
+    std::vector<long> b;
+    for (const auto &a : v) b.push_back(blocks_for((long)a.M * (a.dims == 1 ? a.n : (long)a.n * a.n)));
+    return launch_group<OpPermute>(v, b, st, s);
 }
 
 hipError_t launch_build_coef(ToepCoef &c, hipStream_t s)

@@ -36,28 +36,42 @@ def dev(a):
 
 
 @pytest.mark.parametrize("fft", [0, 2])
-@pytest.mark.parametrize("row", load_golden("table3_v01_1d.txt"))
+@pytest.mark.parametrize("row", load_golden("table3_v01_1d.txt") + load_golden("table3_v01_1d_large.txt"))
 def test_table3_v01_iterations_1d(B, row, fft):
     """First test problem (x in [0, pi], f = 0, g = sin x), V(0,1), the 2-norm,
-    the odd (fine-only) points relaxed first as in the oracle's reading."""
+    the odd (fine-only) points relaxed first as in the oracle's reading.
+
+    From S = 1024 on the rounding floor of an FP64 residual (about
+    4 u |u| / h^2 per point, 3e-7 in the 2-norm at h = pi / 2048, against a
+    target of 1.4e-7) meets the 1e-10 reduction, so those grids run the same
+    cycle on the error equation with the iterate carried in double-double
+    (precision fp64r: in exact arithmetic the same iterates).  A printed
+    count that its own printed mean factor cannot produce (factor - 0.005,
+    the rounding of the print, to the power of the count above 1e-10: the
+    rows delta = 1.0, S >= 1024, 6 iterations at 0.05) is read as the count
+    that factor needs."""
     alpha, S, its_paper, fac_paper = row
     S = int(S)
     w = W.paper_test1(N=S - 1, M=S, alpha=alpha)
     g = W.paper_test1_g(w)
     f = np.zeros((S, S - 1))
+    prec = "fp64" if S <= 512 else "fp64r"
     with B.Solver(S - 1, S, alpha, dims=1, nu1=0, nu2=1, first_colour=1, norm="l2", L=math.pi,
-                  fft=fft) as s:
+                  fft=fft, precision=prec) as s:
         U = torch.zeros(s.grid_shape, dtype=torch.float64, device="cuda")
         info = s.solve(dev(f), U, g=dev(g), tol=1e-10)
-    print(f"alpha {alpha} S {S} fft {fft}: {info['iters']} iterations, factor {info['mean_factor']:.3f}"
-          f" (paper {int(its_paper)}, {fac_paper})")
+    its = its_paper
+    if (fac_paper - 0.005) ** its_paper > 1e-10:
+        its = math.ceil(math.log(1e-10) / math.log(fac_paper))
+    print(f"alpha {alpha} S {S} fft {fft} {prec}: {info['iters']} iterations, factor {info['mean_factor']:.3f}"
+          f" (paper {int(its_paper)}, {fac_paper}; expected {its})")
     assert info["rc"] == 0, info
-    assert abs(info["iters"] - its_paper) <= 1
+    assert abs(info["iters"] - its) <= 1
     assert info["mean_factor"] <= fac_paper + 0.025
 
 
 @pytest.mark.parametrize("fft", [0, 2])
-@pytest.mark.parametrize("row", load_golden("table4_v11_2d.txt"))
+@pytest.mark.parametrize("row", load_golden("table4_v11_2d.txt") + load_golden("table4_v11_2d_large.txt"))
 def test_table4_v11_iterations_2d(B, row, fft):
     """Second test problem on (0, 2)^2 with its printed forcing, V(1,1), the
     max norm."""
@@ -75,11 +89,13 @@ def test_table4_v11_iterations_2d(B, row, fft):
 
 
 @pytest.mark.parametrize("fft", [0, 2])
-@pytest.mark.parametrize("row", load_golden("table2_wcycle_1d.txt"))
+@pytest.mark.parametrize("row", load_golden("table2_wcycle_1d_all.txt"))
 def test_table2_wcycle_asymptotic_factor(B, row, fft):
     """W-cycle with one pre-smoothing step, random initial guess, zero
     right-hand side; lambda = tau^alpha Gamma(2 - alpha) / h^2 set through the
-    final time T; the factor of the last five of twelve cycles (2-norm)."""
+    final time T; the factor of the last five of twelve cycles (2-norm),
+    within 0.012, or 25 % of the printed factor plus 0.001 where that is
+    tighter (the small factors of large lambda)."""
     l2lam, M, _pred, measured = row
     M = int(M)
     alpha, N = 0.4, 63
@@ -95,7 +111,7 @@ def test_table2_wcycle_asymptotic_factor(B, row, fft):
             norms.append(l2)
     fac = (norms[-1] / norms[-6]) ** (1 / 5)
     print(f"log2 lambda {l2lam} M {M} fft {fft}: factor {fac:.4f} (paper {measured})")
-    assert abs(fac - measured) <= 0.012, fac
+    assert abs(fac - measured) <= min(0.012, 0.25 * measured + 0.001), fac
 
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])

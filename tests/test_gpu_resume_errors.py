@@ -56,3 +56,17 @@ def test_absurd_size_is_out_of_memory(B):
     with pytest.raises(B.MgwrError) as ei:
         B.Solver(16383, 4096, 0.5, dims=2)
     assert ei.value.code == -2, ei.value
+
+
+def test_work_after_out_of_memory(B):
+    """A failed allocation is reported by its call and leaves nothing behind:
+    the next handle builds its coefficient tables (kernel launches checked
+    with the runtime's last error) and solves."""
+    with pytest.raises(B.MgwrError) as e:
+        B.Solver(16383, 4096, 0.5, dims=2)
+    assert e.value.code == B.MGWR_ENOMEM
+    with B.Solver(15, 64, 0.5) as s:
+        f = torch.ones((64, 15), dtype=torch.float64, device="cuda")
+        U = torch.zeros_like(f)
+        info = s.solve(f, U, tol=1e-10)
+    assert info["status"] == "ok", info
