@@ -95,6 +95,12 @@ struct EpiArgs {
     // EPI_RESID*: storage order (lay_pos) of F, U, lo (and of the product's
     // columns) and of out; EPI_RESID_R: of the coarse level written
     int lay_in = 0, lay_out = 0;
+    // Smoother products of a split level on the FFT route: the operand (and
+    // EPI_STORE_DIAG's right-hand side) is not stored but computed where it
+    // is read, b = F + ih2 (neighbour sum) + cd g, from F (its first point
+    // the colour's first, rows ldu apart) and the level's iterate U (the
+    // other colour's values; rows ldu apart), g in natural order
+    int rhs = 0;
 };
 
 // Tile choices of the product kernels (set by the autotuner).

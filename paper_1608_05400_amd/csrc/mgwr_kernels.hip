@@ -118,6 +118,35 @@ __device__ inline void stencil_dd(Ptr H, Ptr Lo, int dims, int n, int p, double 
     slo = acc + lo;
 }
 
+// Right-hand side of the smoother (Section 3, eq. red-black; Section 6, eq.
+// red-black_2d) at time row i and the j-th point of a colour, on a level
+// stored split by colour: f + (neighbour sum) / h^2 + c d_i g (EpiArgs::rhs).
+// In 1D the neighbours of colour 0's point j are the other colour's points
+// j and j + 1, those of colour 1's point j the other's j - 1 and j (each
+// inside the grid); loads at clamped indices.
+__device__ inline double rhs_val(const EpiArgs &e, int i, int j)
+{
+    const long k = (long)i * e.ldu;
+    const GLOBAL double *Uk = gview<double>(e.U) + k;
+    double b = gview<double>(e.F)[k + j];
+    double ns;
+    if (e.dims == 1) {
+        const int o = e.colour == 0 ? e.n / 2 : 0;            // the other colour's first point
+        const int po = e.colour == 0 ? (e.n + 1) / 2 : e.n / 2;   // and its count (0 when n = 1)
+        const int jl = e.colour == 0 ? j : j - 1, jr = e.colour == 0 ? j + 1 : j;
+        // loads clamped into the level's row (the other colour may be empty)
+        double vl = Uk[min(max(o + jl, 0), e.n - 1)], vr = Uk[min(max(o + jr, 0), e.n - 1)];
+        if (jl < 0 || jl >= po) vl = 0.0;
+        if (jr < 0 || jr >= po) vr = 0.0;
+        ns = vl + vr;
+    } else {
+        ns = nbr_sum(Uk, 2, e.n, colour_point(2, e.n, e.colour, j), 1);
+    }
+    b += ns * e.ih2;
+    if (e.g) b += gview<double>(e.cd)[i] * gview<double>(e.g)[colour_point(e.dims, e.n, e.colour, j)];
+    return b;
+}
+
 // ---------------------------------------------------------------------------
 // Epilogue of the Toeplitz products, element (i, p) with product value acc,
 // in two parts so that a thread can issue the loads of all its elements
@@ -1200,7 +1229,9 @@ struct FftPass {
 };
 // The work arrays are read once and written once per pass: their loads and
 // stores are nontemporal (measured a few per cent faster).
-enum FftSrc { FS_REAL = 0, FS_CPLX = 1, FS_SPEC = 2 };
+// FS_RHS: the real input is the smoother's right-hand side computed where it
+// is read (rhs_val; FP64 route of a split level).
+enum FftSrc { FS_REAL = 0, FS_CPLX = 1, FS_SPEC = 2, FS_RHS = 3 };
 
 // Column of B read for product column j (the colour's points when b_colour >= 0).
 __device__ inline int fft_bcol(const FftPass &a, int j)
@@ -1306,12 +1337,17 @@ __global__ __launch_bounds__(256) void k_fft_pass(Grp<FftPass> grp)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int tau = j + r * nj;
-        if constexpr (SRC == FS_REAL) {
+        if constexpr (SRC == FS_REAL || SRC == FS_RHS) {
             T re = 0, im = 0;
             if (tau < a.K) {
-                const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb;
-                if (a.c0 + 2 * q < a.P) re = (T)row[fft_bcol(a, a.c0 + 2 * q)];
-                if (a.c0 + 2 * q + 1 < a.P) im = (T)row[fft_bcol(a, a.c0 + 2 * q + 1)];
+                if constexpr (SRC == FS_RHS) {
+                    if (a.c0 + 2 * q < a.P) re = (T)rhs_val(a.ea, tau, a.c0 + 2 * q);
+                    if (a.c0 + 2 * q + 1 < a.P) im = (T)rhs_val(a.ea, tau, a.c0 + 2 * q + 1);
+                } else {
+                    const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb;
+                    if (a.c0 + 2 * q < a.P) re = (T)row[fft_bcol(a, a.c0 + 2 * q)];
+                    if (a.c0 + 2 * q + 1 < a.P) im = (T)row[fft_bcol(a, a.c0 + 2 * q + 1)];
+                }
             }
             v[r] = C{re, im};
         } else {
@@ -1407,12 +1443,17 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
         const int r = R2 * r1 + r2, tau = j + r * nj;
         C x = C{0, 0};
         if (busy && q < a.Q) {
-            if constexpr (SRC == FS_REAL) {
+            if constexpr (SRC == FS_REAL || SRC == FS_RHS) {
                 T re = 0, im = 0;
                 if (tau < a.K) {
-                    const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb;
-                    if (a.c0 + 2 * q < a.P) re = (T)row[fft_bcol(a, a.c0 + 2 * q)];
-                    if (a.c0 + 2 * q + 1 < a.P) im = (T)row[fft_bcol(a, a.c0 + 2 * q + 1)];
+                    if constexpr (SRC == FS_RHS) {
+                        if (a.c0 + 2 * q < a.P) re = (T)rhs_val(a.ea, tau, a.c0 + 2 * q);
+                        if (a.c0 + 2 * q + 1 < a.P) im = (T)rhs_val(a.ea, tau, a.c0 + 2 * q + 1);
+                    } else {
+                        const GLOBAL TIN *row = gview<TIN>(a.B) + (long)tau * a.ldb;
+                        if (a.c0 + 2 * q < a.P) re = (T)row[fft_bcol(a, a.c0 + 2 * q)];
+                        if (a.c0 + 2 * q + 1 < a.P) im = (T)row[fft_bcol(a, a.c0 + 2 * q + 1)];
+                    }
                 }
                 x = C{re, im};
             } else {
@@ -1829,8 +1870,13 @@ static hipError_t fft_group(const std::vector<const GemmArgs *> &as, const std::
     for (size_t i = 0; i + (mid ? 1 : 0) < n; ++i) {
         ns(Ns);
         to();
-        RET_IF((i == 0 ? launch_fft_pass<T, TIN, -1, FS_REAL, FD_CPLX, 0>(plan[i], ps, st, s)
-                       : launch_fft_pass<T, T, -1, FS_CPLX, FD_CPLX, 0>(plan[i], ps, st, s)));
+        if (i == 0 && a0.ea.rhs) {
+            if constexpr (std::is_same<T, double>::value) RET_IF((launch_fft_pass<T, TIN, -1, FS_RHS, FD_CPLX, 0>(plan[i], ps, st, s)));
+            else return hipErrorInvalidValue;   // right-hand sides computed in the pass: FP64 route only
+        } else {
+            RET_IF((i == 0 ? launch_fft_pass<T, TIN, -1, FS_REAL, FD_CPLX, 0>(plan[i], ps, st, s)
+                           : launch_fft_pass<T, T, -1, FS_CPLX, FD_CPLX, 0>(plan[i], ps, st, s)));
+        }
         from();
         Ns *= plan[i];
     }
@@ -1883,7 +1929,8 @@ static hipError_t launch_toep_fft(const std::vector<const GemmArgs *> &all, Stag
         const size_t csz = (a->mode == GM_F64) ? 16 : 8;
         const long qcap = (long)(a->fft_buf_cap / (csz * (size_t)a->fft_L));
         if (qcap < 1) return hipErrorInvalidValue;
-        const long key = ((long)a->fft_L << 8) | (a->mode << 6) | ((a->fft_b64 ? 1 : 0) << 5) | a->epi;
+        const long key = ((long)a->fft_L << 8) | (a->mode << 6) | ((a->fft_b64 ? 1 : 0) << 5) | ((a->ea.rhs ? 1 : 0) << 4) |
+                         a->epi;
         if ((a->P + 1) / 2 > qcap) {   // several chunks: alone
             groups.push_back({-1, {a}});
             continue;
