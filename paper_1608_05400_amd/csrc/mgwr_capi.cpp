@@ -385,7 +385,8 @@ struct mgwr_ctx {
     double *xcol = nullptr;          // 1D FP32 FFT route: the first colour's new values [M][maxPc]
     float *xop32 = nullptr;          // D&C: its FP32 copy
     uint16_t *xpk_hi = nullptr, *xpk_lo = nullptr;   // D&C: its split-BF16 copy
-    double *partials = nullptr;
+    double *partials = nullptr;      // norm partials: 2 partials_nblk doubles
+    long partials_nblk = 0;
     void *part = nullptr;            // split-K partials of the Toeplitz products
     size_t part_cap = 0;
     // FFT route of the FP64 products: transform length, twiddles, spectra, work arrays
@@ -1265,6 +1266,7 @@ struct FineRes {
     double *norm2;   // nullptr: no norms
     double *out;     // nullptr: the handle's residual buffer
     int out_split = 0;   // out in the split storage order (the inner hierarchy's right-hand side)
+    const double *dd_e = nullptr;   // correction (split order) added to (u, lo) first
 };
 
 int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
@@ -1273,6 +1275,7 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
     std::vector<FillArgs> fills;
     std::vector<PostArgs> posts;
     std::vector<NormArgs> norms;
+    std::vector<DDArgs> upd;
     int level = -1;
     for (const FineRes &r : v) {
         mgwr_ctx *h = r.h;
@@ -1280,6 +1283,7 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
         level = (int)h->lv.size() - 1;
         double *out = r.out ? r.out : h->res64;
         bool fused = false;
+        long norm_blocks = 0;   // > 0: the product writes the norm partials
         // the dense route stores the product apart when out is split (the
         // residual kernel reads it in natural order)
         double *prod_at = r.out_split ? h->rs64 : out;
@@ -1299,19 +1303,34 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
                 a.ea.ih2 = L.ih2; a.ea.diag = 0.0; a.ea.ldu = L.P;
                 a.ea.lay_in = 0; a.ea.lay_out = r.out_split;
                 fused = true;
+                // in one chunk of radix-256 passes the last pass writes the
+                // norm partials itself (adding the double-double update to
+                // the first pass measured slower than the update kernel:
+                // 1.07 ms against 0.33 + 0.55 ms on the 1D N = 4095,
+                // M = 16384 problems)
+                const long nb = fft_fused_blocks(a);
+                if (nb > 0 && r.norm2 && nb <= h->partials_nblk) {
+                    a.ea.norm_part = h->partials;
+                    norm_blocks = nb;
+                }
             }
             prods.push_back(a);
         }
+        if (r.dd_e)
+            upd.push_back(DDArgs{(long)h->M * L.P, r.dd_e, const_cast<double *>(r.u), const_cast<double *>(r.lo),
+                                 h->dims, L.n, 1});
         if (!fused) {
             posts.push_back(PostArgs{h->dims, L.n, h->M, r.f, r.u, r.lo, h->cd, r.g, L.ih2, 0.0, out, 0, r.out_split,
                                      prod_at});
         }
         if (r.norm2) {
             const long n = (long)h->M * L.P;
-            norms.push_back(NormArgs{n, out, h->partials, norm_partial_blocks(n), r.norm2});
+            if (norm_blocks > 0) norms.push_back(NormArgs{n, out, h->partials, (int)norm_blocks, r.norm2, 1});
+            else norms.push_back(NormArgs{n, out, h->partials, norm_partial_blocks(n), r.norm2});
         }
     }
     HIPCHK(launch_fill(fills, ex.st, ex.s));
+    HIPCHK(launch_dd_update(upd, ex.st, ex.s));
     CHK(run_gemms(ex, prods, level));
     HIPCHK(launch_post(posts, ex.st, ex.s));
     HIPCHK(launch_norms(norms, ex.st, ex.s));
@@ -1534,20 +1553,19 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
         Body step = [&](Exec &ex) -> int {
             std::vector<Task> plain, inner;
             std::vector<FillArgs> zero;
-            std::vector<DDArgs> upd;
             std::vector<FineRes> res;
             for (int i : act) {
                 mgwr_ctx *h = hs[i];
                 const int top = (int)h->lv.size() - 1;
+                res.push_back(fine_res(i, false));
                 if (!refine(i)) {
                     plain.push_back(Task{&Hp[i], top});
                 } else {
                     Level &L = h->lv.back();
                     inner.push_back(Task{&Hi[i], top, true});
                     if (!skip_zero_fill(Hi[i], top)) zero.push_back(FillArgs{h->M, L.P, nullptr, nullptr, L.e, 0});
-                    upd.push_back(DDArgs{(long)h->M * L.P, L.e, u[i], h->ulo, h->dims, L.n, 1});
+                    res.back().dd_e = L.e;   // u += e (double-double) ahead of the residual
                 }
-                res.push_back(fine_res(i, false));
             }
             CHK(cycle(ex, plain));
             HIPCHK(launch_fill(zero, ex.st, ex.s));
@@ -1563,7 +1581,6 @@ int solve_group(Runner &R, const std::vector<mgwr_ctx *> &hs, const double *cons
                     }
                 CHK(cycle(ex, sel));
             }
-            HIPCHK(launch_dd_update(upd, ex.st, ex.s));
             return fine_residuals(ex, res);
         };
         {
@@ -2060,7 +2077,16 @@ int mgwr_create_ex(int N, int M, double alpha, double T, int dims, const mgwr_op
         CHK(dmalloc(h->alloc, (void **)&h->res64, sizeof(double) * M * Pf));
         CHK(dmalloc(h->alloc, (void **)&h->panel64, sizeof(double) * M * h->maxPc));
         CHK(dmalloc(h->alloc, (void **)&h->ulo, sizeof(double) * M * Pf));
-        CHK(dmalloc(h->alloc, (void **)&h->partials, sizeof(double) * 2 * 2048));
+        // norm partials: the blocks of the reduction kernel, or those of the
+        // last pass of the finest FP64 residual product by FFT (which writes them)
+        h->partials_nblk = 2048;
+        {
+            long L = 64;
+            while (L < 2L * M) L <<= 1;
+            const long Q = (Pf + 1) / 2;
+            if (L >= 512) h->partials_nblk = std::max(h->partials_nblk, (Q + 15) / 16 * (L / 256));
+        }
+        CHK(dmalloc(h->alloc, (void **)&h->partials, sizeof(double) * 2 * h->partials_nblk));
         // split-K scratch: the largest any lone product of this hierarchy
         // needs under any tile knobs the tuner tries
         size_t part = 0;

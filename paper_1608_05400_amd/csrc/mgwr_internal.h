@@ -101,6 +101,10 @@ struct EpiArgs {
     // the colour's first, rows ldu apart) and the level's iterate U (the
     // other colour's values; rows ldu apart), g in natural order
     int rhs = 0;
+    // FP64 residual on the FFT route (EPI_RESID, EPI_RESID_DD) in one chunk
+    // of radix-256 passes: norm_part != nullptr: the last pass writes each
+    // block's {max |r|, sum r^2} to norm_part[2 b], [2 b + 1]
+    double *norm_part = nullptr;
 };
 
 // Tile choices of the product kernels (set by the autotuner).
@@ -298,6 +302,7 @@ struct NormArgs {
     double *partials;
     int nblk;
     double *out2;
+    int have_partials = 0;   // the partials were written by the product (only the final reduction)
 };
 // (hi, lo) += e (double-double); lo == nullptr: hi += e.  hi and lo in
 // natural order; e in the storage order `split` of a level with npd points
@@ -341,6 +346,10 @@ hipError_t launch_permute(const std::vector<PermuteArgs> &v, Staging *st, hipStr
 // one product (written by the first kernel, read and written by each middle
 // one, read by the last).
 double fft_work_bytes(const GemmArgs &a);
+// Blocks of the last pass of an FP64 FFT-route product whose columns fit its
+// work arrays in one chunk and whose transform uses the radix-256 passes
+// (the residual products that can write norm partials); 0 for any other.
+long fft_fused_blocks(const GemmArgs &a);
 // Fill one coefficient table (fp32 copy and bf16 fragment table) from d64.
 hipError_t launch_build_coef(ToepCoef &c, hipStream_t s);
 // Blocks of the norm partials of an n-element array.

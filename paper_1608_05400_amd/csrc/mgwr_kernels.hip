@@ -1321,6 +1321,9 @@ __device__ inline void dft_reg(typename Cx<T>::v (&v)[R])
     }
 }
 
+__device__ inline double nan_max(double a, double m);
+__device__ inline void block_reduce(double &mx, double &sq);
+
 template <typename T, typename TIN, int R, int SIGN, int SRC, int DST, int EPI>
 __global__ __launch_bounds__(256) void k_fft_pass(Grp<FftPass> grp)
 {
@@ -1485,6 +1488,13 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
     }
     __syncthreads();
     const int base = (j / a.Ns) * a.Ns * R + jm;
+    // FP64 residual with fused norms: this thread's max |r| and sum r^2
+    constexpr bool NORMS = DST == FD_EPI && (EPI == EPI_RESID || EPI == EPI_RESID_DD) && sizeof(T) == 8;
+    double nmx = 0.0, nsq = 0.0;
+    auto acc_norm = [&](double r) {
+        nmx = nan_max(fabs(r), nmx);
+        nsq += r * r;
+    };
     for (int job = threadIdx.x; job < R1 * NC; job += NT) {
         const int c = job % NC, k1 = job / NC, q = q0 + c;
         C v[R2];
@@ -1516,8 +1526,13 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
                         for (int k = 0; k < CH; ++k) {
                             const int tau = base + (k1 + R1 * (k0 + k)) * a.Ns;
                             if (tau >= a.M) continue;
-                            epi_put<EPI>(a.ea, tau, cc, pre[k][0], (double)v[k0 + k].x * a.scale);
-                            if (cc + 1 < a.P) epi_put<EPI>(a.ea, tau, cc + 1, pre[k][1], (double)v[k0 + k].y * a.scale);
+                            const double q0 = (double)v[k0 + k].x * a.scale, q1 = (double)v[k0 + k].y * a.scale;
+                            epi_put<EPI>(a.ea, tau, cc, pre[k][0], q0);
+                            if constexpr (NORMS) acc_norm(pre[k][0] - q0);   // the value stored
+                            if (cc + 1 < a.P) {
+                                epi_put<EPI>(a.ea, tau, cc + 1, pre[k][1], q1);
+                                if constexpr (NORMS) acc_norm(pre[k][1] - q1);
+                            }
                         }
                     }
                     continue;
@@ -1564,9 +1579,25 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
                 for (int k = 0; k < CH; ++k) {
                     const int tau = base + (k1 + R1 * (k0 + k)) * a.Ns;
                     if (tau >= a.M) continue;
-                    if (cc < a.P) epi_put<EPI>(a.ea, tau, cc, pre[k][0], (double)v[k0 + k].x * a.scale);
-                    if (cc + 1 < a.P) epi_put<EPI>(a.ea, tau, cc + 1, pre[k][1], (double)v[k0 + k].y * a.scale);
+                    const double q0 = (double)v[k0 + k].x * a.scale, q1 = (double)v[k0 + k].y * a.scale;
+                    if (cc < a.P) {
+                        epi_put<EPI>(a.ea, tau, cc, pre[k][0], q0);
+                        if constexpr (NORMS) acc_norm(pre[k][0] - q0);
+                    }
+                    if (cc + 1 < a.P) {
+                        epi_put<EPI>(a.ea, tau, cc + 1, pre[k][1], q1);
+                        if constexpr (NORMS) acc_norm(pre[k][1] - q1);
+                    }
                 }
+            }
+        }
+    }
+    if constexpr (NORMS) {
+        if (a.ea.norm_part) {   // a launch-wide choice: every thread reaches the reduction
+            block_reduce(nmx, nsq);
+            if (threadIdx.x == 0) {
+                gview_rw<double>(a.ea.norm_part)[2 * lb] = nmx;
+                gview_rw<double>(a.ea.norm_part)[2 * lb + 1] = nsq;
             }
         }
     }
@@ -1780,6 +1811,16 @@ double fft_work_bytes(const GemmArgs &a)
     return 2.0 * (kernels - 1) * array;
 }
 
+long fft_fused_blocks(const GemmArgs &a)
+{
+    if (!a.fft_spec || a.mode != GM_F64) return 0;
+    if (fft_plan(a.fft_L).back() != 256) return 0;
+    const long Q = (a.P + 1) / 2;
+    if (Q > (long)(a.fft_buf_cap / (16 * (size_t)a.fft_L))) return 0;   // several chunks
+    constexpr int NC = fft_lds_cols<double, EPI_RESID>();
+    return (Q + NC - 1) / NC * (a.fft_L / 256);
+}
+
 template <typename T, typename TIN, int R1, int R2, int SIGN, int SRC, int DST, int EPI>
 static hipError_t launch_fft_lds(const std::vector<FftPass> &ps, Staging *st, hipStream_t s)
 {
@@ -1929,8 +1970,8 @@ static hipError_t launch_toep_fft(const std::vector<const GemmArgs *> &all, Stag
         const size_t csz = (a->mode == GM_F64) ? 16 : 8;
         const long qcap = (long)(a->fft_buf_cap / (csz * (size_t)a->fft_L));
         if (qcap < 1) return hipErrorInvalidValue;
-        const long key = ((long)a->fft_L << 8) | (a->mode << 6) | ((a->fft_b64 ? 1 : 0) << 5) | ((a->ea.rhs ? 1 : 0) << 4) |
-                         a->epi;
+        const long key = ((long)a->fft_L << 8) | (a->mode << 6) | ((a->fft_b64 ? 1 : 0) << 5) |
+                         ((a->ea.rhs ? 1 : 0) << 4) | a->epi;
         if ((a->P + 1) / 2 > qcap) {   // several chunks: alone
             groups.push_back({-1, {a}});
             continue;
@@ -2453,7 +2494,7 @@ int norm_partial_blocks(long n)
 hipError_t launch_norms(const std::vector<NormArgs> &v, Staging *st, hipStream_t s)
 {
     RET_IF(launch_subset<OpNormPartial>(
-        v, [](const NormArgs &) { return true; }, [](const NormArgs &a) { return (long)a.nblk; }, st, s));
+        v, [](const NormArgs &a) { return !a.have_partials; }, [](const NormArgs &a) { return (long)a.nblk; }, st, s));
     return launch_subset<OpNormFinal>(
         v, [](const NormArgs &) { return true; }, [](const NormArgs &) { return 1L; }, st, s);
 }
