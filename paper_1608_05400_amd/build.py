@@ -20,6 +20,11 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fully unroll the loops marked for it even when their bodies are large:
+    # the FFT passes' epilogues index the DFT outputs by the loop counter,
+    # which left rolled puts them in scratch memory (272-528 bytes per lane
+    # on the FP64 residual passes)
+    "-mllvm", "-pragma-unroll-threshold=200000",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

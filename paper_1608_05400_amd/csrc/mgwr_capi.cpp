@@ -1294,9 +1294,11 @@ int fine_residuals(Exec &ex, const std::vector<FineRes> &v)
             a.M = h->M; a.P = (int)L.P; a.K = h->M; a.off = 0; a.coef = &h->tm; a.epi = EPI_STORE;
             a.ea.out = prod_at; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n;
             a.B = r.u; a.ldb = L.P;
-            if (fft_for(h, level)) {
-                set_fft(h, a, h->spec_tm);
-                // the FFT route's last pass applies the stencil part itself
+            if (fft_for(h, level)) set_fft(h, a, h->spec_tm);
+            // In 1D the FFT route's last pass applies the stencil part itself.
+            // In 2D its stencil reads rows n points apart, and the product
+            // stored as it is plus the residual kernel take less time
+            if (fft_for(h, level) && h->dims == 1) {
                 a.epi = r.lo ? EPI_RESID_DD : EPI_RESID;
                 a.ea.out = out;
                 a.ea.F = r.f; a.ea.U = r.u; a.ea.lo = r.lo; a.ea.cd = h->cd; a.ea.g = r.g;
