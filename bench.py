@@ -409,6 +409,45 @@ def bench_fas(B, args):
     print(json.dumps(line), flush=True)
 
 
+def bench_products(B, args):
+    """The dense matrix-core Toeplitz products on their own (mgwr_toeplitz_apply
+    on a handle with the FFT route off), at the shapes of the benchmark
+    workloads: the residual product of the 1D N = 4095, M = 16384 problem
+    (T_M times all 4095 columns) and a smoother product of the 2D N = 511,
+    M = 2048 problem (one colour, 130560 columns), in FP64, FP32 and split
+    BF16.  Per-launch times from the library's HIP events; algorithmic flops
+    2 x (multiply-adds not structurally zero).  Prints one JSON line."""
+    import torch
+    shapes = [("1d_residual_N4095_M16384", 1, 4095, 16384, 0.3, 4095),
+              ("2d_smoother_N511_M2048", 2, 511, 2048, 0.4, 130560)]
+    out = {}
+    for name, dims, N, M, alpha, P in shapes:
+        X = torch.randn((M, P), dtype=torch.float64, device="cuda")
+        for prec in ("fp64", "fp32", "bf16x3"):
+            with B.Solver(N, M, alpha, dims=dims, fft=0, precision=prec) as s:
+                # T_M for the residual, the finest level's inverse column for the smoother
+                which = -1 if "residual" in name else s.levels() - 1
+                C = torch.empty_like(X)
+                for _ in range(args.warmup):
+                    s.toeplitz_apply(X, which=which, precision=prec, C=C)
+                torch.cuda.synchronize()
+                s.profile(True)
+                for _ in range(args.steps):
+                    s.toeplitz_apply(X, which=which, precision=prec, C=C)
+                recs = s.profile_records()
+                s.profile(False)
+            ms = sum(r["ms"] for r in recs) / len(recs)
+            fl = recs[0]["flops"]
+            tf = fl / (ms * 1e-3) / 1e12
+            out[f"{name}_{prec}"] = {"kernel": recs[0]["name"], "avg_ms": round(ms, 4), "gflop": round(fl / 1e9, 2),
+                                     "tflops": round(tf, 1), "peak": PEAK_TFLOPS[{"fp64": 0, "fp32": 1, "bf16x3": 2}[prec]],
+                                     "launches": len(recs)}
+            log(f"{name} {prec}: {recs[0]['name']} {ms:.3f} ms, {tf:.1f} TFLOP/s")
+        del X
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "products", "results": out}), flush=True)
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -452,17 +491,18 @@ def calibrate_copy(mib=512, reps=3):
 
 
 # Precision modes per workload, the first one reported as `value`: the mixed
-# mode whose products actually differ from the others there.  On the 1D
-# N = 4095, M = 16384 problems every mixed product takes the FP32 FFT route
-# (split-BF16 products lose to it by 3-4x at M = 16384, so the split-BF16
-# mode runs the same FP32 products); on the 2D and batch workloads the
-# split-BF16 matrix-core products are chosen per level where they are faster.
+# mode whose products actually run there.  On the 1D N = 4095, M = 16384
+# problems and on the batch every mixed product takes the FP32 FFT route (the
+# split-BF16 products lose to it at M >= 4096 and on the batch's many small
+# levels, so the split-BF16 mode's tuner picks the same FP32 products); on
+# the 2D workload the split-BF16 matrix-core products win on the levels with
+# many columns and are chosen there.
 DEFAULT_MODES = {"1d": "fp32,fp64,bf16x3,fp64r", "2d": "bf16x3,fp64,fp32,fp64r",
                  "2dns": "bf16x3,fp64,fp32,fp64r", "small": "fp32,fp64,bf16x3,fp64r",
-                 "batch": "bf16x3,fp64,fp32,fp64r"}
+                 "batch": "fp32,fp64,bf16x3,fp64r"}
 # Workloads measured after the default one and reported beside it (mixed
 # mode and plain FP64, fewer steps).
-EXTRA = {"2d": "bf16x3,fp64", "batch": "bf16x3,fp64"}
+EXTRA = {"2d": "bf16x3,fp64", "batch": "fp32,fp64"}
 
 
 def log_kernels(mode, res, recs, steps):
@@ -512,7 +552,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="1d", choices=["1d", "2d", "2dns", "small", "batch", "fas"])
+    ap.add_argument("--workload", default="1d", choices=["1d", "2d", "2dns", "small", "batch", "fas", "products"])
     ap.add_argument("--smoother", default="inverse", choices=["inverse", "dc", "auto"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -541,6 +581,8 @@ def main():
     B.load()
     if args.workload == "fas":
         return bench_fas(B, args)
+    if args.workload == "products":
+        return bench_products(B, args)
     modes = [m.strip() for m in (args.modes or DEFAULT_MODES[args.workload]).split(",") if m.strip()]
     results, rooflines, wname = run_workload(args.workload, modes, args, args.steps, args.warmup)
     primary = modes[0]
