@@ -422,6 +422,33 @@ def test_table2_wcycle_asymptotic_factor(row):
     assert abs(fac - measured) <= 0.012, fac
 
 
+@pytest.mark.parametrize("row", [r for r in load_golden("table2_wcycle_1d_transient.txt") if r[1] <= 64])
+def test_table2_wcycle_transient_rows(row):
+    """Rows with log2 lambda < 0 (M = 32, 64): 400 W-cycles, the iterate
+    rescaled to unit norm after each; the printed factor lies in the range of
+    the 20-cycle factors ending at cycles 100, 200, 300, 400 (margin 0.005,
+    or 25 % of the printed factor plus 0.001 where tighter): the factor is a
+    transient of the non-normal cycle operator there."""
+    l2lam, M, _pred, measured = row
+    M = int(M)
+    alpha, N = 0.4, 63
+    h = 1.0 / (N + 1)
+    tau = (2.0 ** l2lam * h * h / math.gamma(2 - alpha)) ** (1 / alpha)
+    T = M * tau
+    f = np.zeros((M, N))
+    u = np.random.default_rng(1).standard_normal((M, N))
+    logs, scale = [], 0.0
+    for _ in range(400):
+        u = oracle.vcycle(1, N, M, alpha, f, u, nu1=1, nu2=0, gamma=2, T=T)
+        logs.append(scale + math.log(np.linalg.norm(oracle.residual(1, N, M, alpha, f, u, T=T))))
+        nu = np.linalg.norm(u)
+        scale += math.log(nu)
+        u = u / nu
+    facs = [math.exp((logs[k - 1] - logs[k - 21]) / 20) for k in (100, 200, 300, 400)]
+    margin = min(0.005, 0.25 * measured + 0.001)
+    assert min(facs) - margin <= measured <= max(facs) + margin, facs
+
+
 # --------------------------------------------------------------------------
 # first test problem of Section 7: exact solution E_alpha(-t^alpha) sin x
 
