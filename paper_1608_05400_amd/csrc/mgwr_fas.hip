@@ -28,6 +28,11 @@ namespace {
 
 constexpr int kNlThreads = 256;
 constexpr int kNlMaxM = 4096;   // 2 M doubles of LDS per smoother block
+// From this many time levels the residual's T_M u runs on the Toeplitz
+// product kernels; below, the per-unknown history sum is faster (N = 255:
+// 0.015 ms against 0.040 ms for the product at M = 256, whose few tiles
+// leave the GPU mostly idle)
+constexpr int kNlProductMinM = 1024;
 
 __device__ inline double nl_D(double q, double v) { return 1.0 + q * v * v; }
 
@@ -105,29 +110,35 @@ __global__ __launch_bounds__(64) void k_nl_sweep(int N, int M, double h, double 
 
 // out = sf f + sn N(u) + add (f, add may be null): sf = 1, sn = -1 is the
 // residual; sf = 0, sn = 1, add = restricted residual the coarse FAS
-// right-hand side.
-__global__ void k_nl_apply(int N, int M, double h, double c, double q, const double *r, const double *u,
-                           const double *f, double sf, double sn, const double *add, double *out)
+// right-hand side.  The time-fractional part T_M u (the causal product with
+// first column r) is tu, computed before by the FP64 Toeplitz product
+// kernels, or (tu null: short time lines) summed here per unknown.
+__global__ void k_nl_apply(int N, int M, double h, double c, double q, const double *r, const double *tu,
+                           const double *u, const double *f, double sf, double sn, const double *add, double *out)
 {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)M * N) return;
     const int m = (int)(e / N), n = (int)(e - (long)m * N) + 1;
-    // the history sum in order of j, its loads issued eight at a time so
-    // that they are in flight together rather than one after another
-    const double *col = u + (n - 1);
     double s = 0.0;
-    int j = 0;
-    for (; j + 8 <= m + 1; j += 8) {
-        double x[8], w[8];
+    if (tu) {   // a launch-wide choice
+        s = tu[e];
+    } else {
+        // the history sum in order of j, its loads issued eight at a time so
+        // that they are in flight together rather than one after another
+        const double *col = u + (n - 1);
+        int j = 0;
+        for (; j + 8 <= m + 1; j += 8) {
+            double x[8], w[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            x[t] = col[(size_t)(j + t) * N];
-            w[t] = r[m - j - t];
+            for (int t = 0; t < 8; ++t) {
+                x[t] = col[(size_t)(j + t) * N];
+                w[t] = r[m - j - t];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) s += w[t] * x[t];
         }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) s += w[t] * x[t];
+        for (; j <= m; ++j) s += r[m - j] * col[(size_t)j * N];
     }
-    for (; j <= m; ++j) s += r[m - j] * col[(size_t)j * N];
     const double *row = u + (size_t)m * N;
     const double uc = row[n - 1], ul = nl_at(row, N, n - 1), ur = nl_at(row, N, n + 1);
     const double ap = 0.5 * (nl_D(q, ur) + nl_D(q, uc)), am = 0.5 * (nl_D(q, ul) + nl_D(q, uc));
@@ -213,6 +224,11 @@ struct NlSolver {
     int M = 0, nu1 = 0, nu2 = 1, first = 1;
     double c = 1.0, q = 1.0;
     const double *r = nullptr;   // device, M coefficients
+    mgwr::ToepCoef tc;           // the same, for the product kernels
+    double *tu = nullptr;        // device, [M][N of the finest level]: T_M u of the level being applied
+                                 // (nullptr: the residual sums the history itself)
+    double *part = nullptr;      // split-K partials of that product
+    size_t part_cap = 0;
     std::vector<NlLevel> lv;
     hipStream_t s = nullptr;
 
@@ -229,8 +245,21 @@ struct NlSolver {
     hipError_t apply(const NlLevel &L, const double *u, const double *f, double sf, double sn, const double *add,
                      double *out)
     {
+        if (tu) {
+            // long time lines: T_M u by the dense FP64 matrix-core product
+            // (O(N M^2) flops near the matrix cores' peak instead of an O(M)
+            // loop per unknown), then the rest
+            mgwr::GemmArgs a;
+            a.mode = mgwr::GM_F64;
+            a.M = M; a.P = L.N; a.K = M; a.off = 0; a.coef = &tc;
+            a.B = u; a.ldb = L.N;
+            a.part = part; a.part_cap = part_cap;
+            a.epi = mgwr::EPI_STORE; a.ea.out = tu; a.ea.ldo = L.N;
+            hipError_t e = mgwr::launch_toep_gemm({a}, nullptr, s);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(k_nl_apply, dim3(blocks((long)M * L.N)), dim3(kNlThreads), 0, s, L.N, M, L.h, c, q, r,
-                           u, f, sf, sn, add, out);
+                           (const double *)tu, u, f, sf, sn, add, out);
         return hipGetLastError();
     }
     hipError_t cycle(int l)
@@ -347,6 +376,16 @@ int fas_solve(int count, int N, int M, const double *alphas, double T, double c,
             ok = hipStreamWaitEvent(S.s, start, 0) == hipSuccess;
         }
         ok = ok && alloc((double **)&S.r, M) && alloc(&P[i].dmax, 1);
+        S.tc.n = M;
+        S.tc.d64 = (double *)S.r;
+        if (ok && M >= kNlProductMinM) {
+            size_t part = 0;
+            for (int l = 0; l <= k; ++l)
+                part = std::max(part, mgwr::splitk_bytes(mgwr::GM_F64, M, (1 << (l + 1)) - 1, M, 0, M,
+                                                         mgwr::TileKnobs{}));
+            ok = alloc(&S.tu, (long)M * N) && (part == 0 || alloc(&S.part, (long)(part / sizeof(double))));
+            S.part_cap = S.part ? part : 0;
+        }
         S.lv.resize(k + 1);
         for (int l = 0; l <= k && ok; ++l) {
             NlLevel &L = S.lv[l];
