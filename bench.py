@@ -27,12 +27,14 @@ HIP events (the roofline's launch times); one more step replays the recorded
 HIP graphs and is reported beside them.
 
 The default run also measures, as `extra_workloads`, the 2D problem
-(N = 511 per dimension, M = 2048, alpha = 0.4, u = t^2 sin(pi x) sin(pi y))
-and the batch of 256 independent 1D problems of uneven size (N in
-{127..2047}, M in {256..8192}, alpha in (0.1, 0.9), seeded; every stage of
-their cycles is one launch over all problems still iterating), each in the
-split-BF16 mode and in plain FP64.  `cpu_baseline` is the oracle's direct
-solve of the first problem, all of it, timed on the host's cores.
+(N = 511 per dimension, M = 2048, alpha = 0.4, u = t^2 sin(pi x) sin(pi y)),
+the 2D problem with a non-smooth solution (N = 1023, M = 1024, alpha = 0.3,
+u = (t^alpha + t^2) sin(pi x) sin(pi y)), both in the split-BF16 mode, and
+the batch of 256 independent 1D problems of uneven size (N in {127..2047},
+M in {256..8192}, alpha in (0.1, 0.9), seeded; every stage of their cycles
+is one launch over all problems still iterating) in the FP32 mode, each
+also in plain FP64.  `cpu_baseline` is the oracle's direct solve of the
+first problem, all of it, timed on the host's cores.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -502,7 +504,7 @@ DEFAULT_MODES = {"1d": "fp32,fp64,bf16x3,fp64r", "2d": "bf16x3,fp64,fp32,fp64r",
                  "batch": "fp32,fp64,bf16x3,fp64r"}
 # Workloads measured after the default one and reported beside it (mixed
 # mode and plain FP64, fewer steps).
-EXTRA = {"2d": "bf16x3,fp64", "batch": "fp32,fp64"}
+EXTRA = {"2d": "bf16x3,fp64", "2dns": "bf16x3,fp64", "batch": "fp32,fp64"}
 
 
 def log_kernels(mode, res, recs, steps):
@@ -564,7 +566,8 @@ def main():
                     help="time the oracle on the first K time levels only (default: the whole solve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 2D and batch workloads of the default run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 2D, 2D non-smooth and batch workloads of the default run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU (one problem or one batch per GPU); --gpus must be 1",
