@@ -382,7 +382,6 @@ struct mgwr_ctx {
     uint16_t *pk_hi = nullptr, *pk_lo = nullptr;
     long pk_ld = 0;
     double *xpanel = nullptr;        // D&C: FP64 solution panel [M][maxPc]
-    double *xcol = nullptr;          // 1D FP32 FFT route: the first colour's new values [M][maxPc]
     float *xop32 = nullptr;          // D&C: its FP32 copy
     uint16_t *xpk_hi = nullptr, *xpk_lo = nullptr;   // D&C: its split-BF16 copy
     double *partials = nullptr;      // norm partials: 2 partials_nblk doubles
@@ -694,7 +693,7 @@ int alloc_inner(mgwr_t h, int prec, bool dc)
     HIPCHK(hipDeviceSynchronize());
     free_list(h->inner_alloc);
     for (auto &L : h->lv) { L.e = nullptr; L.fe = nullptr; }
-    h->rs64 = nullptr; h->panel32 = nullptr; h->op32 = nullptr; h->xcol = nullptr;
+    h->rs64 = nullptr; h->panel32 = nullptr; h->op32 = nullptr;
     h->pk_hi = h->pk_lo = nullptr;
     h->xpanel = nullptr; h->xop32 = nullptr; h->xpk_hi = h->xpk_lo = nullptr;
     h->inner_prec = -1;
@@ -714,7 +713,6 @@ int alloc_inner(mgwr_t h, int prec, bool dc)
     if (low) {
         CHK(dmalloc(A, (void **)&h->panel32, sizeof(float) * M * h->maxPc));
         CHK(dmalloc(A, (void **)&h->op32, sizeof(float) * M * Pf));
-        if (h->dims == 1 && h->opt.fft != 0 && M >= 32) CHK(dmalloc(A, (void **)&h->xcol, sizeof(double) * M * h->maxPc));
     }
     h->pk_ld = (Pf + 127) / 128 * 128;
     const size_t pk_bytes = sizeof(uint16_t) * (size_t)h->Mpad * h->pk_ld;
@@ -860,26 +858,6 @@ int dc_half_sweep(Exec &ex, const std::vector<DcItem> &items)
     return MGWR_OK;
 }
 
-// Whether a task's two half-sweeps both take the FP32 FFT route with the
-// diagonal term in the last pass (1D, inverse-column smoother): then the
-// first writes its colour's new values into a contiguous panel (xcol) rather
-// than into every other point of U, and the second reads its neighbours
-// from that panel and writes whole rows of U, its own colour's points and
-// the panel's (a scatter to every other point costs a third of the
-// product's time in partially written lines).
-bool colour_panels(const Task &t)
-{
-    const mgwr_ctx *h = t.H->h;
-    if (t.H->split || h->dims != 1 || !h->xcol || dc_block_of(h, t.lev) > 0) return false;
-    const Level &L = h->lv[t.lev];
-    for (int c = 0; c < 2; ++c) {
-        if (L.Pc[c] == 0) return false;
-        const int mode = level_mode(*t.H, L.Pc[c]);
-        if (mode == GM_F64 || !fft_for(h, t.lev, mode) || h->c > kFft32MaxHist * L.sigma) return false;
-    }
-    return true;
-}
-
 // One half-sweep (colour `rank` 0 = first, 1 = second) of every task: every
 // point of the colour gets the solution of (T_M + sigma I) x = b along its
 // time line.  Inverse-column solve: in FP64 the product is the whole solve;
@@ -955,38 +933,29 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
         } else if (fft_for(h, t.lev, mode)) {
             // FP64 right-hand sides; the FFT's first pass rounds them to FP32
             // and its last pass writes lambda_0 b + history into the colour's
-            // points of U (one store, the diagonal term in FP64)
-            a.coef = &L.inv_h; a.epi = EPI_SCATTER_DIAG; a.ea.diag = L.lam0;
+            // contiguous points of U (one store, the diagonal term in FP64)
+            a.coef = &L.inv_h; a.epi = EPI_STORE_DIAG; a.ea.diag = L.lam0;
             set_fft32(h, a, L.spec32_inv_h, true);
-            const int other = L.Pc[1 - colour];
-            if (colour_panels(t) && rank == 1) {
-                // neighbours from the first colour's panel, not from U
-                rhs.push_back(RhsArgs{0, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev],
-                                      h->cd, g, L.ih2, 0.0, h->panel64, nullptr, Pc, h->xcol, other, other});
-                a.B = h->panel64; a.ldb = Pc;
-                a.epi = EPI_MERGE_DIAG; a.ea.x = h->xcol; a.ea.ldx = other; a.ea.px = other;
-            } else {
-                rhs_panel();
-                if (colour_panels(t)) { a.epi = EPI_STORE_DIAG; a.ea.out = h->xcol; a.ea.ldo = Pc; }
-            }
-            a.ea.b = (const double *)a.B; a.ea.ldb_diag = a.ldb; a.ea.b_colour = a.b_colour;
+            rhs_panel();
+            a.ea.b = (const double *)a.B; a.ea.ldb_diag = a.ldb;
         } else if (mode == GM_F32) {
             push_rhs(RhsArgs{1, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
                              L.ih2, L.lam0, h->panel32, nullptr, Pc});
-            a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.B = h->panel32; a.ldb = Pc;
+            a.coef = &L.inv_h; a.epi = EPI_ADD; a.B = h->panel32; a.ldb = Pc;
         } else {
             const long ldp = packed_ld(Pc);
             push_rhs(RhsArgs{2, h->dims, L.n, colour, h->M, h->Mpad, t.H->f[t.lev], t.H->u[t.lev], h->cd, g,
                              L.ih2, L.lam0, h->pk_hi, h->pk_lo, ldp});
-            a.coef = &L.inv_h; a.epi = EPI_SCATTER_ADD; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
-        }
-        if (split) {
-            // the colour's points are contiguous from `off`: the scatters are
-            // plain stores there
+            a.coef = &L.inv_h; a.epi = EPI_ADD; a.Bhi = h->pk_hi; a.Blo = h->pk_lo; a.ldb = ldp;
+        }        if (split) {
+            // the colour's points are contiguous from `off`: the FP64 route's
+            // scatter is a plain store there
             a.ea.out = t.H->u[t.lev] + off;
             if (a.epi == EPI_SCATTER) a.epi = EPI_STORE;
-            else if (a.epi == EPI_SCATTER_ADD) a.epi = EPI_ADD;
-            else if (a.epi == EPI_SCATTER_DIAG) a.epi = EPI_STORE_DIAG;
+        } else if (a.epi != EPI_SCATTER) {
+            // the low-precision epilogues write a colour's contiguous points:
+            // only the refinement's inner hierarchy (split) runs them
+            return fail(MGWR_EINVAL, "low-precision smoothing on a level in natural order");
         }
         prods.push_back(a);
     }

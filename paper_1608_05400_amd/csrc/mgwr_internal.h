@@ -46,14 +46,13 @@ struct ToepCoef {
 // They are kept light (one load and one store per element) so that the
 // product kernels keep their occupancy; the stencil parts of the residual
 // and of the smoother run in the bandwidth kernels before the product.
-enum EpiKind {
+enum EpiKind {   // the values are part of the kernel ids of the profiling records
     EPI_STORE = 0,       // out[i][p] = acc                        (residual product)
-    EPI_SCATTER = 1,     // out[i][colour_point(p)] = acc          (smoother, full product)
-    EPI_SCATTER_ADD = 2, // out[i][colour_point(p)] += acc         (smoother, history product)
+    EPI_SCATTER = 1,     // out[i][colour_point(p)] = acc          (FP64 smoother on a level
+                         //   in natural order, full product)
     EPI_SUB = 3,         // out[i][p] -= acc                       (D&C history update)
-    EPI_ADD = 4,         // out[i][p] += acc                       (D&C base block, history part)
-    EPI_SCATTER_DIAG = 5,// out[i][colour_point(p)] = diag b[i][p] + acc  (smoother: the FP64
-                         //   diagonal term of the line solve plus its history product)
+    EPI_ADD = 4,         // out[i][p] += acc                       (D&C base block, or a
+                         //   split level's colour points: the history part)
     EPI_RESID = 6,       // out[i][p] = (F + cd g - diag U - A_h U) - acc at (i, p)  (the
                          //   residual; FFT route only)
     EPI_RESID_DD = 7,    // the same with the iterate U + lo (double-double)
@@ -64,24 +63,18 @@ enum EpiKind {
                          //   points are the coarse points and the other colour's
                          //   residual is zero, so out[i][p] = 0.25 (2 r) is the coarse
                          //   right-hand side (full weighting)
-    EPI_STORE_DIAG = 10, // out[i][p] = diag b[i][p] + acc: EPI_SCATTER_DIAG into a
-                         //   panel of the colour's points, contiguous (1D, first
-                         //   half-sweep; the second one merges the panel into U)
-    EPI_MERGE_DIAG = 11  // 1D: EPI_SCATTER_DIAG, and beside each point of the colour
-                         //   the other colour's point paired with it (pt + 1 for
-                         //   colour 1, pt - 1 for colour 0, and n - 1 from colour 0's
-                         //   last point) from that colour's panel x, so that whole
-                         //   rows of U are written
+    EPI_STORE_DIAG = 10  // out[i][p] = diag b[i][p] + acc: the FP64 diagonal term of the
+                         //   line solve plus its history product, into the contiguous
+                         //   points of one colour of a split level (FP32 FFT route)
 };
 
 struct EpiArgs {
-    double *out = nullptr;     // output (STORE/SUB/ADD) or the iterate U of the level (SCATTER*)
+    double *out = nullptr;     // output (STORE/SUB/ADD/STORE_DIAG) or the iterate U of the level (SCATTER)
     long ldo = 0;
     int dims = 1, n = 1, colour = 0;   // grid of the level (points per dim) and colour
-    const double *b = nullptr; // EPI_SCATTER_DIAG: right-hand sides [M][ldb_diag]
+    const double *b = nullptr; // EPI_STORE_DIAG: right-hand sides [M][ldb_diag]
     long ldb_diag = 0;
-    int b_colour = -1;         // >= 0: column p of them is point colour_point(p) of b's rows
-    double diag = 0.0;         // EPI_SCATTER_DIAG: first entry of the inverse column;
+    double diag = 0.0;         // EPI_STORE_DIAG: first entry of the inverse column;
                                // EPI_RESID: coefficient of U (r_1 when acc is the history part)
     // EPI_RESID: the level's right-hand side F [M][P], iterate U (+ lo, its
     // double-double low part, or nullptr), c d_m, the initial condition g
@@ -89,9 +82,6 @@ struct EpiArgs {
     const double *F = nullptr, *U = nullptr, *lo = nullptr, *cd = nullptr, *g = nullptr;
     double ih2 = 0.0;
     long ldu = 0;              // EPI_RESID*: row length of F, U, lo (the level's points)
-    const double *x = nullptr; // EPI_MERGE_DIAG: the other colour's panel [M][ldx]
-    long ldx = 0;
-    int px = 0;                // its points per row
     // EPI_RESID*: storage order (lay_pos) of F, U, lo (and of the product's
     // columns) and of out; EPI_RESID_R: of the coarse level written
     int lay_in = 0, lay_out = 0;
@@ -235,11 +225,6 @@ struct RhsArgs {
     double ih2, lam0;
     void *panel, *panel_lo;
     long ldp;
-    // 1D, fmt 0: the neighbours (the other colour's points) are read from
-    // that colour's panel X [M][ldx] of px points per row instead of U
-    const double *X = nullptr;
-    long ldx = 0;
-    int px = 0;
     int split = 0;          // storage order of F and U (lay_pos)
 };
 // Residual from a Toeplitz product already in out (the history part, or all

@@ -159,11 +159,8 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
     const GLOBAL double *out = gview<double>(e.out);
     if constexpr (EPI == EPI_SUB || EPI == EPI_ADD) {
         return out[(long)i * e.ldo + p];
-    } else if constexpr (EPI == EPI_SCATTER_ADD) {
-        return out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)];
-    } else if constexpr (EPI == EPI_SCATTER_DIAG || EPI == EPI_STORE_DIAG || EPI == EPI_MERGE_DIAG) {
-        const int pb = e.b_colour < 0 ? p : colour_point(e.dims, e.n, e.b_colour, p);
-        return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + pb];
+    } else if constexpr (EPI == EPI_STORE_DIAG) {
+        return e.diag * gview<double>(e.b)[(long)i * e.ldb_diag + p];
     } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD || EPI == EPI_RESID_C || EPI == EPI_RESID_R) {
         // the stencil part of the residual (as OpPost), fused; no load
         // behind a divergent branch (g and cd are read only when there is an
@@ -197,21 +194,6 @@ __device__ inline double epi_pre(const EpiArgs &e, int i, int p)
     }
 }
 
-// EPI_MERGE_DIAG store of column j (1D) of row i: the colour's point pt gets
-// val; the other colour's point paired with it (pt + 1 for colour 1, while
-// inside the grid; pt - 1 for colour 0), whose index in that colour's panel
-// is j, gets xv; colour 0's last point also writes point n - 1, the other
-// colour's last one.  Every point of the row is written once.
-__device__ inline void merge_put(const EpiArgs &e, int i, int j, double val, double xv)
-{
-    GLOBAL double *row = gview_rw<double>(e.out) + (long)i * e.ldo;
-    const int pt = colour_point(1, e.n, e.colour, j);
-    const int q = e.colour == 1 ? pt + 1 : pt - 1;
-    row[pt] = val;
-    if (q < e.n) row[q] = xv;
-    if (e.colour == 0 && pt == e.n - 2) row[e.n - 1] = gview<double>(e.x)[(long)i * e.ldx + e.px - 1];
-}
-
 template <int EPI>
 __device__ inline void epi_put(const EpiArgs &e, int i, int p, double pre, double acc)
 {
@@ -224,11 +206,6 @@ __device__ inline void epi_put(const EpiArgs &e, int i, int p, double pre, doubl
         out[(long)i * e.ldo + p] = pre + acc;
     } else if constexpr (EPI == EPI_SCATTER) {
         out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = acc;
-    } else if constexpr (EPI == EPI_SCATTER_ADD || EPI == EPI_SCATTER_DIAG) {
-        out[(long)i * e.ldo + colour_point(e.dims, e.n, e.colour, p)] = pre + acc;
-    } else if constexpr (EPI == EPI_MERGE_DIAG) {
-        // (the radix-256 last pass loads the panel values ahead instead)
-        merge_put(e, i, p, pre + acc, gview<double>(e.x)[(long)i * e.ldx + min(p, e.px - 1)]);
     } else if constexpr (EPI == EPI_STORE_DIAG) {
         out[(long)i * e.ldo + p] = pre + acc;
     } else if constexpr (EPI == EPI_RESID || EPI == EPI_RESID_DD) {
@@ -385,17 +362,17 @@ __device__ inline void k_range(const KP &kp, int i0, int s, int &kbase, int &ks0
 // product column p, whether the epilogue reads the old value, and the new value.
 template <int EPI> __device__ constexpr bool epi_reads()
 {
-    return EPI == EPI_SCATTER_ADD || EPI == EPI_SUB || EPI == EPI_ADD;
+    return EPI == EPI_SUB || EPI == EPI_ADD;
 }
 template <int EPI> __device__ inline long epi_col(const EpiArgs &e, int p)
 {
-    if constexpr (EPI == EPI_SCATTER || EPI == EPI_SCATTER_ADD) return colour_point(e.dims, e.n, e.colour, p);
+    if constexpr (EPI == EPI_SCATTER) return colour_point(e.dims, e.n, e.colour, p);
     else return p;
 }
 template <int EPI> __device__ inline double epi_combine(double prev, double acc)
 {
     if constexpr (EPI == EPI_SUB) return prev - acc;
-    else if constexpr (EPI == EPI_SCATTER_ADD || EPI == EPI_ADD) return prev + acc;
+    else if constexpr (EPI == EPI_ADD) return prev + acc;
     else return acc;
 }
 
@@ -1107,7 +1084,6 @@ static hipError_t launch_mode(int epi, std::vector<KP> &kps, const std::vector<G
     if constexpr (MODE == GM_F64) {
         if (epi == EPI_SCATTER) return launch_class<MODE, EPI_SCATTER>(kps, geos, st, s);
     } else {
-        if (epi == EPI_SCATTER_ADD) return launch_class<MODE, EPI_SCATTER_ADD>(kps, geos, st, s);
         if (epi == EPI_ADD) return launch_class<MODE, EPI_ADD>(kps, geos, st, s);
     }
     return hipErrorInvalidValue;
@@ -1405,14 +1381,11 @@ __global__ __launch_bounds__(256) void k_fft_pass(Grp<FftPass> grp)
 // passes other than the last take R2 = 16, so that every thread has a DFT of
 // the first stage, the one that reads the input).  Rows
 // of NC pairs are read and written whole: 16 pairs in FP64 (256 bytes), 32
-// in FP32 (256 bytes, 7 % faster than 16 on the largest products) except in
-// the FP32 last passes that scatter into a colour's points (EPI), where 16
-// measured 5 % faster.  16 pairs per block beat 8 (narrow rows) and two DFTs
-// per thread.
+// in FP32 (256 bytes, 7 % faster than 16 on the largest products).  16 pairs
+// per block beat 8 (narrow rows) and two DFTs per thread.
 template <typename T, int EPI = -1> constexpr int fft_lds_cols()
 {
-    return (sizeof(T) == 4 && EPI != EPI_SCATTER && EPI != EPI_SCATTER_ADD && EPI != EPI_SCATTER_DIAG &&
-            EPI != EPI_MERGE_DIAG) ? 32 : 16;
+    return sizeof(T) == 4 ? 32 : 16;
 }
 template <typename T, int EPI = -1> constexpr int fft_lds_threads() { return 16 * fft_lds_cols<T, EPI>(); }
 
@@ -1537,34 +1510,6 @@ __global__ __launch_bounds__((fft_lds_threads<T, DST == FD_EPI ? EPI : -1>())) v
                     }
                     continue;
                 }
-            }
-            if constexpr (EPI == EPI_MERGE_DIAG) {
-                // the other colour's values beside the two columns, loaded
-                // with the right-hand sides ahead of the stores (clamped:
-                // colour 1's last column has no partner)
-                const int j0 = min(cc, a.P - 1), j1 = min(cc + 1, a.P - 1), xl = a.ea.px - 1;
-#pragma unroll
-                for (int k0 = 0; k0 < R2; k0 += CH) {
-                    double pre[CH][2], xv[CH][2];
-#pragma unroll
-                    for (int k = 0; k < CH; ++k) {
-                        const int tau = min(base + (k1 + R1 * (k0 + k)) * a.Ns, a.M - 1);
-                        const GLOBAL double *xr = gview<double>(a.ea.x) + (long)tau * a.ea.ldx;
-                        pre[k][0] = epi_pre<EPI>(a.ea, tau, j0);
-                        pre[k][1] = epi_pre<EPI>(a.ea, tau, j1);
-                        xv[k][0] = xr[min(j0, xl)];
-                        xv[k][1] = xr[min(j1, xl)];
-                    }
-#pragma unroll
-                    for (int k = 0; k < CH; ++k) {
-                        const int tau = base + (k1 + R1 * (k0 + k)) * a.Ns;
-                        if (tau >= a.M) continue;
-                        if (cc < a.P) merge_put(a.ea, tau, cc, pre[k][0] + (double)v[k0 + k].x * a.scale, xv[k][0]);
-                        if (cc + 1 < a.P)
-                            merge_put(a.ea, tau, cc + 1, pre[k][1] + (double)v[k0 + k].y * a.scale, xv[k][1]);
-                    }
-                }
-                continue;
             }
 #pragma unroll
             for (int k0 = 0; k0 < R2; k0 += CH) {
@@ -1942,14 +1887,11 @@ static hipError_t fft_group(const std::vector<const GemmArgs *> &as, const std::
             switch (a0.epi) {
             case EPI_STORE: RET_IF((launch_fft_last<T, EPI_STORE>(plan[i], ps, st, s))); break;
             case EPI_SCATTER: RET_IF((launch_fft_last<T, EPI_SCATTER>(plan[i], ps, st, s))); break;
-            case EPI_SCATTER_ADD: RET_IF((launch_fft_last<T, EPI_SCATTER_ADD>(plan[i], ps, st, s))); break;
-            case EPI_SCATTER_DIAG: RET_IF((launch_fft_last<T, EPI_SCATTER_DIAG>(plan[i], ps, st, s))); break;
             case EPI_RESID: RET_IF((launch_fft_last<T, EPI_RESID>(plan[i], ps, st, s))); break;
             case EPI_RESID_DD: RET_IF((launch_fft_last<T, EPI_RESID_DD>(plan[i], ps, st, s))); break;
             case EPI_RESID_C: RET_IF((launch_fft_last<T, EPI_RESID_C>(plan[i], ps, st, s))); break;
             case EPI_RESID_R: RET_IF((launch_fft_last<T, EPI_RESID_R>(plan[i], ps, st, s))); break;
             case EPI_STORE_DIAG: RET_IF((launch_fft_last<T, EPI_STORE_DIAG>(plan[i], ps, st, s))); break;
-            case EPI_MERGE_DIAG: RET_IF((launch_fft_last<T, EPI_MERGE_DIAG>(plan[i], ps, st, s))); break;
             default: return hipErrorInvalidValue;
             }
         }
@@ -2025,15 +1967,7 @@ template <typename S> struct OpRhsPanel {
             int pt = colour_point(a.dims, a.n, a.colour, j);             // natural
             int sp = lay_cpos(a.dims, a.n, a.split, a.colour, j);        // stored at
             GLOBAL double *Uk = U + (long)k * P;
-            double ns;
-            if (a.X) {   // 1D: the neighbours pt -+ 1 are the other colour's points jl, jr of X
-                const GLOBAL double *Xk = gview<double>(a.X) + (long)k * a.ldx;
-                const int jl = a.colour == 1 ? j - 1 : j, jr = a.colour == 1 ? j : j + 1;
-                ns = (jl >= 0 ? Xk[jl] : 0.0) + (jr < a.px ? Xk[jr] : 0.0);
-            } else {
-                ns = nbr_sum(Uk, a.dims, a.n, pt, a.split);
-            }
-            double b = F[(long)k * P + sp] + ns * a.ih2;
+            double b = F[(long)k * P + sp] + nbr_sum(Uk, a.dims, a.n, pt, a.split) * a.ih2;
             if (a.g) b += cd[k] * g[pt];
             panel[(long)k * a.ldp + j] = (S)b;
             if (a.lam0 != 0.0) Uk[sp] = a.lam0 * b;
