@@ -320,14 +320,16 @@ int mgwr_batch_destroy(mgwr_batch_t b);
  * 0 = narrow (64x16 tiles), 1 = wide 128x64, 2 = wide 256x64, 3 = split-BF16
  * 256x128, 4 = FFT route (all passes of one product); mode 0 = FP64, 1 = FP32,
  * 2 = split-BF16; epilogue 0 = store (residual product, D&C base block in
- * FP64), 1 = colour scatter (smoother, whole line solve), 2 = colour
- * scatter-add (smoother, history part), 3 = subtract (D&C history update),
- * 4 = add (D&C base block, history part), 5 = colour scatter of the diagonal
- * term plus the history part (smoother, FFT route), 6 = residual (FFT route:
- * the stencil part minus the product, written as the residual), 7 = the
- * same for a double-double iterate, 8 = the residual at one colour's points
- * (inner cycles of the refinement after pre-smoothing), 9 = the same in 1D
- * with colour 0 first, written restricted to the coarse grid.
+ * FP64, FP64 smoother on a level stored split by colour), 1 = colour scatter
+ * (FP64 smoother, whole line solve, level in natural order), 3 = subtract
+ * (D&C history update), 4 = add (D&C base block, or the history part of a
+ * split level's smoother), 6 = residual (FFT route: the stencil part minus
+ * the product, written as the residual), 7 = the same for a double-double
+ * iterate, 8 = the residual at one colour's points (inner cycles of the
+ * refinement after pre-smoothing), 9 = the same in 1D with colour 0 first,
+ * written restricted to the coarse grid, 10 = the diagonal term plus the
+ * history part into a split level's colour points (smoother, FP32 FFT
+ * route).
  * A record covers one launch, possibly over several products (of several
  * problems): M and K are the largest of them, P the sum of their columns,
  * and flops, bytes and pass_bytes sums of per-product values.  ms covers

@@ -6,13 +6,14 @@ split BF16 (the diagonal term, the stencils and every grid function stay
 FP64).  ``mgwr_smooth`` and ``mgwr_vcycle`` run in the handle's precision,
 so one smoothing step and one cycle are compared here point by point with
 the oracle's FP64 half-sweep (Section 3, eq. red-black; Section 6, eq.
-red-black_2d) and cycle (Algorithm 1).  Covered: the FFT route's colour
-panel and merge epilogues (1D, first colour stored contiguously, second
-colour merged into whole rows), its scatter of the diagonal term (2D), its
-one-colour and restricted residuals (cycles with pre-smoothing), the dense
-FP32 and split-BF16 scatter-add epilogues (``fft=0``), transform lengths
-below and above 512 (register and LDS passes), both colour orders (in 1D
-the two colours have an odd and an even number of points), ragged M.
+red-black_2d) and cycle (Algorithm 1).  The cycle's hierarchy is stored
+split by colour, so covered are: the FFT route's epilogue writing the
+diagonal term plus the history part into a colour's contiguous points (1D
+and 2D), its one-colour and restricted residuals and the residual implied
+by the sweep (cycles with pre-smoothing), the dense FP32 and split-BF16
+epilogues adding the history part (``fft=0``), transform lengths below and
+above 512 (register and LDS passes), both colour orders (in 1D the two
+colours have an odd and an even number of points), ragged M.
 
 Tolerances come from the unit roundoff u of the low precision and the
 history share of the line solve.  With lambda the first column of
