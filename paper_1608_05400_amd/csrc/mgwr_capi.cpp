@@ -468,13 +468,9 @@ double product_bytes(const GemmArgs &a)
     case EPI_RESID_DD: case EPI_RESID_C: case EPI_RESID_R: out = 24.0; break;
     default: out = 16.0; break;                               // read-modify-write, b + x
     }
-    if (a.ea.rhs) {
-        // the right-hand sides computed where they are read: F and the
-        // other colour's values (about one per point) instead of a panel,
-        // in the first pass and again for the diagonal term
-        in = 16.0;
-        if (a.epi == EPI_STORE_DIAG) out = 24.0;
-    }
+    // the right-hand sides computed where the first pass reads them: F and
+    // the other colour's values (about one per point) instead of a panel
+    if (a.ea.rhs) in = 16.0;
     return (double)a.K * a.P * in + (double)a.M * a.P * out;
 }
 
@@ -904,8 +900,10 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
                 // FP64 route: the passes compute the right-hand sides where
                 // they read them (F and the other colour's values instead of
                 // a panel: 9 % less time per FP64-refinement step on the 1D
-                // N = 4095, M = 16384 problems; the FP32 passes, with twice
-                // the columns per block, became bound by those loads' latency)
+                // N = 4095, M = 16384 problems).  Not on the FP32 route, whose
+                // last pass needs b again for the diagonal term: computing it
+                // there too measured 6 % slower per step (83.0 -> 88.0 ms),
+                // with 16 column pairs per block in the first pass
                 a.B = t.H->f[t.lev] + off; a.ldb = L.P;
                 a.ea.rhs = 1;
                 a.ea.F = t.H->f[t.lev] + off; a.ea.U = t.H->u[t.lev]; a.ea.ldu = L.P;

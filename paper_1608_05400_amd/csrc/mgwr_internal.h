@@ -85,11 +85,11 @@ struct EpiArgs {
     // EPI_RESID*: storage order (lay_pos) of F, U, lo (and of the product's
     // columns) and of out; EPI_RESID_R: of the coarse level written
     int lay_in = 0, lay_out = 0;
-    // Smoother products of a split level on the FFT route: the operand (and
-    // EPI_STORE_DIAG's right-hand side) is not stored but computed where it
-    // is read, b = F + ih2 (neighbour sum) + cd g, from F (its first point
-    // the colour's first, rows ldu apart) and the level's iterate U (the
-    // other colour's values; rows ldu apart), g in natural order
+    // FP64 smoother products of a split level on the FFT route: the operand
+    // is not stored but computed where the first pass reads it,
+    // b = F + ih2 (neighbour sum) + cd g, from F (its first point the
+    // colour's first, rows ldu apart) and the level's iterate U (the other
+    // colour's values; rows ldu apart), g in natural order
     int rhs = 0;
     // FP64 residual on the FFT route (EPI_RESID, EPI_RESID_DD) in one chunk
     // of radix-256 passes: norm_part != nullptr: the last pass writes each
