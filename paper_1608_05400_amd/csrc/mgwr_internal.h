@@ -179,6 +179,41 @@ __host__ __device__ inline int lay_pos(int dims, int n, int split, int p)
     const int before = (y & 1) ? (c == 0 ? (n + 1) / 2 : n / 2) : 0;
     return (c == 0 ? 0 : colour_count(2, n, 0)) + (y >> 1) * n + before + (x >> 1);
 }
+// 2D forms that avoid divisions by n in the hot kernels: the j-th point of
+// a colour as (x, y) (one division), the storage index of (x, y) (none) and
+// the natural (x, y) of storage index s (one division).
+__host__ __device__ inline void colour_xy(int n, int colour, int j, int &x, int &y)
+{
+    const int a = (colour == 0) ? (n + 1) / 2 : n / 2;
+    const int q = j / n;
+    int r = j - q * n;
+    if (r < a) {
+        y = 2 * q;
+        x = (colour == 0) ? 2 * r : 2 * r + 1;
+    } else {
+        r -= a;
+        y = 2 * q + 1;
+        x = (colour == 0) ? 2 * r + 1 : 2 * r;
+    }
+}
+__host__ __device__ inline int lay_pos_xy(int n, int split, int x, int y)
+{
+    if (!split) return y * n + x;
+    const int c = (x + y) & 1;
+    const int before = (y & 1) ? (c == 0 ? (n + 1) / 2 : n / 2) : 0;
+    return (c == 0 ? 0 : (int)(((long)n * n + 1) / 2)) + (y >> 1) * n + before + (x >> 1);
+}
+__host__ __device__ inline void lay_xy(int n, int split, int s, int &x, int &y)
+{
+    if (!split) {
+        y = s / n;
+        x = s - y * n;
+        return;
+    }
+    const int p0 = (int)(((long)n * n + 1) / 2);
+    if (s < p0) colour_xy(n, 0, s, x, y);
+    else colour_xy(n, 1, s - p0, x, y);
+}
 // Natural point of storage index s:
 __host__ __device__ inline int lay_nat(int dims, int n, int split, int s)
 {

@@ -66,21 +66,40 @@ __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b <<
 // p is the natural index of the point; the row is stored in the order
 // `split` (lay_pos).
 template <typename Ptr>
-__device__ inline void nbr_vals(Ptr U, int dims, int n, int p, double (&v)[4], int split = 0)
+__device__ inline void nbr_vals_xy(Ptr U, int n, int x, int y, double (&v)[4], int split)
 {
-    // a 1D row is an n x 1 grid: its y-neighbours are outside
-    const int ny = dims == 1 ? 1 : n;
-    const int y = dims == 1 ? 0 : p / n, x = p - y * n;
-    v[0] = (double)U[lay_pos(dims, n, split, x > 0 ? p - 1 : p)];
-    v[1] = (double)U[lay_pos(dims, n, split, x < n - 1 ? p + 1 : p)];
-    v[2] = (double)U[lay_pos(dims, n, split, y > 0 ? p - n : p)];
-    v[3] = (double)U[lay_pos(dims, n, split, y < ny - 1 ? p + n : p)];
+    v[0] = (double)U[lay_pos_xy(n, split, x > 0 ? x - 1 : x, y)];
+    v[1] = (double)U[lay_pos_xy(n, split, x < n - 1 ? x + 1 : x, y)];
+    v[2] = (double)U[lay_pos_xy(n, split, x, y > 0 ? y - 1 : y)];
+    v[3] = (double)U[lay_pos_xy(n, split, x, y < n - 1 ? y + 1 : y)];
     if (x == 0) v[0] = 0.0;
     if (x == n - 1) v[1] = 0.0;
     if (y == 0) v[2] = 0.0;
-    if (y == ny - 1) v[3] = 0.0;
+    if (y == n - 1) v[3] = 0.0;
+}
+template <typename Ptr>
+__device__ inline void nbr_vals(Ptr U, int dims, int n, int p, double (&v)[4], int split = 0)
+{
+    if (dims == 2) {
+        const int y = p / n;
+        nbr_vals_xy(U, n, p - y * n, y, v, split);
+        return;
+    }
+    // a 1D row is an n x 1 grid: its y-neighbours are outside
+    v[0] = (double)U[lay_pos(1, n, split, p > 0 ? p - 1 : p)];
+    v[1] = (double)U[lay_pos(1, n, split, p < n - 1 ? p + 1 : p)];
+    v[2] = v[3] = 0.0;
+    if (p == 0) v[0] = 0.0;
+    if (p == n - 1) v[1] = 0.0;
 }
 
+template <typename Ptr>
+__device__ inline double nbr_sum_xy(Ptr U, int n, int x, int y, int split)
+{
+    double v[4];
+    nbr_vals_xy(U, n, x, y, v, split);
+    return ((v[0] + v[1]) + v[2]) + v[3];
+}
 template <typename Ptr>
 __device__ inline double nbr_sum(Ptr U, int dims, int n, int p, int split = 0)
 {
@@ -99,15 +118,11 @@ __device__ inline void two_sum(double a, double b, double &s, double &e)
 // A_h (hi + lo) at point p as an unevaluated sum (shi + slo) / h^2:
 // shi + slo = 2 d hi_p - sum(neighbours of hi) + (same stencil of lo),
 // the hi part without rounding error (error-free transformations).
-template <typename Ptr>
-__device__ inline void stencil_dd(Ptr H, Ptr Lo, int dims, int n, int p, double &shi, double &slo, int split = 0)
+__device__ inline void stencil_dd_vals(double hc, double lc, const double (&h)[4], const double (&l)[4], double d,
+                                       double &shi, double &slo)
 {
-    double h[4], l[4];
-    nbr_vals(H, dims, n, p, h, split);
-    nbr_vals(Lo, dims, n, p, l, split);
-    const int sp = lay_pos(dims, n, split, p);
-    double s = (dims == 1 ? 2.0 : 4.0) * H[sp], e, acc = 0.0;
-    double lo = (dims == 1 ? 2.0 : 4.0) * Lo[sp];
+    double s = d * hc, e, acc = 0.0;
+    double lo = d * lc;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {   // a zero neighbour leaves s exact and adds nothing
         two_sum(s, -h[k], s, e);
@@ -116,6 +131,32 @@ __device__ inline void stencil_dd(Ptr H, Ptr Lo, int dims, int n, int p, double 
     }
     shi = s;
     slo = acc + lo;
+}
+template <typename Ptr>
+__device__ inline void stencil_dd(Ptr H, Ptr Lo, int dims, int n, int p, double &shi, double &slo, int split = 0)
+{
+    double h[4], l[4];
+    int sp;
+    if (dims == 2) {
+        const int y = p / n, x = p - y * n;
+        nbr_vals_xy(H, n, x, y, h, split);
+        nbr_vals_xy(Lo, n, x, y, l, split);
+        sp = lay_pos_xy(n, split, x, y);
+    } else {
+        nbr_vals(H, 1, n, p, h, split);
+        nbr_vals(Lo, 1, n, p, l, split);
+        sp = lay_pos(1, n, split, p);
+    }
+    stencil_dd_vals(H[sp], Lo[sp], h, l, dims == 1 ? 2.0 : 4.0, shi, slo);
+}
+// The same at the 2D point (x, y) stored at sp.
+template <typename Ptr>
+__device__ inline void stencil_dd_xy(Ptr H, Ptr Lo, int n, int x, int y, int sp, double &shi, double &slo, int split)
+{
+    double h[4], l[4];
+    nbr_vals_xy(H, n, x, y, h, split);
+    nbr_vals_xy(Lo, n, x, y, l, split);
+    stencil_dd_vals(H[sp], Lo[sp], h, l, 4.0, shi, slo);
 }
 
 // Right-hand side of the smoother (Section 3, eq. red-black; Section 6, eq.
@@ -140,7 +181,9 @@ __device__ inline double rhs_val(const EpiArgs &e, int i, int j)
         if (jr < 0 || jr >= po) vr = 0.0;
         ns = vl + vr;
     } else {
-        ns = nbr_sum(Uk, 2, e.n, colour_point(2, e.n, e.colour, j), 1);
+        int x, y;
+        colour_xy(e.n, e.colour, j, x, y);
+        ns = nbr_sum_xy(Uk, e.n, x, y, 1);
     }
     b += ns * e.ih2;
     if (e.g) b += gview<double>(e.cd)[i] * gview<double>(e.g)[colour_point(e.dims, e.n, e.colour, j)];
@@ -776,8 +819,8 @@ __global__ __launch_bounds__(256) void k_toep_bf16x3(KGrp grp)
                 }
         return;
     }
-    // one row block at a time, loads before stores (see k_toep_wide)
     GLOBAL double *out = gview_rw<double>(kp.ea.out);
+    const long ldo = kp.ea.ldo;
     long col[4];
     bool cok[4];
 #pragma unroll
@@ -785,6 +828,38 @@ __global__ __launch_bounds__(256) void k_toep_bf16x3(KGrp grp)
         cok[b] = pl + 16 * b < kp.P;
         col[b] = cok[b] ? epi_col<EPI>(kp.ea, pl + 16 * b) : 0;
     }
+    // A wave whose 128 x 64 tile lies inside the product (every tile but the
+    // last column strip's and a ragged M's) writes it without per-element
+    // predicates, its loads of the old values (read-modify-write epilogues)
+    // one row block ahead of the stores: predicated accesses split the
+    // epilogue into branches whose stores the compiler waits for one by one,
+    // and at one wave per SIMD that idles the matrix cores.
+    const bool inner = __builtin_amdgcn_readfirstlane((int)(iw + 128 <= kp.M && p0 + wn * 64 + 64 <= kp.P));
+    if (inner) {
+        GLOBAL double *ob = out + (long)(iw + 4 * (lane >> 4)) * ldo;
+        double prev[2][4][4];
+        auto load_rows = [&](int a, double (&pv)[4][4]) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pv[b][v] = ob[(long)(16 * a + v) * ldo + col[b]];
+        };
+        if constexpr (epi_reads<EPI>()) load_rows(0, prev[0]);
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            if constexpr (epi_reads<EPI>())
+                if (a + 1 < 8) load_rows(a + 1, prev[(a + 1) & 1]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double pv = epi_reads<EPI>() ? prev[a & 1][b][v] : 0.0;
+                    ob[(long)(16 * a + v) * ldo + col[b]] = epi_combine<EPI>(pv, (double)acc[a][b][v]);
+                }
+        }
+        return;
+    }
+    // edge tiles: one row block at a time, its loads before its stores
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
         double prev[4][4];
@@ -795,7 +870,7 @@ __global__ __launch_bounds__(256) void k_toep_bf16x3(KGrp grp)
                 const int i = iw + 16 * a + 4 * (lane >> 4) + v;
                 prev[b][v] = 0.0;
                 if constexpr (epi_reads<EPI>())
-                    if (cok[b] && i < kp.M) prev[b][v] = out[(long)i * kp.ea.ldo + col[b]];
+                    if (cok[b] && i < kp.M) prev[b][v] = out[(long)i * ldo + col[b]];
             }
 #pragma unroll
         for (int b = 0; b < 4; ++b)
@@ -803,7 +878,7 @@ __global__ __launch_bounds__(256) void k_toep_bf16x3(KGrp grp)
             for (int v = 0; v < 4; ++v) {
                 const int i = iw + 16 * a + 4 * (lane >> 4) + v;
                 if (cok[b] && i < kp.M)
-                    out[(long)i * kp.ea.ldo + col[b]] = epi_combine<EPI>(prev[b][v], (double)acc[a][b][v]);
+                    out[(long)i * ldo + col[b]] = epi_combine<EPI>(prev[b][v], (double)acc[a][b][v]);
             }
     }
 }
@@ -852,6 +927,37 @@ __device__ inline void grp_select(const Grp<A> &g, A &a, long &lb, long &nb)
 constexpr int kThreads = 256;
 #define GRID_STRIDE(e, total) \
     for (long e = lb * kThreads + threadIdx.x; e < (total); e += nb * kThreads)
+
+// The same walk over the (row, column) pairs (k, s) of rows of P elements,
+// without a 64-bit division per element: the stride is split once into whole
+// rows and a remainder.
+struct KsWalk {
+    long k, dk;
+    int s, ds, P;
+    __device__ KsWalk(long lb, long nb, int P_) : P(P_)
+    {
+        if (P <= 0) {   // empty rows: no pair (k never below a row count)
+            k = 0x7fffffffffffffffL;
+            dk = 0;
+            s = ds = 0;
+            return;
+        }
+        const long e = lb * kThreads + threadIdx.x, st = nb * kThreads;
+        k = e / P;
+        s = (int)(e - k * P);
+        dk = st / P;
+        ds = (int)(st - dk * P);
+    }
+    __device__ void next()
+    {
+        s += ds;
+        k += dk;
+        if (s >= P) {
+            s -= P;
+            ++k;
+        }
+    }
+};
 
 template <class Op>
 __global__ __launch_bounds__(kThreads) void k_group(Grp<typename Op::A> g)
@@ -1962,12 +2068,20 @@ template <typename S> struct OpRhsPanel {
         GLOBAL S *panel = gview_rw<S>(a.panel);
         const GLOBAL double *F = gview<double>(a.F), *cd = gview<double>(a.cd), *g = gview<double>(a.g);
         GLOBAL double *U = gview_rw<double>(a.U);
-        GRID_STRIDE(e, (long)a.M * Pc) {
-            int k = (int)(e / Pc), j = (int)(e - (long)k * Pc);
-            int pt = colour_point(a.dims, a.n, a.colour, j);             // natural
-            int sp = lay_cpos(a.dims, a.n, a.split, a.colour, j);        // stored at
-            GLOBAL double *Uk = U + (long)k * P;
-            double b = F[(long)k * P + sp] + nbr_sum(Uk, a.dims, a.n, pt, a.split) * a.ih2;
+        for (KsWalk w(lb, nb, Pc); w.k < a.M; w.next()) {
+            const long k = w.k;
+            const int j = w.s;
+            int x = 0, y = 0, pt;   // natural index pt (x + n y in 2D)
+            if (a.dims == 2) {
+                colour_xy(a.n, a.colour, j, x, y);
+                pt = y * a.n + x;
+            } else {
+                pt = colour_point(1, a.n, a.colour, j);
+            }
+            const int sp = a.split ? lay_cpos(a.dims, a.n, 1, a.colour, j) : pt;   // stored at
+            GLOBAL double *Uk = U + k * P;
+            const double ns = (a.dims == 2) ? nbr_sum_xy(Uk, a.n, x, y, a.split) : nbr_sum(Uk, 1, a.n, pt, a.split);
+            double b = F[k * P + sp] + ns * a.ih2;
             if (a.g) b += cd[k] * g[pt];
             panel[(long)k * a.ldp + j] = (S)b;
             if (a.lam0 != 0.0) Uk[sp] = a.lam0 * b;
@@ -2004,18 +2118,29 @@ struct OpRhsPacked {
         const long P = (a.dims == 1) ? a.n : (long)a.n * a.n;
         const GLOBAL double *F = gview<double>(a.F), *cd = gview<double>(a.cd), *g = gview<double>(a.g);
         GLOBAL double *U = gview_rw<double>(a.U);
-        GRID_STRIDE(e, (long)(a.Mpad / 8) * a.ldp) {
-            int kg = (int)(e / a.ldp), j = (int)(e - (long)kg * a.ldp);
+        for (KsWalk w(lb, nb, (int)a.ldp); w.k < a.Mpad / 8; w.next()) {
+            const int kg = (int)w.k, j = w.s;
+            const long e = w.k * a.ldp + j;
             float b8[8];
-            int pt = (j < Pc) ? colour_point(a.dims, a.n, a.colour, j) : 0;
-            int sp = (j < Pc) ? lay_cpos(a.dims, a.n, a.split, a.colour, j) : 0;
+            // the point: natural index pt (x + n y in 2D), storage index sp
+            int x = 0, y = 0, pt = 0, sp = 0;
+            if (j < Pc) {
+                if (a.dims == 2) {
+                    colour_xy(a.n, a.colour, j, x, y);
+                    pt = y * a.n + x;
+                } else {
+                    pt = colour_point(1, a.n, a.colour, j);
+                }
+                sp = a.split ? lay_cpos(a.dims, a.n, 1, a.colour, j) : pt;
+            }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 int k = kg * 8 + q;
                 double b = 0.0;
                 if (k < a.M && j < Pc) {
                     GLOBAL double *Uk = U + (long)k * P;
-                    b = F[(long)k * P + sp] + nbr_sum(Uk, a.dims, a.n, pt, a.split) * a.ih2;
+                    const double ns = (a.dims == 2) ? nbr_sum_xy(Uk, a.n, x, y, a.split) : nbr_sum(Uk, 1, a.n, pt, a.split);
+                    b = F[(long)k * P + sp] + ns * a.ih2;
                     if (a.g) b += cd[k] * g[pt];
                     if (a.lam0 != 0.0) Uk[sp] = a.lam0 * b;
                 }
@@ -2034,15 +2159,19 @@ struct OpPost {
     using A = PostArgs;
     __device__ static void run(const PostArgs &a, long lb, long nb)
     {
-        const long P = (a.dims == 1) ? a.n : (long)a.n * a.n;
+        const int n = a.n, P = (a.dims == 1) ? n : n * n;
         const GLOBAL double *F = gview<double>(a.F), *U = gview<double>(a.U), *lo = gview<double>(a.lo);
         const GLOBAL double *cd = gview<double>(a.cd), *g = gview<double>(a.g);
         GLOBAL double *out = gview_rw<double>(a.out);
         const GLOBAL double *prod = a.prod ? gview<double>(a.prod) : out;
-        GRID_STRIDE(e, (long)a.M * P) {
-            // s: storage index (order lay_in), p: the natural point
-            int k = (int)(e / P), s = (int)(e - (long)k * P);
-            const int p = lay_nat(a.dims, a.n, a.lay_in, s);
+        for (KsWalk w(lb, nb, P); w.k < a.M; w.next()) {
+            // s: storage index (order lay_in), p = x + n y: the natural point
+            const int k = (int)w.k, s = w.s;
+            const long e = (long)k * P + s;
+            int x, y;
+            if (a.dims == 2) lay_xy(n, a.lay_in, s, x, y);
+            else x = lay_nat(1, n, a.lay_in, s), y = 0;
+            const int p = y * n + x;
             const GLOBAL double *Uk = U + (long)k * P;
             double rhs = F[e];
             if (a.g) rhs += cd[k] * g[p];
@@ -2050,13 +2179,17 @@ struct OpPost {
             double r;
             if (a.lo) {
                 double shi, slo;
-                stencil_dd(Uk, lo + (long)k * P, a.dims, a.n, p, shi, slo, a.lay_in);
+                if (a.dims == 2) stencil_dd_xy(Uk, lo + (long)k * P, n, x, y, s, shi, slo, a.lay_in);
+                else stencil_dd(Uk, lo + (long)k * P, 1, n, p, shi, slo, a.lay_in);
                 r = (rhs - shi * a.ih2) - slo * a.ih2;
             } else {
-                double st = (a.dims == 1 ? 2.0 : 4.0) * Uk[s] - nbr_sum(Uk, a.dims, a.n, p, a.lay_in);
+                const double ns = (a.dims == 2) ? nbr_sum_xy(Uk, n, x, y, a.lay_in) : nbr_sum(Uk, 1, n, p, a.lay_in);
+                double st = (a.dims == 1 ? 2.0 : 4.0) * Uk[s] - ns;
                 r = rhs - st * a.ih2;
             }
-            const long o = (a.lay_out == a.lay_in) ? e : (long)k * P + lay_pos(a.dims, a.n, a.lay_out, p);
+            const long o = (a.lay_out == a.lay_in)
+                               ? e
+                               : (long)k * P + (a.dims == 2 ? lay_pos_xy(n, a.lay_out, x, y) : lay_pos(1, n, a.lay_out, p));
             out[o] = r - prod[e];
         }
     }
@@ -2116,20 +2249,20 @@ struct OpXfer {
     __device__ static void restrict_fw(const XferArgs &a, long lb, long nb)
     {
         const int nf = a.n, nc = (nf - 1) / 2;
-        const long Pc = (a.dims == 1) ? nc : (long)nc * nc;
+        const int Pc = (a.dims == 1) ? nc : nc * nc;
         const long Pf = (a.dims == 1) ? nf : (long)nf * nf;
         const int sp = a.split;
-        GRID_STRIDE(e, (long)a.M * Pc) {
-            int k = (int)(e / Pc);
-            // q: natural index of the coarse point stored at e (both levels in
-            // the order `split`)
-            const int q = lay_nat(a.dims, nc, sp, (int)(e - (long)k * Pc));
-            const GLOBAL double *r = gview<double>(a.src) + (long)k * Pf;
+        for (KsWalk w(lb, nb, Pc); w.k < a.M; w.next()) {
+            const long e = w.k * Pc + w.s;
+            const GLOBAL double *r = gview<double>(a.src) + w.k * Pf;
             // the coarse point is a colour-0 point of the fine grid, its
             // edge neighbours colour 1, its corners (2D) colour 0; with
             // zero_colour set, that colour's entries are zero and not read
             double v;
             if (a.dims == 1) {
+                // q: natural index of the coarse point stored at s (both
+                // levels in the order `split`)
+                const int q = lay_nat(1, nc, sp, w.s);
                 int x = 2 * q + 1;
                 auto R = [&](int xx) {
                     return a.implicit ? a.ih2 * nbr_sum(r, 1, nf, xx, sp) : r[lay_pos(1, nf, sp, xx)];
@@ -2138,11 +2271,11 @@ struct OpXfer {
                 else if (a.zero_colour == 0) v = 0.25 * (R(x - 1) + R(x + 1));
                 else v = 0.25 * (R(x - 1) + 2.0 * R(x) + R(x + 1));
             } else {
-                int I = q % nc, J = q / nc;
+                int I, J;
+                lay_xy(nc, sp, w.s, I, J);
                 int x = 2 * I + 1, y = 2 * J + 1;
                 auto R = [&](int yy, int xx) {
-                    return a.implicit ? a.ih2 * nbr_sum(r, 2, nf, yy * nf + xx, sp)
-                                      : r[lay_pos(2, nf, sp, yy * nf + xx)];
+                    return a.implicit ? a.ih2 * nbr_sum_xy(r, nf, xx, yy, sp) : r[lay_pos_xy(nf, sp, xx, yy)];
                 };
                 if (a.zero_colour == 1)
                     v = (R(y - 1, x - 1) + R(y - 1, x + 1) + 2.0 * (2.0 * R(y, x)) + R(y + 1, x - 1) + R(y + 1, x + 1))
@@ -2165,25 +2298,27 @@ struct OpXfer {
         const int sp = a.split;
         // with skip_colour, the points of the other colour only
         const int oc = 1 - a.skip_colour;
-        const long Pw = a.skip_colour >= 0 ? colour_count(a.dims, nf, oc) : Pf;
-        GRID_STRIDE(w, (long)a.M * Pw) {
-            int k = (int)(w / Pw);
-            const int jw = (int)(w - (long)k * Pw);
-            // e: storage index of the fine point, p: its natural index
-            const long e = (long)k * Pf + (a.skip_colour >= 0 ? lay_cpos(a.dims, nf, sp, oc, jw) : jw);
-            const int p = a.skip_colour >= 0 ? colour_point(a.dims, nf, oc, jw) : lay_nat(a.dims, nf, sp, jw);
-            const GLOBAL double *c = gview<double>(a.src) + (long)k * Pc;
+        const int Pw = a.skip_colour >= 0 ? colour_count(a.dims, nf, oc) : (int)Pf;
+        for (KsWalk w(lb, nb, Pw); w.k < a.M; w.next()) {
+            const int jw = w.s;
+            const GLOBAL double *c = gview<double>(a.src) + w.k * Pc;
             double v;
+            long e;   // storage index of the fine point
             if (a.dims == 1) {
+                e = w.k * Pf + (a.skip_colour >= 0 ? lay_cpos(1, nf, sp, oc, jw) : jw);
+                const int p = a.skip_colour >= 0 ? colour_point(1, nf, oc, jw) : lay_nat(1, nf, sp, jw);
                 int nn = p + 1;   // paper numbering
                 auto at = [&](int X) -> double { return (X >= 1 && X <= nc) ? c[lay_pos(1, nc, sp, X - 1)] : 0.0; };
                 v = 0.5 * (at(nn / 2) + at((nn + 1) / 2));
             } else {
-                int nn = p % nf + 1, ll = p / nf + 1;
+                int x, y;   // the fine point
+                if (a.skip_colour >= 0) colour_xy(nf, oc, jw, x, y);
+                else lay_xy(nf, sp, jw, x, y);
+                e = w.k * Pf + lay_pos_xy(nf, sp, x, y);
+                int nn = x + 1, ll = y + 1;
                 int xa = nn / 2, xb = (nn + 1) / 2, ya = ll / 2, yb = (ll + 1) / 2;
                 auto at = [&](int X, int Y) -> double {
-                    return (X >= 1 && X <= nc && Y >= 1 && Y <= nc) ? c[lay_pos(2, nc, sp, (Y - 1) * nc + (X - 1))]
-                                                                    : 0.0;
+                    return (X >= 1 && X <= nc && Y >= 1 && Y <= nc) ? c[lay_pos_xy(nc, sp, X - 1, Y - 1)] : 0.0;
                 };
                 v = 0.25 * (at(xa, ya) + at(xb, ya) + at(xa, yb) + at(xb, yb));
             }
