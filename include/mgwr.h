@@ -318,7 +318,8 @@ int mgwr_batch_destroy(mgwr_batch_t b);
  * its launches one by one instead of replaying graphs.  kernel identifies
  * the kernel instantiation: (kind << 8) | (mode << 4) | epilogue, with kind
  * 0 = narrow (64x16 tiles), 1 = wide 128x64, 2 = wide 256x64, 3 = split-BF16
- * 256x128, 4 = FFT route (all passes of one product); mode 0 = FP64, 1 = FP32,
+ * 256x128, 4 = FFT route (all passes of one product), 5 = FFT route with
+ * the whole product in one kernel (FP64, M <= 2048); mode 0 = FP64, 1 = FP32,
  * 2 = split-BF16; epilogue 0 = store (residual product, D&C base block in
  * FP64, FP64 smoother on a level stored split by colour), 1 = colour scatter
  * (FP64 smoother, whole line solve, level in natural order), 3 = subtract

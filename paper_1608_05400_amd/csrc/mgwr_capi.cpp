@@ -475,10 +475,11 @@ double product_bytes(const GemmArgs &a)
 }
 
 // Kernel id of a product: (kind << 8) | (mode << 4) | epilogue, kind 0 =
-// narrow, 1 = wide 128 x 64, 2 = wide 256 x 64, 3 = split-BF16.
+// narrow, 1 = wide 128 x 64, 2 = wide 256 x 64, 3 = split-BF16, 4 = FFT
+// route (passes), 5 = FFT route on chip.
 int kernel_id(const GemmArgs &a)
 {
-    const int kind = a.fft_spec ? 4 : product_kernel_kind(a.mode, a.M, a.P, a.knobs);
+    const int kind = a.fft_spec ? (fft_on_chip(a) ? 5 : 4) : product_kernel_kind(a.mode, a.M, a.P, a.knobs);
     return (kind << 8) | (a.mode << 4) | a.epi;
 }
 
@@ -2428,6 +2429,7 @@ const char *mgwr_kernel_name(int kernel)
     case 1: name = "k_toep_wide<" + m + ", " + e + ", 0>"; break;
     case 2: name = "k_toep_wide<" + m + ", " + e + ", 1>"; break;
     case 4: name = std::string(mode == 0 ? "k_fft_pass<double> (FFT route, epilogue " : "k_fft_pass<float> (FFT route, epilogue ") + e + ")"; break;
+    case 5: name = "k_fft_chip<double> (FFT route on chip, epilogue " + e + ")"; break;
     default: name = "k_toep_bf16x3<" + e + ">"; break;
     }
     return name.c_str();

@@ -366,6 +366,9 @@ hipError_t launch_permute(const std::vector<PermuteArgs> &v, Staging *st, hipStr
 // one product (written by the first kernel, read and written by each middle
 // one, read by the last).
 double fft_work_bytes(const GemmArgs &a);
+// Whether an FFT-route product runs as one on-chip kernel (FP64, L <= 4096,
+// plain input, store or scatter epilogue).
+bool fft_on_chip(const GemmArgs &a);
 // Blocks of the last pass of an FP64 FFT-route product whose columns fit its
 // work arrays in one chunk and whose transform uses the radix-256 passes
 // (the residual products that can write norm partials); 0 for any other.

@@ -1391,11 +1391,15 @@ __device__ inline void dft_reg(typename Cx<T>::v (&v)[R])
     for (int m = 2; m <= R; m <<= 1) {
 #pragma unroll
         for (int t = 0; t < m / 2; ++t) {
-            // exp(SIGN 2 pi i t / m)
-            C w = C{(T)kTw32.c[t * (32 / m)], (T)(SIGN * kTw32.s[t * (32 / m)])};
+            // exp(SIGN 2 pi i t / m); the twiddles 1 and SIGN i (t = 0 and
+            // t = m / 4) as a copy and a swap, not as products with zeros
+            const int tq = t * (32 / m);
+            C w = C{(T)kTw32.c[tq], (T)(SIGN * kTw32.s[tq])};
 #pragma unroll
             for (int k = 0; k < R; k += m) {
-                const C a = v[k + t], b = cmul(v[k + t + m / 2], w);
+                const C x = v[k + t + m / 2];
+                const C b = (tq == 0) ? x : (tq == 8) ? C{(T)(-SIGN) * x.y, (T)SIGN * x.x} : cmul(x, w);
+                const C a = v[k + t];
                 v[k + t] = a + b;
                 v[k + t + m / 2] = a - b;
             }
@@ -1852,8 +1856,191 @@ static std::vector<int> fft_plan(int L)
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// FFT route with the whole product on chip (FP64, transform lengths
+// L = 256 R3, R3 in {4, 8, 16}, i.e. M <= 2048): one block of T = L / 16
+// threads per column pair, thread j holding the 16 points j + T s of the
+// sequence in registers.  Each transform is three Stockham stages (radix 16,
+// 16 and R3; the last one as 16 / R3 DFTs per thread) with LDS exchanges
+// between them.  The forward transform's last stage leaves thread j the
+// spectrum points j + T s, exactly the points the inverse transform's first
+// stage reads, so the product with the coefficient spectrum stays in
+// registers, and the inverse transform's last stage leaves the outputs
+// j + T s, those below M going to the epilogue.  Global traffic is the
+// operand read once and the result written once (the pass route also writes
+// and reads two complex work arrays).  Blocks go to the 8 XCDs in turn, so
+// block b takes pair (b mod 8) nb / 8 + b / 8: the blocks of one XCD take
+// consecutive pairs, whose 16-byte row segments share cache lines in its L2.
+constexpr int kChipMaxLg = 12;
+// two adjacent doubles, 8-byte aligned (one 16-byte access)
+typedef double D2u __attribute__((ext_vector_type(2), aligned(8)));
+__device__ inline int chip_pad(int i) { return i + (i >> 4); }   // LDS index (bank spread)
+
+template <int LG, int SIGN>
+__device__ inline void chip_transform(Cx<double>::v (&v)[16], Cx<double>::v *X, const Cx<double>::v *Wlo,
+                                      const Cx<double>::v *Whi)
+{
+    using C = Cx<double>::v;
+    constexpr int L = 1 << LG, T = L / 16, R3 = L / 256, NB = 16 / R3;
+    const int j = threadIdx.x;
+    // w^m for m < L (conjugated for the inverse)
+    auto tw = [&](int m) {
+        C w = cmul(Wlo[m & 63], Whi[m >> 6]);
+        if (SIGN > 0) w.y = -w.y;
+        return w;
+    };
+    // stage 1 (sub-transforms of length 1 -> 16): the input points j + T r
+    dft_reg<double, 16, SIGN>(v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) X[chip_pad(16 * j + r)] = v[r];
+    __syncthreads();
+    // stage 2 (16 -> 256)
+    {
+        const int k = j & 15;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = X[chip_pad(j + T * r)];
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw(R3 * r * k));   // exp(SIGN 2 pi i r k / 256)
+        dft_reg<double, 16, SIGN>(v);
+        __syncthreads();
+        const int base = (j >> 4) * 256 + k;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) X[chip_pad(base + 16 * r)] = v[r];
+        __syncthreads();
+    }
+    // stage 3 (256 -> L): butterflies jj = j + T i; its outputs jj + 256 r
+    // are the points j + T (i + NB r)
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int jj = j + T * i;
+        C u[R3];
+#pragma unroll
+        for (int r = 0; r < R3; ++r) u[r] = X[chip_pad(jj + 256 * r)];
+#pragma unroll
+        for (int r = 1; r < R3; ++r) u[r] = cmul(u[r], tw(r * jj));   // exp(SIGN 2 pi i r jj / L)
+        dft_reg<double, R3, SIGN>(u);
+#pragma unroll
+        for (int r = 0; r < R3; ++r) v[i + NB * r] = u[r];
+    }
+    __syncthreads();   // X is free again
+}
+
+template <int LG, int EPI>
+__global__ __launch_bounds__(256) void k_fft_chip(Grp<FftPass> grp)
+{
+    using C = Cx<double>::v;
+    constexpr int L = 1 << LG, T = L / 16;
+    static_assert(LG >= 10 && LG <= kChipMaxLg, "L = 1024 .. 4096");
+    __shared__ C X[L + L / 16];
+    __shared__ C Wlo[64], Whi[L / 64];
+    FftPass a;
+    long lb, nb;
+    grp_select(grp, a, lb, nb);
+    const int q = (int)((lb & 7) * (nb >> 3) + (lb >> 3));
+    const int c = a.c0 + 2 * q;   // the pair's first product column
+    if (c >= a.P) return;         // (whole block)
+    const int j = threadIdx.x;
+    // w^m = Wlo[m mod 64] Whi[m / 64], w = exp(-2 pi i / L)
+    const GLOBAL C *tw = gview<C>(a.tw);
+    const long st = a.Ltw / L;
+    for (int i = j; i < 64; i += T) Wlo[i] = tw[i * st];
+    for (int i = j; i < L / 64; i += T) Whi[i] = tw[i * 64 * st];
+    // the pair as one complex sequence, zero from row K on
+    const bool two = c + 1 < a.P;
+    const long b0 = fft_bcol(a, c), b1 = two ? fft_bcol(a, c + 1) : b0;
+    const GLOBAL double *B = gview<double>(a.B);
+    // adjacent columns: one 16-byte access per row (8-byte aligned)
+    const bool adj = two && b1 == b0 + 1;
+    C v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int m = j + T * r;
+        C x = C{0.0, 0.0};
+        if (m < a.K) {
+            const GLOBAL double *row = B + (long)m * a.ldb;
+            if (adj) {
+                x = *(const GLOBAL D2u *)(row + b0);
+            } else {
+                x.x = row[b0];
+                if (two) x.y = row[b1];
+            }
+        }
+        v[r] = x;
+    }
+    __syncthreads();   // the twiddle tables
+    chip_transform<LG, -1>(v, X, Wlo, Whi);
+    const GLOBAL C *spec = gview<C>(a.spec);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = cmul(v[r], spec[j + T * r]);
+    chip_transform<LG, 1>(v, X, Wlo, Whi);
+    // epilogue: the outputs j + T r below M, loads before stores
+    double pre[16][2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {   // at clamped indices: no load behind a branch
+        const int m = min(j + T * r, a.M - 1);
+        pre[r][0] = epi_pre<EPI>(a.ea, m, c);
+        pre[r][1] = epi_pre<EPI>(a.ea, m, two ? c + 1 : c);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int m = j + T * r;
+        if (m >= a.M) continue;
+        if (EPI == EPI_STORE && two) {   // the pair's two outputs are adjacent
+            *(GLOBAL D2u *)(gview_rw<double>(a.ea.out) + (long)m * a.ea.ldo + c) = v[r] * a.scale;
+            continue;
+        }
+        epi_put<EPI>(a.ea, m, c, pre[r][0], v[r].x * a.scale);
+        if (two) epi_put<EPI>(a.ea, m, c + 1, pre[r][1], v[r].y * a.scale);
+    }
+}
+
+// Whether an FFT-route product takes the on-chip kernel.
+bool fft_on_chip(const GemmArgs &a)
+{
+    return a.mode == GM_F64 && !a.ea.rhs && (a.epi == EPI_STORE || a.epi == EPI_SCATTER) && a.fft_L >= 1024 &&
+           a.fft_L <= (1 << kChipMaxLg) && (a.fft_L & (a.fft_L - 1)) == 0 && a.K <= a.fft_L / 2 &&
+           a.M <= a.fft_L / 2;
+}
+
+template <int LG, int EPI>
+static hipError_t launch_fft_chip(const std::vector<const GemmArgs *> &as, Staging *st, hipStream_t s)
+{
+    std::vector<FftPass> ps;
+    std::vector<long> blocks;
+    for (const GemmArgs *ap : as) {
+        const GemmArgs &a = *ap;
+        FftPass p{};
+        p.L = a.fft_L; p.Q = (a.P + 1) / 2; p.Ns = 0;
+        p.M = a.M; p.K = a.K; p.P = a.P; p.c0 = 0;
+        p.B = a.B; p.ldb = a.ldb; p.b_colour = a.b_colour;
+        p.spec = a.fft_spec; p.tw = a.fft_tw; p.Ltw = a.fft_Ltw;
+        p.scale = 1.0 / a.fft_L;
+        p.ea = a.ea;
+        ps.push_back(p);
+        blocks.push_back((p.Q + 7) / 8 * 8);   // a multiple of 8: every set starts on XCD 0
+    }
+    return fft_launch(
+        [&](dim3 grid, const Grp<FftPass> &g) { hipLaunchKernelGGL((k_fft_chip<LG, EPI>), grid, dim3(1 << (LG - 4)), 0, s, g); },
+        ps, blocks, st);
+}
+
+static hipError_t launch_fft_chip_all(const std::vector<const GemmArgs *> &as, Staging *st, hipStream_t s)
+{
+    const GemmArgs &a0 = *as[0];
+    const int lg = a0.fft_L == 1024 ? 10 : a0.fft_L == 2048 ? 11 : 12;
+    if (a0.epi == EPI_STORE) {
+        if (lg == 10) return launch_fft_chip<10, EPI_STORE>(as, st, s);
+        if (lg == 11) return launch_fft_chip<11, EPI_STORE>(as, st, s);
+        return launch_fft_chip<12, EPI_STORE>(as, st, s);
+    }
+    if (lg == 10) return launch_fft_chip<10, EPI_SCATTER>(as, st, s);
+    if (lg == 11) return launch_fft_chip<11, EPI_SCATTER>(as, st, s);
+    return launch_fft_chip<12, EPI_SCATTER>(as, st, s);
+}
+
 double fft_work_bytes(const GemmArgs &a)
 {
+    if (fft_on_chip(a)) return 0.0;
     const std::vector<int> plan = fft_plan(a.fft_L);
     // kernels per product: one per pass, the last forward and the first
     // inverse pass fused when the plan ends in radix 256
@@ -2012,9 +2199,14 @@ static hipError_t fft_group(const std::vector<const GemmArgs *> &as, const std::
 static hipError_t launch_toep_fft(const std::vector<const GemmArgs *> &all, Staging *st, hipStream_t s)
 {
     std::vector<std::pair<long, std::vector<const GemmArgs *>>> groups;
+    std::map<int, std::vector<const GemmArgs *>> chip;   // on-chip products by (L, epilogue)
     for (const GemmArgs *a : all) {
         if (a->off != 0 || a->K > a->M || a->fft_L < 2 * a->M || a->fft_L < 64 || a->fft_L > a->fft_Ltw)
             return hipErrorInvalidValue;
+        if (fft_on_chip(*a)) {
+            chip[(a->fft_L << 4) | a->epi].push_back(a);
+            continue;
+        }
         const size_t csz = (a->mode == GM_F64) ? 16 : 8;
         const long qcap = (long)(a->fft_buf_cap / (csz * (size_t)a->fft_L));
         if (qcap < 1) return hipErrorInvalidValue;
@@ -2052,6 +2244,7 @@ static hipError_t launch_toep_fft(const std::vector<const GemmArgs *> &all, Stag
             for (long c = 0; c < a0.P; c += 2 * qcap) RET_IF(run({c}));
         }
     }
+    for (auto &kv : chip) RET_IF(launch_fft_chip_all(kv.second, st, s));
     return hipSuccess;
 }
 
@@ -2418,14 +2611,10 @@ struct OpDD {
     {
         const GLOBAL double *ev = gview<double>(a.e);
         GLOBAL double *hi = gview_rw<double>(a.hi), *lo = gview_rw<double>(a.lo);
-        const long P = a.split ? (a.dims == 1 ? a.npd : (long)a.npd * a.npd) : 1;
-        GRID_STRIDE(i, a.n) {
-            // e in the storage order `split`: the natural point i % P is at
-            // lay_pos of it
-            double d = a.split ? ev[(i / P) * P + lay_pos(a.dims, a.npd, 1, (int)(i % P))] : ev[i];
+        auto add = [&](long i, double d) {
             if (!a.lo) {
                 hi[i] += d;
-                continue;
+                return;
             }
             double s, err;
             two_sum(hi[i], d, s, err);
@@ -2433,6 +2622,25 @@ struct OpDD {
             double h2 = s + l;
             lo[i] = l - (h2 - s);
             hi[i] = h2;
+        };
+        if (!a.split) {
+            GRID_STRIDE(i, a.n) add(i, ev[i]);
+            return;
+        }
+        // e in the storage order `split`: natural point p of row k is at
+        // lay_pos of it
+        const int n = a.npd, P = (a.dims == 1) ? n : n * n;
+        const long rows = a.n / P;
+        for (KsWalk w(lb, nb, P); w.k < rows; w.next()) {
+            const int p = w.s;
+            int sp;
+            if (a.dims == 2) {
+                const int y = p / n;
+                sp = lay_pos_xy(n, 1, p - y * n, y);
+            } else {
+                sp = lay_pos(1, n, 1, p);
+            }
+            add(w.k * P + p, ev[w.k * P + sp]);
         }
     }
 };

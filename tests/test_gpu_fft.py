@@ -202,6 +202,49 @@ def test_fft_product_every_plan(B, M, P):
     assert relmax(C32, ref, scale) <= 1e-6
 
 
+# FP64 products with 512 < M <= 2048 take the kernel that keeps the whole
+# transform on chip (one block per column pair): ragged column counts (a
+# last pair of one column), M below the half transform length, and the
+# scatter epilogue of the FP64 smoother on a level in natural order.
+@pytest.mark.parametrize("M", [513, 1000, 1024, 1500, 2048])
+@pytest.mark.parametrize("P", [1, 2, 9, 130])
+def test_fft_product_on_chip(B, M, P):
+    alpha = 0.45
+    rng = np.random.default_rng(11 * M + P)
+    X = rng.standard_normal((M, P))
+    c, d, r = oracle.l1_coeffs(M, alpha)
+    ref = np.stack([np.convolve(r, X[:, p])[:M] for p in range(P)], axis=1)
+    scale = np.stack([np.convolve(np.abs(r), np.abs(X[:, p]))[:M] for p in range(P)], axis=1).max()
+    with B.Solver(7, M, alpha, fft=2) as s:
+        s.profile(True)
+        C = host(s.toeplitz_apply(dev(X), which=-1, precision="fp64"))
+        recs = s.profile_records()
+        s.profile(False)
+    assert relmax(C, ref, scale) <= 1e-12
+    assert recs and all(rec["kernel"] >> 8 == 5 for rec in recs), [rec["name"] for rec in recs]
+
+
+@pytest.mark.parametrize("N,M", [(31, 700), (15, 2048)])
+def test_fft_on_chip_smoother_scatter(B, N, M):
+    """One FP64 sweep on a 2D level in natural order (the scatter epilogue)
+    with the on-chip products, against the oracle's sweep."""
+    alpha = 0.5
+    rng = np.random.default_rng(N + M)
+    f = rng.standard_normal((M, N, N))
+    u0 = rng.standard_normal((M, N, N))
+    ref = oracle.half_sweep(2, N, M, alpha, 0, f, u0)
+    ref = oracle.half_sweep(2, N, M, alpha, 1, f, ref)
+    with B.Solver(N, M, alpha, dims=2, fft=2) as s:
+        s.profile(True)
+        U = dev(u0)
+        s.smooth(dev(f), U)
+        U = host(U)
+        recs = s.profile_records()
+        s.profile(False)
+    assert any(rec["kernel"] == (5 << 8) | 1 for rec in recs), [rec["name"] for rec in recs]
+    assert relmax(U, ref) <= 1e-10
+
+
 @pytest.mark.parametrize("dims,N,M,alpha", [(1, 127, 200, 0.3), (2, 31, 64, 0.7), (1, 255, 600, 0.5), (2, 63, 520, 0.4)])
 @pytest.mark.parametrize("first", [0, 1])
 @pytest.mark.parametrize("nu", [(1, 1), (0, 1), (2, 1)])
