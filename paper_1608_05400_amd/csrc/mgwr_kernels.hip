@@ -925,6 +925,9 @@ __device__ inline void grp_select(const Grp<A> &g, A &a, long &lb, long &nb)
 }
 
 constexpr int kThreads = 256;
+// Whether a launch argument set has a `dims` member (the level's dimension).
+template <class A, class = void> struct HasDims : std::false_type {};
+template <class A> struct HasDims<A, std::void_t<decltype(std::declval<A>().dims)>> : std::true_type {};
 #define GRID_STRIDE(e, total) \
     for (long e = lb * kThreads + threadIdx.x; e < (total); e += nb * kThreads)
 
@@ -965,6 +968,13 @@ __global__ __launch_bounds__(kThreads) void k_group(Grp<typename Op::A> g)
     typename Op::A a;
     long lb, nb;
     grp_select(g, a, lb, nb);
+    // Blocks go to the 8 XCDs in turn.  On a 2D level, when the set's blocks
+    // fill whole rounds, they are renumbered so that each XCD runs one
+    // contiguous eighth of them: a 5-point stencil's neighbour rows are then
+    // read through the same L2 (2D N = 1023 step 976 -> 939 ms, N = 511
+    // 529 -> 521 ms; the same on the 1D workloads measured 2 % slower).
+    if constexpr (HasDims<typename Op::A>::value)
+        if (a.dims == 2 && (nb & 7) == 0 && ((blockIdx.x - lb) & 7) == 0) lb = (lb & 7) * (nb >> 3) + (lb >> 3);
     Op::run(a, lb, nb);
 }
 
