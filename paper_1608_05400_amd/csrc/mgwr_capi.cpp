@@ -885,15 +885,17 @@ int half_sweep(Exec &ex, const std::vector<Task> &ts, int rank)
         GemmArgs a = gemm_base(h, mode);
         a.M = h->M; a.P = Pc; a.K = h->M; a.off = 0;
         a.ea.out = t.H->u[t.lev]; a.ea.ldo = L.P; a.ea.dims = h->dims; a.ea.n = L.n; a.ea.colour = colour;
-        auto push_rhs = [&](RhsArgs r) {
-            r.split = split;
-            rhs.push_back(r);
-        };
         // On the FFT route, a zero iterate (first half-sweep of a level that
         // starts from zero, no initial-condition term) makes the right-hand
         // sides the colour's points of F: the products read them there and
-        // no panel is built.
+        // no panel is built; the right-hand-side kernels of the other routes
+        // read no neighbours then.
         const bool from_f = t.zero && !g;
+        auto push_rhs = [&](RhsArgs r) {
+            r.split = split;
+            r.zero_nbrs = from_f ? 1 : 0;
+            rhs.push_back(r);
+        };
         auto rhs_panel = [&]() {
             if (from_f && split) {
                 a.B = t.H->f[t.lev] + off; a.ldb = L.P;
@@ -1094,20 +1096,18 @@ int level_residual(Exec &ex, const std::vector<Task> &ts)
 // at their coarsest level do the exact one-point solve while the others
 // pre-smooth, then the others recurse together.
 // A level that starts a cycle from zero needs no zero fill when every point
-// is written before it is read: pre-smoothing comes first and the first
-// half-sweep takes the FFT route, whose products then read their right-hand
-// sides from F (no initial-condition term) and write the colour's points
-// without reading them; the second half-sweep reads only those.  (A dense or
-// D&C first half-sweep builds its right-hand sides from the iterate.)
+// is written before it is read: pre-smoothing comes first, and its first
+// half-sweep (no initial-condition term) takes its right-hand sides from F
+// alone (the FFT route's products read F's colour points, the right-hand-side
+// kernels of the dense routes read no neighbours) and writes the colour's
+// points before any read of them; the second half-sweep reads only those.
+// (The D&C half-sweep builds its right-hand sides from the iterate.)
 bool skip_zero_fill(const Hier &H, int lev)
 {
     const mgwr_ctx *h = H.h;
     if (h->opt.nu1 < 1 || dc_block_of(h, lev) > 0) return false;
     if (lev == (int)h->lv.size() - 1 && H.g) return false;
-    const int Pc = h->lv[lev].Pc[h->opt.first_colour];
-    if (Pc == 0) return false;
-    const int mode = level_mode(H, Pc);
-    return mode == GM_F64 ? fft_for(h, lev) : fft_for(h, lev, mode);
+    return h->lv[lev].Pc[h->opt.first_colour] > 0;
 }
 
 int cycle(Exec &ex, const std::vector<Task> &ts)

@@ -261,6 +261,7 @@ struct RhsArgs {
     void *panel, *panel_lo;
     long ldp;
     int split = 0;          // storage order of F and U (lay_pos)
+    int zero_nbrs = 0;      // the iterate is zero: no neighbour values are read (b = F + c d g)
 };
 // Residual from a Toeplitz product already in out (the history part, or all
 // of T_M U when diag = 0): out = (F + cd g - diag U - A_h U) - out, with A_h

@@ -2283,7 +2283,8 @@ template <typename S> struct OpRhsPanel {
             }
             const int sp = a.split ? lay_cpos(a.dims, a.n, 1, a.colour, j) : pt;   // stored at
             GLOBAL double *Uk = U + k * P;
-            const double ns = (a.dims == 2) ? nbr_sum_xy(Uk, a.n, x, y, a.split) : nbr_sum(Uk, 1, a.n, pt, a.split);
+            const double ns = a.zero_nbrs ? 0.0
+                              : (a.dims == 2) ? nbr_sum_xy(Uk, a.n, x, y, a.split) : nbr_sum(Uk, 1, a.n, pt, a.split);
             double b = F[k * P + sp] + ns * a.ih2;
             if (a.g) b += cd[k] * g[pt];
             panel[(long)k * a.ldp + j] = (S)b;
@@ -2342,7 +2343,9 @@ struct OpRhsPacked {
                 double b = 0.0;
                 if (k < a.M && j < Pc) {
                     GLOBAL double *Uk = U + (long)k * P;
-                    const double ns = (a.dims == 2) ? nbr_sum_xy(Uk, a.n, x, y, a.split) : nbr_sum(Uk, 1, a.n, pt, a.split);
+                    const double ns = a.zero_nbrs ? 0.0
+                                      : (a.dims == 2) ? nbr_sum_xy(Uk, a.n, x, y, a.split)
+                                                      : nbr_sum(Uk, 1, a.n, pt, a.split);
                     b = F[(long)k * P + sp] + ns * a.ih2;
                     if (a.g) b += cd[k] * g[pt];
                     if (a.lam0 != 0.0) Uk[sp] = a.lam0 * b;
