@@ -2476,6 +2476,24 @@ struct OpXfer {
                 if (a.zero_colour == 1) v = 0.25 * (2.0 * R(x));
                 else if (a.zero_colour == 0) v = 0.25 * (R(x - 1) + R(x + 1));
                 else v = 0.25 * (R(x - 1) + 2.0 * R(x) + R(x + 1));
+            } else if (a.implicit && a.zero_colour == 1) {
+                // the implicit residual at the centre and the four corners,
+                // each ih2 times its four second-colour neighbours, weighted
+                // 4 and 1: the four edge midpoints enter with weight 6 and the
+                // eight second-colour points two apart with weight 1 (zero
+                // outside the grid), twelve loads instead of twenty
+                int I, J;
+                lay_xy(nc, sp, w.s, I, J);
+                const int x = 2 * I + 1, y = 2 * J + 1;
+                auto at = [&](int yy, int xx) {   // clamped index, zero outside
+                    const double v = r[lay_pos_xy(nf, sp, min(max(xx, 0), nf - 1), min(max(yy, 0), nf - 1))];
+                    return (xx < 0 || xx >= nf || yy < 0 || yy >= nf) ? 0.0 : v;
+                };
+                const double inner = (r[lay_pos_xy(nf, sp, x, y - 1)] + r[lay_pos_xy(nf, sp, x, y + 1)]) +
+                                     (r[lay_pos_xy(nf, sp, x - 1, y)] + r[lay_pos_xy(nf, sp, x + 1, y)]);
+                const double outer = ((at(y - 2, x - 1) + at(y - 2, x + 1)) + (at(y + 2, x - 1) + at(y + 2, x + 1))) +
+                                     ((at(y - 1, x - 2) + at(y + 1, x - 2)) + (at(y - 1, x + 2) + at(y + 1, x + 2)));
+                v = a.ih2 * (6.0 * inner + outer) * (1.0 / 16.0);
             } else {
                 int I, J;
                 lay_xy(nc, sp, w.s, I, J);
